@@ -1,0 +1,38 @@
+"""Plain FP64 CPU oracle for the plane-wave Kohn-Sham H|psi> and block Davidson.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+its Python binding) imports, links or calls this package; only the tests, the
+graft smoke check and the CPU-baseline leg of the benchmark do.  It shares no
+code with the HIP path: its only common input is the seeded cell generator
+(``cellgen``), which holds none of the method's arithmetic.
+
+What it computes, and where the paper names it (Quantum ESPRESSO toward the
+exascale):
+
+* ``apply_h``: the one-particle Hamiltonian applied to Bloch states (the
+  "Hamiltonian builds" of the quantum-engine layer in section "Challenges and
+  opportunities of new heterogeneous architectures"), as the sum of the
+  kinetic, local-potential and pseudopotential contributions listed among the
+  GPU-ported kernels (section "Evolution of the GPU-enabled version").  The
+  local part goes through the oracle's own dense per-axis DFT (``dft``), the
+  exact definition of the operator that the pruned FFT path computes.
+* ``dense_h``: the same operator written out as a matrix for tiny cells.
+* ``davidson``: the Davidson iterative diagonalisation (same section) with the
+  Rayleigh-Ritz step solved as a Hermitian generalized eigenproblem, as the
+  paper's dense-solver library does.
+
+The paper prints no formula for any of these; the forms are the standard
+plane-wave pseudopotential ones.  Every reading taken where the paper is
+silent is listed in the design notes of the repository.
+
+Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
+closed forms, invariants, brute force and library routines (see that file).
+"""
+
+from .dft import dft_matrix, dft_axis, inv3, fwd3
+from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, vloc_coeffs,
+                          hdiag)
+from .davidson import davidson, rayleigh_ritz
+
+__all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
+           "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz"]
