@@ -1,0 +1,162 @@
+/*
+ * qeh.h - plane-wave Kohn-Sham H|psi> and block-Davidson eigensolver on one
+ * AMD MI355X (gfx950).  C ABI: plain pointers and sizes, no library types in
+ * the arguments.
+ *
+ * The paper (Quantum ESPRESSO toward the exascale) asks its extracted
+ * libraries to expose plain-array interfaces without structured arguments
+ * (section "Domain-specific mathematical libraries"), to keep the iterative
+ * solver separate from the Hamiltonian builder it calls (same section), and
+ * lists the kernels ported to GPUs: local-potential, pseudopotential and
+ * kinetic contributions to the Hamiltonian, the preconditioner, the overlap
+ * operator (the identity for the norm-conserving form used here) and the
+ * Davidson solver (section "Evolution of the GPU-enabled version").
+ *
+ * Units: Rydberg atomic units (lengths in bohr, energies in Ry).
+ * Complex numbers: interleaved (re, im) pairs of double.
+ * Bands: one band per row, psi[b * ldpsi + G], plane-wave index fastest.
+ * Memory: the library never allocates device memory.  Device storage is an
+ *   arena the caller allocates (size from the *_plan call) and keeps alive
+ *   until the matching destroy.  Every host array passed in is copied before
+ *   the call returns; the caller keeps ownership of everything it passes.
+ * Errors: every call returns a qeh_status; nothing aborts.  qeh_last_error()
+ *   gives a thread-local message for the last failing call on that thread.
+ *   Errors of asynchronous device work surface at the next synchronising call.
+ * Threads: a context is used by one thread at a time; its work is ordered on
+ *   the HIP stream given at creation.
+ */
+#ifndef QEH_H
+#define QEH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int qeh_status;
+enum {
+  QEH_OK = 0,
+  QEH_ERR_INVALID = -1,        /* bad argument, shape or Miller list            */
+  QEH_ERR_NOMEM = -2,          /* arena / workspace smaller than the plan       */
+  QEH_ERR_NUMERIC = -3,        /* NaN or Inf in an input                        */
+  QEH_ERR_CHOLESKY = -4,       /* overlap matrix not positive definite twice    */
+  QEH_ERR_NOT_CONVERGED = -5,  /* Davidson hit maxiter (results still written)  */
+  QEH_ERR_REJECTED = -6,       /* served request can never fit the budget       */
+  QEH_ERR_DEVICE = -7,         /* a HIP call failed                             */
+  QEH_ERR_BUSY = -8            /* served request not finished yet               */
+};
+
+enum { QEH_FP64 = 0, QEH_MIXED = 1 };
+/* QEH_FP64:  every step in double precision.
+ * QEH_MIXED: FFTs, the V_loc multiply and the projector GEMMs in single
+ *            precision with single-precision accumulation (long sums split
+ *            into fixed chunks reduced in double); the kinetic term, psi,
+ *            H psi and the whole Davidson subspace algebra in double.       */
+
+/* One cell at one k-point.  Every pointer is a HOST pointer, read during
+ * qeh_ctx_plan / qeh_ctx_create only. */
+typedef struct {
+  double lattice[9];      /* rows a1, a2, a3 (bohr), row-major               */
+  int fft[3];             /* N1, N2, N3; prime factors in {2,3,5,7}, <= 1024 */
+  double kpt[3];          /* cartesian k (bohr^-1)                           */
+  int npw;                /* plane waves in the sphere                       */
+  const int *miller;      /* [npw][3] (h,k,l), lexicographic, each (h,k)
+                             stick a contiguous run of consecutive l, and
+                             max(m_i) - min(m_i) < N_i on every axis         */
+  const double *vloc;     /* [N3][N2][N1] real local potential on the grid
+                             r_j = sum_i j_i/N_i a_i (Ry), x fastest         */
+  int nat;                /* atoms (may be 0)                                */
+  const int *nproj;       /* [nat] projectors per atom                       */
+  const double *beta;     /* complex [nkb][npw], nkb = sum nproj; includes
+                             1/sqrt(Omega) and exp(-i(k+G).tau)              */
+  const double *dmat;     /* complex: per-atom Hermitian nproj x nproj D
+                             blocks (row-major), concatenated (Ry)           */
+  int precision;          /* QEH_FP64 or QEH_MIXED                           */
+  int block;              /* bands per H-application launch (>= 1)           */
+} qeh_cell;
+
+typedef struct qeh_ctx qeh_ctx;
+
+/* Device bytes the context needs for this cell (validates the cell). */
+qeh_status qeh_ctx_plan(const qeh_cell *cell, size_t *arena_bytes);
+
+/* Build the index maps on the host (stick table, box positions, |k+G|^2,
+ * diag(H)), copy them, V/N, beta and D into the arena, and bind the context
+ * to hip_stream (a hipStream_t; NULL = the null stream).  arena must be a
+ * device pointer with 256-byte alignment and >= the planned size.  The
+ * copies are complete when the call returns. */
+qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
+                          void *hip_stream, qeh_ctx **out);
+
+qeh_status qeh_ctx_destroy(qeh_ctx *ctx);
+
+/* H|psi> for nb bands: hpsi_b = |k+G|^2 psi_b + V_loc psi_b + beta D beta^H psi_b.
+ * psi and hpsi are DEVICE pointers (complex, rows of length npw with leading
+ * dimensions ldpsi, ldh >= npw, in complex elements); they must not overlap.
+ * Enqueued on the context stream in launches of `block` bands; returns
+ * without waiting.  Result is independent of how bands are grouped. */
+qeh_status qeh_apply_h(qeh_ctx *ctx, int nb, const double *psi, int ldpsi,
+                       double *hpsi, int ldh);
+
+/* The three parts of H separately (same layout rules as qeh_apply_h):
+ * part 0 = kinetic + local (the FFT path), part 1 = nonlocal only. */
+qeh_status qeh_apply_h_part(qeh_ctx *ctx, int part, int nb, const double *psi,
+                            int ldpsi, double *hpsi, int ldh);
+
+/* Davidson options: nvecx = maximum basis size (>= 2 nb; 0 = 2 nb),
+ * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
+ * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single
+ * precision limits how small the residual can get; a band also counts as
+ * converged there when its Ritz value moved by <= 1e-8 Ry in one iteration. */
+typedef struct {
+  int nvecx;
+  double rtol;
+  int maxiter;
+} qeh_dav_opts;
+
+typedef struct {
+  int iters;              /* Rayleigh-Ritz steps taken                       */
+  int notconv;            /* bands not converged at exit                     */
+  int restarts;           /* basis restarts (including Cholesky recoveries)  */
+  long band_applies;      /* bands passed through H                          */
+  double resid_max;       /* max_i ||H psi_i - eps_i psi_i|| at exit         */
+  double t_total;         /* wall seconds                                    */
+  double t_hpsi;          /* seconds in H application (device events)        */
+  double t_subspace;      /* seconds in reductions + subspace eigensolve     */
+} qeh_dav_info;
+
+/* Device workspace bytes for qeh_davidson with nb bands. */
+qeh_status qeh_davidson_plan(const qeh_ctx *ctx, int nb, const qeh_dav_opts *opts,
+                             size_t *work_bytes);
+
+/* Lowest nb eigenpairs of H by block Davidson, starting from psi_inout
+ * (DEVICE, nb rows, ldpsi).  On return psi_inout holds orthonormal Ritz
+ * vectors and eig (HOST, nb doubles) the ascending Ritz values.  Blocks
+ * until done.  Returns QEH_ERR_NOT_CONVERGED (results written) at maxiter,
+ * QEH_ERR_CHOLESKY if the overlap matrix fails twice in a row. */
+qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
+                        double *eig, const qeh_dav_opts *opts, void *work,
+                        size_t work_bytes, qeh_dav_info *info);
+
+/* Per-stage device timing of H application (HIP events on the context
+ * stream).  Stages: 0 scatter+z-FFT, 1 plane pass, 2 z-FFT+gather+kinetic,
+ * 3 beta^H psi, 4 D scaling, 5 beta ps accumulate.  enable=1 starts
+ * recording (and clears totals); qeh_ctx_stage_times synchronises the
+ * stream and returns total milliseconds and launch counts per stage. */
+#define QEH_NSTAGES 6
+qeh_status qeh_ctx_profile(qeh_ctx *ctx, int enable);
+qeh_status qeh_ctx_stage_times(qeh_ctx *ctx, double *ms, long *launches, int nstages);
+
+/* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
+ * precision, plane path (0 fused in one kernel, 1 split through HBM)]. */
+qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);
+
+const char *qeh_status_str(qeh_status s);
+const char *qeh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QEH_H */

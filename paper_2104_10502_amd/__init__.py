@@ -1,0 +1,256 @@
+"""Python binding of the qeh HIP library (plane-wave H|psi> and block Davidson
+on one MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libqeh.so``.  PyTorch provides device memory (the arena and the
+band arrays) and the HIP stream.  Importing this module loads the library and
+raises if it has not been built; there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqeh.so")
+
+QEH_OK = 0
+QEH_ERR_INVALID = -1
+QEH_ERR_NOMEM = -2
+QEH_ERR_NUMERIC = -3
+QEH_ERR_CHOLESKY = -4
+QEH_ERR_NOT_CONVERGED = -5
+QEH_ERR_REJECTED = -6
+QEH_ERR_DEVICE = -7
+QEH_ERR_BUSY = -8
+QEH_FP64 = 0
+QEH_MIXED = 1
+NSTAGES = 6
+STAGE_NAMES = ["k1_scatter_zinv", "k2_plane", "k3_zfwd_gather", "calbec_gemm", "dscale",
+               "addnl_gemm"]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libqeh.so is not built: run `python -m paper_2104_10502_amd.build` "
+                      "(or __graft_entry__.build()) first; there is no non-GPU fallback")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+
+class QehCell(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_double * 9), ("fft", ctypes.c_int * 3),
+                ("kpt", ctypes.c_double * 3), ("npw", ctypes.c_int),
+                ("miller", _c_int_p), ("vloc", _c_dbl_p), ("nat", ctypes.c_int),
+                ("nproj", _c_int_p), ("beta", _c_dbl_p), ("dmat", _c_dbl_p),
+                ("precision", ctypes.c_int), ("block", ctypes.c_int)]
+
+
+class DavOpts(ctypes.Structure):
+    _fields_ = [("nvecx", ctypes.c_int), ("rtol", ctypes.c_double), ("maxiter", ctypes.c_int)]
+
+
+class DavInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("notconv", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("band_applies", ctypes.c_long), ("resid_max", ctypes.c_double),
+                ("t_total", ctypes.c_double), ("t_hpsi", ctypes.c_double),
+                ("t_subspace", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_sz_p = ctypes.POINTER(ctypes.c_size_t)
+_SIGS = {
+    "qeh_ctx_plan": ([ctypes.POINTER(QehCell), _sz_p], ctypes.c_int),
+    "qeh_ctx_create": ([ctypes.POINTER(QehCell), _vp, ctypes.c_size_t, _vp,
+                        ctypes.POINTER(_vp)], ctypes.c_int),
+    "qeh_ctx_destroy": ([_vp], ctypes.c_int),
+    "qeh_apply_h": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int], ctypes.c_int),
+    "qeh_apply_h_part": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp,
+                          ctypes.c_int], ctypes.c_int),
+    "qeh_davidson_plan": ([_vp, ctypes.c_int, ctypes.POINTER(DavOpts), _sz_p], ctypes.c_int),
+    "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
+                      _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
+    "qeh_ctx_profile": ([_vp, ctypes.c_int], ctypes.c_int),
+    "qeh_ctx_stage_times": ([_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_long), ctypes.c_int],
+                            ctypes.c_int),
+    "qeh_ctx_info": ([_vp, ctypes.POINTER(ctypes.c_long), ctypes.c_int], ctypes.c_int),
+    "qeh_status_str": ([ctypes.c_int], ctypes.c_char_p),
+    "qeh_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class QehError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.qeh_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%d): %s" % (where, _lib.qeh_status_str(status).decode(),
+                                              status, msg))
+
+
+def _check(st, where, allow=()):
+    if st != QEH_OK and st not in allow:
+        raise QehError(st, where)
+    return st
+
+
+def exported_symbols():
+    """Names the library exports (for load checks)."""
+    return sorted(_SIGS)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _vp(stream.cuda_stream)
+
+
+class Context:
+    """A cell at one k-point, resident on the device.
+
+    Inputs are plain host arrays: lattice (3,3) rows a_i, fft (N1,N2,N3), kpt (3,),
+    miller (npw,3) int, vloc (N3,N2,N1) float64, nproj (nat,) int,
+    beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128.
+    """
+
+    def __init__(self, lattice, fft, kpt, miller, vloc, nproj, beta, dmat, *,
+                 precision=QEH_FP64, block=64, device=None, stream=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda")
+        self._keep = dict(
+            miller=np.ascontiguousarray(miller, dtype=np.int32),
+            vloc=np.ascontiguousarray(vloc, dtype=np.float64),
+            nproj=np.ascontiguousarray(nproj, dtype=np.int32),
+            beta=np.ascontiguousarray(beta, dtype=np.complex128),
+            dmat=np.ascontiguousarray(dmat, dtype=np.complex128))
+        k = self._keep
+        c = QehCell()
+        c.lattice[:] = [float(x) for x in np.asarray(lattice, dtype=np.float64).ravel()]
+        c.fft[:] = [int(x) for x in fft]
+        c.kpt[:] = [float(x) for x in np.asarray(kpt, dtype=np.float64).ravel()]
+        c.npw = int(k["miller"].shape[0])
+        c.miller = k["miller"].ctypes.data_as(_c_int_p)
+        c.vloc = k["vloc"].ctypes.data_as(_c_dbl_p)
+        c.nat = int(k["nproj"].shape[0])
+        c.nproj = k["nproj"].ctypes.data_as(_c_int_p)
+        c.beta = k["beta"].ctypes.data_as(_c_dbl_p)
+        c.dmat = k["dmat"].ctypes.data_as(_c_dbl_p)
+        c.precision = int(precision)
+        c.block = int(block)
+        self._cell = c
+        nbytes = ctypes.c_size_t()
+        _check(_lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(nbytes)), "qeh_ctx_plan")
+        self.arena_bytes = int(nbytes.value)
+        self.arena = torch.empty(max(self.arena_bytes, 256), dtype=torch.uint8,
+                                 device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(_lib.qeh_ctx_create(ctypes.byref(c), _vp(self.arena.data_ptr()),
+                                   self.arena_bytes, _stream_ptr(self.stream), ctypes.byref(h)),
+               "qeh_ctx_create")
+        self._h = h
+        self.npw = c.npw
+        self.precision = int(precision)
+        self.block = int(block)
+        # the host copies are no longer needed after create
+        self._keep = None
+        self._cell = None
+
+    @classmethod
+    def from_cell(cls, cell, **kw):
+        return cls(cell.lattice, cell.fft, cell.kpt, cell.miller, cell.vloc, cell.nproj,
+                   cell.beta, cell.dmat, **kw)
+
+    # ---------------------------------------------------------------- H|psi>
+    def _bands(self, psi):
+        torch = _torch()
+        if psi.dtype != torch.complex128 or psi.device.type != "cuda":
+            raise TypeError("psi must be a complex128 CUDA tensor")
+        if psi.dim() != 2 or psi.shape[1] < self.npw or psi.stride(1) != 1:
+            raise ValueError("psi must be (nb, >= npw) with unit stride along G")
+        return psi
+
+    def apply_h(self, psi, out=None, part=None):
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.npw), dtype=torch.complex128, device=psi.device)
+        ld_in, ld_out = psi.stride(0), out.stride(0)
+        if part is None:
+            st = _lib.qeh_apply_h(self._h, nb, _vp(psi.data_ptr()), ld_in, _vp(out.data_ptr()),
+                                  ld_out)
+        else:
+            st = _lib.qeh_apply_h_part(self._h, int(part), nb, _vp(psi.data_ptr()), ld_in,
+                                       _vp(out.data_ptr()), ld_out)
+        _check(st, "qeh_apply_h")
+        return out
+
+    # ---------------------------------------------------------------- Davidson
+    def davidson_plan(self, nb, nvecx=0, rtol=1e-8, maxiter=0):
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
+        n = ctypes.c_size_t()
+        _check(_lib.qeh_davidson_plan(self._h, int(nb), ctypes.byref(o), ctypes.byref(n)),
+               "qeh_davidson_plan")
+        return int(n.value)
+
+    def davidson(self, psi, nvecx=0, rtol=1e-8, maxiter=0, work=None, allow_notconv=False):
+        """In-place Davidson on psi (nb, npw) complex128; returns (eig ndarray, info dict)."""
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
+        need = self.davidson_plan(nb, nvecx, rtol, maxiter)
+        if work is None or work.numel() < need:
+            work = torch.empty(max(need, 256), dtype=torch.uint8, device=psi.device)
+        eig = np.zeros(nb, dtype=np.float64)
+        info = DavInfo()
+        st = _lib.qeh_davidson(self._h, nb, _vp(psi.data_ptr()), psi.stride(0),
+                               eig.ctypes.data_as(_c_dbl_p), ctypes.byref(o),
+                               _vp(work.data_ptr()), int(work.numel()), ctypes.byref(info))
+        _check(st, "qeh_davidson", allow=(QEH_ERR_NOT_CONVERGED,) if allow_notconv else ())
+        d = info.as_dict()
+        d["status"] = st
+        return eig, d
+
+    # ---------------------------------------------------------------- profiling
+    def profile(self, enable=True):
+        _check(_lib.qeh_ctx_profile(self._h, 1 if enable else 0), "qeh_ctx_profile")
+
+    def stage_times(self):
+        ms = (ctypes.c_double * NSTAGES)()
+        n = (ctypes.c_long * NSTAGES)()
+        _check(_lib.qeh_ctx_stage_times(self._h, ms, n, NSTAGES), "qeh_ctx_stage_times")
+        return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(NSTAGES)}
+
+    def info(self):
+        out = (ctypes.c_long * 10)()
+        _check(_lib.qeh_ctx_info(self._h, out, 10), "qeh_ctx_info")
+        keys = ["npw", "nst", "nkb", "n1", "n2", "n3", "ext", "block", "precision", "plane_path"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.qeh_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

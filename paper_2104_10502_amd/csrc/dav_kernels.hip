@@ -1,0 +1,170 @@
+// Davidson helper kernels: residual norms, the diagonal preconditioner
+// (listed among the GPU-ported kernels, section "Evolution of the
+// GPU-enabled version"), and small reduced-matrix utilities.  All reductions
+// run in a fixed order inside one workgroup per band (deterministic).
+#include "cplx.h"
+#include "qeh_internal.h"
+
+namespace qeh {
+namespace {
+
+constexpr int kDT = 256;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kDT / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// one workgroup per band
+__global__ __launch_bounds__(kDT) void resid_norms_kernel(const double2 *__restrict__ P,
+                                                          const double2 *__restrict__ Q, long ld,
+                                                          int npw, const double *__restrict__ eps,
+                                                          double *__restrict__ norms) {
+  __shared__ double sh[kDT];
+  const int b = blockIdx.x;
+  const double e = eps[b];
+  const double2 *p = P + (long)b * ld;
+  const double2 *q = Q + (long)b * ld;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < npw; g += kDT) {
+    const double2 a = p[g], h = q[g];
+    const double rx = h.x - e * a.x, ry = h.y - e * a.y;
+    acc += rx * rx + ry * ry;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) norms[b] = s;
+}
+
+__global__ __launch_bounds__(kDT) void precond_kernel(
+    const double2 *__restrict__ P, const double2 *__restrict__ Q, long ld, int npw,
+    const int *__restrict__ idx, const double *__restrict__ eps,
+    const double *__restrict__ hdiag, double2 *__restrict__ V, long ldv) {
+  __shared__ double sh[kDT];
+  const int j = blockIdx.x;
+  const int b = idx[j];
+  const double e = eps[b];
+  const double2 *p = P + (long)b * ld;
+  const double2 *q = Q + (long)b * ld;
+  double2 *v = V + (long)j * ldv;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < npw; g += kDT) {
+    const double2 a = p[g], h = q[g];
+    const double x = hdiag[g] - e;
+    const double w = 1.0 / sqrt(1.0 + x * x);
+    const double rx = (h.x - e * a.x) * w, ry = (h.y - e * a.y) * w;
+    v[g] = make_double2(rx, ry);
+    acc += rx * rx + ry * ry;
+  }
+  const double s = block_sum(acc, sh);
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int g = threadIdx.x; g < npw; g += kDT) {
+    const double2 a = v[g];
+    v[g] = make_double2(a.x * inv, a.y * inv);
+  }
+}
+
+__global__ void copy_rows_kernel(const double2 *__restrict__ src, long lds,
+                                 double2 *__restrict__ dst, long ldd, int npw) {
+  const int r = blockIdx.y;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < npw; g += gridDim.x * blockDim.x)
+    dst[(long)r * ldd + g] = src[(long)r * lds + g];
+}
+
+// col-major M(i,j) at M[i + j*ld].  For j in [n0,n1), i in [0,n0):
+// M(j,i) = conj(M(i,j)).
+__global__ void herm_fill_kernel(double2 *M, long ld, int n0, int n1) {
+  const int j = n0 + blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += gridDim.x * blockDim.x) {
+    const double2 v = M[i + (long)j * ld];
+    M[j + (long)i * ld] = make_double2(v.x, -v.y);
+  }
+}
+
+__global__ void set_diag_kernel(double2 *M, long ld, int n, const double *d) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    M[i + (long)j * ld] = make_double2(i == j ? (d ? d[i] : 1.0) : 0.0, 0.0);
+}
+
+__global__ void hermitise_copy_kernel(const double2 *src, long lds, double2 *dst, long ldd,
+                                      int n) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double2 a = src[i + (long)j * lds];
+    const double2 b = src[j + (long)i * lds];
+    dst[i + (long)j * ldd] = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+  }
+}
+
+__global__ void check_finite_kernel(const double *x, long n, int *flag) {
+  int bad = 0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) bad = 1;
+  if (bad) flag[0] = 1;   // plain store: any writer sets the same value
+}
+
+}  // namespace
+
+hipError_t launch_resid_norms(const double2 *P, const double2 *Q, long ld, int npw, int nb,
+                              const double *eps, double *norms, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(resid_norms_kernel, dim3(nb), dim3(kDT), 0, s, P, Q, ld, npw, eps, norms);
+  return hipGetLastError();
+}
+
+hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw, const int *idx,
+                          int nc, const double *eps, const double *hdiag, double2 *V, long ldv,
+                          hipStream_t s) {
+  if (nc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(precond_kernel, dim3(nc), dim3(kDT), 0, s, P, Q, ld, npw, idx, eps, hdiag,
+                     V, ldv);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const double2 *src, long lds, double2 *dst, long ldd, int npw,
+                            int nrows, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const int gx = (npw + 255) / 256 < 64 ? (npw + 255) / 256 : 64;
+  hipLaunchKernelGGL(copy_rows_kernel, dim3(gx, nrows), dim3(256), 0, s, src, lds, dst, ldd, npw);
+  return hipGetLastError();
+}
+
+hipError_t launch_herm_fill(double2 *M, long ld, int n0, int n1, hipStream_t s) {
+  if (n1 <= n0 || n0 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(herm_fill_kernel, dim3((n0 + 255) / 256, n1 - n0), dim3(256), 0, s, M, ld,
+                     n0, n1);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_diag(double2 *M, long ld, int n, const double *d, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(set_diag_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, M, ld, n, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_hermitise_copy(const double2 *src, long lds, double2 *dst, long ldd, int n,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hermitise_copy_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, src, lds,
+                     dst, ldd, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const double *x, long n, int *flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace qeh

@@ -1,0 +1,314 @@
+// Local-potential path of H|psi>: sphere scatter + z transforms (K1), the
+// per-plane 2D transforms with the V(r) multiply (K2), and z transforms +
+// sphere gather + kinetic term (K3).
+//
+// The paper lists the local-potential and kinetic contributions among the
+// Hamiltonian kernels ported to GPUs and builds its 3D FFT from 1D and 2D
+// transforms (section "Evolution of the GPU-enabled version").  Here the 3D
+// transform is pruned to the data that is non-zero or needed: only the z
+// sticks touched by the plane-wave sphere are transformed along z, only the
+// x-extent columns of each plane along y, and each plane row along x.
+//
+// Transforms are in-place mixed-radix (2,3,4,5,7,8) passes in LDS.  Inverse
+// transforms use decimation in time, which wants digit-reversed input and
+// yields natural order; forward transforms use decimation in frequency,
+// natural in and digit-reversed out.  The permutations are folded into the
+// scatter / gather index tables, so no explicit reordering pass exists.
+#include "cplx.h"
+#include "fft_radix.h"
+#include "qeh_internal.h"
+
+namespace qeh {
+namespace {
+
+// ---------------------------------------------------------------- passes
+// tw[t] = exp(-2 pi i t / n); the inverse uses the conjugate.
+
+template <typename C, int R, bool INV, bool DIT>
+__device__ __forceinline__ void radix_pass(C *buf, int nlines, int ld, int n, int L,
+                                           const C *tw, int tid, int nthr) {
+  const int nbf = n / R;
+  const int total = nlines * nbf;
+  const int tstep = n / (L * R);
+  for (int t = tid; t < total; t += nthr) {
+    const int line = t / nbf;
+    const int u = t - line * nbf;
+    const int blk = u / L;
+    const int j = u - blk * L;
+    C *p = buf + line * ld + blk * (L * R) + j;
+    C v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = p[q * L];
+    if (DIT && L > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        C w = tw[q * j * tstep];
+        if (INV) w.y = -w.y;
+        v[q] = cmul(v[q], w);
+      }
+    }
+    dftR<C, R, INV>(v);
+    if (!DIT && L > 1) {
+#pragma unroll
+      for (int q = 1; q < R; ++q) {
+        C w = tw[q * j * tstep];
+        if (INV) w.y = -w.y;
+        v[q] = cmul(v[q], w);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) p[q * L] = v[q];
+  }
+}
+
+template <typename C, bool INV, bool DIT>
+__device__ __forceinline__ void one_pass(C *buf, int nlines, int ld, int n, int R, int L,
+                                         const C *tw, int tid, int nthr) {
+  switch (R) {
+    case 2: radix_pass<C, 2, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    case 3: radix_pass<C, 3, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    case 4: radix_pass<C, 4, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    case 5: radix_pass<C, 5, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    case 7: radix_pass<C, 7, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    case 8: radix_pass<C, 8, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+    default: break;
+  }
+}
+
+// Inverse transform of nlines lines (stride ld), digit-reversed in, natural out.
+template <typename C>
+__device__ void fft_inv_dit(C *buf, int nlines, int ld, const FftDim &d, const C *tw,
+                            int tid, int nthr) {
+  for (int p = 0; p < d.npass; ++p) {
+    one_pass<C, true, true>(buf, nlines, ld, d.n, d.radix[p], d.span[p], tw, tid, nthr);
+    __syncthreads();
+  }
+}
+
+// Forward transform, natural in, digit-reversed out.
+template <typename C>
+__device__ void fft_fwd_dif(C *buf, int nlines, int ld, const FftDim &d, const C *tw,
+                            int tid, int nthr) {
+  for (int p = d.npass - 1; p >= 0; --p) {
+    one_pass<C, false, false>(buf, nlines, ld, d.n, d.radix[p], d.span[p], tw, tid, nthr);
+    __syncthreads();
+  }
+}
+
+constexpr int kNT = 256;
+
+// ---------------------------------------------------------------- K1
+// One workgroup: S consecutive sticks of one band.  Their sphere runs are one
+// contiguous range of psi (lexicographic Miller order), so the read is
+// coalesced; the output rows [z][s0 .. s0+S) are contiguous too.
+template <typename C>
+__global__ __launch_bounds__(kNT) void k1_scatter_zinv(
+    const double2 *__restrict__ psi, int ldpsi, C *__restrict__ sbuf,
+    const int *__restrict__ stick_off, const int *__restrict__ gmap,
+    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tile = reinterpret_cast<C *>(smem_raw);
+  C *tw = tile + S * ldz;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int s0 = blockIdx.x * S;
+  const int ns = min(S, nst - s0);
+  const int n3 = dz.n;
+  for (int i = tid; i < n3; i += kNT) tw[i] = twz[i];
+  const C zero = cmk<C>(0, 0);
+  for (int i = tid; i < ns * ldz; i += kNT) tile[i] = zero;
+  __syncthreads();
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  const double2 *pb = psi + (size_t)b * ldpsi;
+  const int base = s0 * ldz;
+  for (int g = g0 + tid; g < g1; g += kNT) tile[gmap[g] - base] = ccast<C>(pb[g]);
+  __syncthreads();
+  fft_inv_dit<C>(tile, ns, ldz, dz, tw, tid, kNT);
+  C *out = sbuf + (size_t)b * n3 * nst + s0;
+  for (int i = tid; i < ns * n3; i += kNT) {
+    const int z = i / ns;
+    const int s = i - z * ns;
+    out[(size_t)z * nst + s] = tile[s * ldz + z];
+  }
+}
+
+// ---------------------------------------------------------------- K3
+template <typename C>
+__global__ __launch_bounds__(kNT) void k3_zfwd_gather(
+    const C *__restrict__ sbuf, const double2 *__restrict__ psi, int ldpsi,
+    double2 *__restrict__ hpsi, int ldh, const double *__restrict__ kin,
+    const int *__restrict__ stick_off, const int *__restrict__ gmap,
+    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, int add_kin) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tile = reinterpret_cast<C *>(smem_raw);
+  C *tw = tile + S * ldz;
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int s0 = blockIdx.x * S;
+  const int ns = min(S, nst - s0);
+  const int n3 = dz.n;
+  for (int i = tid; i < n3; i += kNT) tw[i] = twz[i];
+  const C *in = sbuf + (size_t)b * n3 * nst + s0;
+  for (int i = tid; i < ns * n3; i += kNT) {
+    const int z = i / ns;
+    const int s = i - z * ns;
+    tile[s * ldz + z] = in[(size_t)z * nst + s];
+  }
+  __syncthreads();
+  fft_fwd_dif<C>(tile, ns, ldz, dz, tw, tid, kNT);
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  const int base = s0 * ldz;
+  const double2 *pb = psi + (size_t)b * ldpsi;
+  double2 *hb = hpsi + (size_t)b * ldh;
+  for (int g = g0 + tid; g < g1; g += kNT) {
+    double2 r = ccast<double2>(tile[gmap[g] - base]);
+    if (add_kin) {
+      const double2 p = pb[g];
+      const double k = kin[g];
+      r.x += k * p.x;
+      r.y += k * p.y;
+    }
+    hb[g] = r;
+  }
+}
+
+// ---------------------------------------------------------------- K2
+// One workgroup: one z-plane of one band.  T holds the x-extent columns of the
+// plane (column c = h - hmin, y along the column); rc rows at a time are
+// expanded to full x lines in RB for the x transforms and the V multiply.
+// Workgroup ids are remapped so that each XCD (ids are dealt round-robin to
+// the 8 XCDs) walks a contiguous range of (z, band) with band fastest: the
+// bands of one plane share that plane's V in the XCD's L2.
+template <typename C>
+__global__ __launch_bounds__(kNT) void k2_plane(
+    C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
+    const int *__restrict__ tidx, const int *__restrict__ xpos_g,
+    const C *__restrict__ twx_g, const C *__restrict__ twy_g, FftDim dx, FftDim dy,
+    int nst, int n3, int ext, int ldT, int rc, int ldR, int nbk, int per_xcd) {
+  using R = typename real_of<C>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = dx.n, n2 = dy.n;
+  C *T = reinterpret_cast<C *>(smem_raw);
+  C *RB = T + ext * ldT;
+  C *twx = RB + rc * ldR;
+  C *twy = twx + n1;
+  int *xp = reinterpret_cast<int *>(twy + n2);
+  const int id = blockIdx.x;
+  const int logical = (id & 7) * per_xcd + (id >> 3);
+  if (logical >= nbk * n3) return;
+  const int z = logical / nbk;
+  const int b = logical - z * nbk;
+  const int tid = threadIdx.x;
+  const C zero = cmk<C>(0, 0);
+
+  for (int i = tid; i < ext * ldT; i += kNT) T[i] = zero;
+  for (int i = tid; i < n1; i += kNT) twx[i] = twx_g[i];
+  for (int i = tid; i < n2; i += kNT) twy[i] = twy_g[i];
+  for (int i = tid; i < ext; i += kNT) xp[i] = xpos_g[i];
+  __syncthreads();
+  C *plane = sbuf + ((size_t)b * n3 + z) * nst;
+  for (int s = tid; s < nst; s += kNT) T[tidx[s]] = plane[s];
+  __syncthreads();
+  fft_inv_dit<C>(T, ext, ldT, dy, twy, tid, kNT);
+
+  for (int y0 = 0; y0 < n2; y0 += rc) {
+    const int nr = min(rc, n2 - y0);
+    for (int i = tid; i < nr * ldR; i += kNT) RB[i] = zero;
+    __syncthreads();
+    for (int i = tid; i < nr * ext; i += kNT) {
+      const int r = i / ext;
+      const int c = i - r * ext;
+      RB[r * ldR + xp[c]] = T[c * ldT + y0 + r];
+    }
+    __syncthreads();
+    fft_inv_dit<C>(RB, nr, ldR, dx, twx, tid, kNT);
+    const R *vrow = vs + ((size_t)z * n2 + y0) * n1;
+    for (int i = tid; i < nr * n1; i += kNT) {
+      const int r = i / n1;
+      const int x = i - r * n1;
+      RB[r * ldR + x] = cscale(RB[r * ldR + x], vrow[i]);
+    }
+    __syncthreads();
+    fft_fwd_dif<C>(RB, nr, ldR, dx, twx, tid, kNT);
+    for (int i = tid; i < nr * ext; i += kNT) {
+      const int r = i / ext;
+      const int c = i - r * ext;
+      T[c * ldT + y0 + r] = RB[r * ldR + xp[c]];
+    }
+    __syncthreads();
+  }
+  fft_fwd_dif<C>(T, ext, ldT, dy, twy, tid, kNT);
+  for (int s = tid; s < nst; s += kNT) plane[s] = T[tidx[s]];
+}
+
+template <typename K> void allow_lds(K kern, size_t bytes) {
+  if (bytes > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename C>
+hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  const C *tw = reinterpret_cast<const C *>(c->d.tw) + c->tw_off[2];
+  dim3 grid((c->nst + c->sg.S - 1) / c->sg.S, nbk);
+  allow_lds(k1_scatter_zinv<C>, c->sg.lds_bytes);
+  hipLaunchKernelGGL(k1_scatter_zinv<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream, psi,
+                     ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
+                     c->dz, c->nst, c->sg.S, c->sg.ldz);
+  return hipGetLastError();
+}
+
+template <typename C>
+hipError_t k3_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, double2 *hpsi,
+                   int ldh, int add_kin) {
+  const C *tw = reinterpret_cast<const C *>(c->d.tw) + c->tw_off[2];
+  dim3 grid((c->nst + c->sg.S - 1) / c->sg.S, nbk);
+  allow_lds(k3_zfwd_gather<C>, c->sg.lds_bytes);
+  hipLaunchKernelGGL(k3_zfwd_gather<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream,
+                     reinterpret_cast<const C *>(c->d.sbuf), psi, ldpsi, hpsi, ldh, c->d.kin,
+                     c->d.stick_off, c->d.gmap, tw, c->dz, c->nst, c->sg.S, c->sg.ldz, add_kin);
+  return hipGetLastError();
+}
+
+template <typename C> hipError_t k2_impl(const qeh_ctx *c, int nbk) {
+  using R = typename real_of<C>::type;
+  const C *tw = reinterpret_cast<const C *>(c->d.tw);
+  const int total = nbk * c->n3;
+  const int per_xcd = (total + 7) / 8;
+  allow_lds(k2_plane<C>, c->pg.lds_bytes);
+  hipLaunchKernelGGL(k2_plane<C>, dim3(8 * per_xcd), dim3(kNT), c->pg.lds_bytes, c->stream,
+                     reinterpret_cast<C *>(c->d.sbuf), reinterpret_cast<const R *>(c->d.vs),
+                     c->d.tidx, c->d.xpos, tw + c->tw_off[0], tw + c->tw_off[1], c->dx, c->dy,
+                     c->nst, c->n3, c->ext, c->pg.ldT, c->pg.rc, c->pg.ldR, nbk, per_xcd);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
+  const size_t c = prec == QEH_FP64 ? 16 : 8;
+  return c * ((size_t)ext * g.ldT + (size_t)g.rc * g.ldR + n1 + n2) + 4 * (size_t)ext;
+}
+
+size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
+  const size_t c = prec == QEH_FP64 ? 16 : 8;
+  return c * ((size_t)g.S * g.ldz + n3);
+}
+
+hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  return c->prec == QEH_FP64 ? k1_impl<double2>(c, nbk, psi, ldpsi)
+                             : k1_impl<float2>(c, nbk, psi, ldpsi);
+}
+
+hipError_t launch_k2(const qeh_ctx *c, int nbk) {
+  if (c->plane_path != 0) return hipErrorInvalidValue;
+  return c->prec == QEH_FP64 ? k2_impl<double2>(c, nbk) : k2_impl<float2>(c, nbk);
+}
+
+hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, double2 *hpsi,
+                     int ldh, int add_kinetic) {
+  return c->prec == QEH_FP64 ? k3_impl<double2>(c, nbk, psi, ldpsi, hpsi, ldh, add_kinetic)
+                             : k3_impl<float2>(c, nbk, psi, ldpsi, hpsi, ldh, add_kinetic);
+}
+
+}  // namespace qeh

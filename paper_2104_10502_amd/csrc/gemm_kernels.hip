@@ -1,0 +1,272 @@
+// Complex matrix products on the MFMA units, and the D scaling of the
+// projector coefficients.
+//
+// Uses: the pseudopotential contribution of H (becp = beta^H psi, ps = D becp,
+// hpsi += beta ps), which the paper lists among the ported Hamiltonian
+// kernels, and the Rayleigh-Ritz reductions / Ritz rotations of the Davidson
+// solver, which the paper runs through GPU BLAS (section "Evolution of the
+// GPU-enabled version").
+//
+// A complex product is four real MFMA products on planar (re, im) tiles:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
+// (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
+// split into fixed chunks whose partial results are summed in double by a
+// separate kernel in a fixed order (deterministic, no atomics).
+#include "cplx.h"
+#include "qeh_internal.h"
+
+namespace qeh {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct acc_of;
+template <> struct acc_of<float> { using type = floatx4; };
+template <> struct acc_of<double> { using type = doublex4; };
+
+__device__ __forceinline__ void mfma(float a, float b, floatx4 &c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ void mfma(double a, double b, doublex4 &c) {
+  c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kGT = 256;
+
+// Operand load: element of type T (double2/float2) -> compute type R, conj.
+template <typename R, typename T>
+__device__ __forceinline__ void ld_elem(const T *p, bool valid, bool cj, R &re, R &im) {
+  if (valid) {
+    const T v = *p;
+    re = static_cast<R>(v.x);
+    im = cj ? -static_cast<R>(v.y) : static_cast<R>(v.y);
+  } else {
+    re = R(0);
+    im = R(0);
+  }
+}
+
+template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
+__global__ __launch_bounds__(kGT) void cgemm_kernel(
+    const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
+    long ldc, int M, int N, int K, int conjA, int conjB, int accumulate, int kchunk,
+    long split_stride) {
+  using ACC = typename acc_of<R>::type;
+  constexpr int BKP = BK + 1;
+  constexpr int TM = BM / 32;
+  constexpr int TN = BN / 32;
+  __shared__ R As[2][BM * BKP];
+  __shared__ R Bs[2][BN * BKP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * (BM / 2);
+  const int wn0 = (wave & 1) * (BN / 2);
+  const int m0 = blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int kz = blockIdx.z;
+  const int kbeg = kz * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  TC *Cz = C + (long)kz * split_stride;
+
+  ACC acc_r[TM][TN], acc_i[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      acc_r[i][j] = ACC{0, 0, 0, 0};
+      acc_i[i][j] = ACC{0, 0, 0, 0};
+    }
+
+  const int lr = lane & 15;   // row (A) / column (B) inside a 16-block
+  const int lk = lane >> 4;   // k inside a 4-step
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    // ---- global -> LDS (planar re / im, K contiguous per row)
+    for (int e = tid; e < BM * BK; e += kGT) {
+      const int r = e / BK, k = e - (e / BK) * BK;
+      const int gm = m0 + r, gk = k0 + k;
+      R re, im;
+      ld_elem<R, TA>(A + (long)gm * lda + gk, gm < M && gk < kend, conjA != 0, re, im);
+      As[0][r * BKP + k] = re;
+      As[1][r * BKP + k] = im;
+    }
+    if (BMODE == 0) {
+      for (int e = tid; e < BN * BK; e += kGT) {
+        const int r = e / BK, k = e - (e / BK) * BK;
+        const int gn = n0 + r, gk = k0 + k;
+        R re, im;
+        ld_elem<R, TB>(B + (long)gn * ldb + gk, gn < N && gk < kend, conjB != 0, re, im);
+        Bs[0][r * BKP + k] = re;
+        Bs[1][r * BKP + k] = im;
+      }
+    } else {
+      for (int e = tid; e < BN * BK; e += kGT) {
+        const int k = e / BN, r = e - (e / BN) * BN;
+        const int gn = n0 + r, gk = k0 + k;
+        R re, im;
+        ld_elem<R, TB>(B + (long)gk * ldb + gn, gn < N && gk < kend, conjB != 0, re, im);
+        Bs[0][r * BKP + k] = re;
+        Bs[1][r * BKP + k] = im;
+      }
+    }
+    __syncthreads();
+    // ---- MFMA over the staged K slice
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      R ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int off = (wm0 + i * 16 + lr) * BKP + kk + lk;
+        ar[i] = As[0][off];
+        ai[i] = As[1][off];
+        nai[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int off = (wn0 + j * 16 + lr) * BKP + kk + lk;
+        br[j] = Bs[0][off];
+        bi[j] = Bs[1][off];
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          mfma(ar[i], br[j], acc_r[i][j]);
+          mfma(nai[i], bi[j], acc_r[i][j]);
+          mfma(ar[i], bi[j], acc_i[i][j]);
+          mfma(ai[i], br[j], acc_i[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue.  Column lane%16 of each 16x16 block; accumulator entry r
+  // holds row 4*(lane/16)+r for the f32 MFMA but row lane/16+4*r for the f64
+  // one (the two instructions lay out D differently).
+  constexpr bool kF64 = sizeof(R) == 8;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm0 + i * 16 + (kF64 ? lk + 4 * r : 4 * lk + r);
+        const int gn = n0 + wn0 + j * 16 + lr;
+        if (gm < M && gn < N) {
+          TC *p = Cz + (long)gm * ldc + gn;
+          using RC = typename real_of<TC>::type;
+          if (accumulate) {
+            TC v = *p;
+            // the add happens in the result's precision
+            v.x = v.x + static_cast<RC>(acc_r[i][j][r]);
+            v.y = v.y + static_cast<RC>(acc_i[i][j][r]);
+            *p = v;
+          } else {
+            TC v;
+            v.x = static_cast<RC>(acc_r[i][j][r]);
+            v.y = static_cast<RC>(acc_i[i][j][r]);
+            *p = v;
+          }
+        }
+      }
+}
+
+template <typename R, typename TA, typename TB, typename TC, int BMODE>
+hipError_t run(const GemmDesc &g, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nsplit);
+  const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
+  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK>), grid, dim3(kGT), 0, s,
+                     reinterpret_cast<const TA *>(g.A), g.lda, reinterpret_cast<const TB *>(g.B),
+                     g.ldb, reinterpret_cast<TC *>(g.C), g.ldc, g.M, g.N, g.K, g.conjA, g.conjB,
+                     g.accumulate, kchunk, g.split_stride);
+  return hipGetLastError();
+}
+
+template <typename R, typename TA, typename TB, typename TC>
+hipError_t run_b(const GemmDesc &g, hipStream_t s) {
+  return g.bmode == 0 ? run<R, TA, TB, TC, 0>(g, s) : run<R, TA, TB, TC, 1>(g, s);
+}
+
+template <typename R, typename TA, typename TB>
+hipError_t run_c(const GemmDesc &g, hipStream_t s) {
+  return g.tc == T_D2 ? run_b<R, TA, TB, double2>(g, s) : run_b<R, TA, TB, float2>(g, s);
+}
+
+template <typename R, typename TA> hipError_t run_bt(const GemmDesc &g, hipStream_t s) {
+  return g.tb == T_D2 ? run_c<R, TA, double2>(g, s) : run_c<R, TA, float2>(g, s);
+}
+
+// ---------------------------------------------------------------- D scaling
+// grid (chunk, band).  Chunk c covers whole atoms [p0, p1), p1 - p0 <= 256.
+template <typename TP, typename TS>
+__global__ __launch_bounds__(256) void dscale_kernel(
+    const TP *__restrict__ part, long split_stride, int nsplit, int nkb, TS *__restrict__ ps,
+    const double2 *__restrict__ dmat, const int *__restrict__ pj0, const int *__restrict__ pnb,
+    const int *__restrict__ pdoff, const int *__restrict__ chunk) {
+  __shared__ double2 becp[256];
+  const int p0 = chunk[blockIdx.x], p1 = chunk[blockIdx.x + 1];
+  const int b = blockIdx.y;
+  const int t = threadIdx.x;
+  const int j = p0 + t;
+  if (j < p1) {
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const TP v = part[(long)s * split_stride + (long)b * nkb + j];
+      sr += static_cast<double>(v.x);
+      si += static_cast<double>(v.y);
+    }
+    becp[t] = make_double2(sr, si);
+  }
+  __syncthreads();
+  if (j < p1) {
+    const int j0 = pj0[j], nbk = pnb[j];
+    const double2 *drow = dmat + pdoff[j];
+    double sr = 0.0, si = 0.0;
+    for (int q = 0; q < nbk; ++q) {
+      const double2 d = drow[q];
+      const double2 v = becp[j0 + q - p0];
+      sr += d.x * v.x - d.y * v.y;
+      si += d.x * v.y + d.y * v.x;
+    }
+    TS o;
+    o.x = static_cast<typename real_of<TS>::type>(sr);
+    o.y = static_cast<typename real_of<TS>::type>(si);
+    ps[(long)b * nkb + j] = o;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+  if (g.prec == G_F64) {
+    if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
+    return run_b<double, double2, double2, double2>(g, s);
+  }
+  return g.ta == T_D2 ? run_bt<float, double2>(g, s) : run_bt<float, float2>(g, s);
+}
+
+hipError_t launch_dscale(const qeh_ctx *c, int nbk) {
+  if (c->nkb == 0) return hipSuccess;
+  dim3 grid(c->nchunk, nbk);
+  const long ss = (long)c->block * c->nkb;
+  if (c->prec == QEH_FP64) {
+    hipLaunchKernelGGL((dscale_kernel<double2, double2>), grid, dim3(256), 0, c->stream,
+                       reinterpret_cast<const double2 *>(c->d.part), ss, c->nsplit, c->nkb,
+                       reinterpret_cast<double2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
+                       c->d.pdoff, c->d.chunk);
+  } else {
+    hipLaunchKernelGGL((dscale_kernel<float2, float2>), grid, dim3(256), 0, c->stream,
+                       reinterpret_cast<const float2 *>(c->d.part), ss, c->nsplit, c->nkb,
+                       reinterpret_cast<float2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
+                       c->d.pdoff, c->d.chunk);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qeh

@@ -1,0 +1,158 @@
+// Internal declarations of the qeh library: context layout, FFT plans and the
+// kernel launchers.  Not part of the public C ABI (include/qeh.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qeh.h"
+
+namespace qeh {
+
+constexpr int kMaxPass = 12;
+constexpr size_t kAlign = 256;
+constexpr int kLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
+
+// One 1D mixed-radix transform of length n = prod radix[p].  Pass p combines
+// radix[p] sub-transforms of length span[p] (span[0] = 1).  The decimation-
+// in-time form takes digit-reversed input (element m at pos(m)) and returns
+// natural order; the decimation-in-frequency form is its transpose.
+struct FftDim {
+  int n;
+  int npass;
+  int radix[kMaxPass];
+  int span[kMaxPass];
+};
+
+bool make_fft_dim(int n, FftDim *d);
+// position of element m in the digit-reversed input of the DIT transform
+int fft_digit_pos(const FftDim &d, int m);
+
+// Plane-pass LDS geometry (elements of the working complex type).
+struct PlaneGeom {
+  int ldT;   // column stride of the x-extent column tile (>= N2, odd)
+  int rc;    // rows processed together in the row phase
+  int ldR;   // row stride of the row buffer (>= N1, odd)
+  size_t lds_bytes;
+};
+
+struct StickGeom {
+  int ldz;   // z-line stride (>= N3, odd)
+  int S;     // sticks per workgroup
+  size_t lds_bytes;
+};
+
+// Device arrays of one context, all inside the caller's arena.
+struct DevMaps {
+  int *stick_off;    // [nst+1] first G of each stick
+  int *gmap;         // [npw] s*ldz + digit-reversed z position
+  int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2)
+  int *xpos;         // [ext] digit-reversed x position of column c
+  double *kin;       // [npw] |k+G|^2
+  double *hdiag;     // [npw] diag(H)
+  void *vs;          // [N3][N2][N1] V/N (double or float)
+  void *tw;          // twiddles x | y | z (double2 or float2)
+  void *beta;        // [nkb][npw] (double2 or float2)
+  double2 *dmat;     // concatenated blocks
+  int *pj0;          // [nkb] first projector of the atom block of i
+  int *pnb;          // [nkb] size of that block
+  int *pdoff;        // [nkb] offset of row i of its block in dmat
+  int *chunk;        // [nchunk+1] atom-aligned projector ranges (<= 256 each)
+  void *sbuf;        // [block][N3][nst] stick buffer (working complex type)
+  void *part;        // [nsplit][block][nkb] split-K partials
+  void *ps;          // [block][nkb] D * becp (working complex type)
+  void *big;         // split plane path: [block][N3][ext][N2] (or null)
+};
+
+}  // namespace qeh
+
+struct qeh_ctx {
+  int npw = 0, nst = 0, nkb = 0, nat = 0;
+  int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
+  int block = 0, prec = 0;
+  int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM
+  int nsplit = 1, kchunk = 0;
+  int nchunk = 0;
+  qeh::FftDim dx{}, dy{}, dz{};
+  qeh::PlaneGeom pg{};
+  qeh::StickGeom sg{};
+  int tw_off[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  qeh::DevMaps d{};
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  double vmean = 0.0;
+  // profiling
+  bool prof = false;
+  double stage_ms[QEH_NSTAGES] = {0};
+  long stage_n[QEH_NSTAGES] = {0};
+  std::vector<hipEvent_t> ev_pool;   // 2 events per recorded stage launch
+  std::vector<int> ev_recs;          // stage id of each recorded launch
+};
+
+namespace qeh {
+
+void set_error(const std::string &msg);
+qeh_status hip_fail(hipError_t e, const char *what);
+
+// ---- FFT path launchers (fft_kernels.hip) --------------------------------
+// All take band count nbk (<= ctx block) and operate on the ctx stick buffer.
+hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
+hipError_t launch_k2(const qeh_ctx *c, int nbk);
+hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
+                     double2 *hpsi, int ldh, int add_kinetic);
+size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g);
+size_t stick_lds_bytes(int prec, int n3, const StickGeom &g);
+
+// ---- complex GEMM launchers (gemm_kernels.hip) ----------------------------
+// C[m][n] (+)= sum_k opA(A[m][k]) opB(B(k,n)), complex, MFMA.
+//   A: element (m,k) at A[m*lda + k], conjugated if conjA.
+//   B: bmode 0: element (k,n) at B[n*ldb + k] (conjugated if conjB);
+//      bmode 1: element (k,n) at B[k*ldb + n].
+//   Split-K: grid z = nsplit slices of kchunk; slice s writes
+//      C + s*split_stride (accumulate must be 0 then).
+enum GemmPrec { G_F64 = 0, G_F32 = 1 };
+enum GemmType { T_D2 = 0, T_F2 = 1 };   // storage type of an operand
+struct GemmDesc {
+  const void *A; long lda; int ta;
+  const void *B; long ldb; int tb; int bmode;
+  void *C; long ldc; int tc;
+  int M, N, K;
+  int conjA, conjB, accumulate;
+  int nsplit, kchunk; long split_stride;
+  int prec;
+};
+hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
+
+// Sum split-K partials (double2 or float2 partials, double accumulation) and
+// apply the block-diagonal D: ps[b][i] = sum_j D_ij sum_s part[s][b][j].
+hipError_t launch_dscale(const qeh_ctx *c, int nbk);
+
+// ---- Davidson helpers (dav_kernels.hip) ----------------------------------
+// norms[b] = || Q_b - eps_b P_b ||^2 over npw (double), one launch.
+hipError_t launch_resid_norms(const double2 *P, const double2 *Q, long ld, int npw,
+                              int nb, const double *eps, double *norms, hipStream_t s);
+// V[dst_b] = t / ||t||, t = (Q_b - eps_b P_b) / sqrt(1 + (h - eps_b)^2) for the
+// listed bands b = idx[j], dst row j.
+hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw,
+                          const int *idx, int nc, const double *eps, const double *hdiag,
+                          double2 *V, long ldv, hipStream_t s);
+// Copy rows; Hermitian fill; diag set etc.
+hipError_t launch_copy_rows(const double2 *src, long lds, double2 *dst, long ldd, int npw,
+                            int nrows, hipStream_t s);
+// M[j][i] = conj(M[i][j]) for i in [0,n0), j in [n0,n1) (col-major, ld): fills
+// the rows n0..n1 of the first n0 columns from the new columns.
+hipError_t launch_herm_fill(double2 *M, long ld, int n0, int n1, hipStream_t s);
+// M[0:n,0:n] = diag(d) (complex), or identity if d == null.
+hipError_t launch_set_diag(double2 *M, long ld, int n, const double *d, hipStream_t s);
+// dst (n x n, ldd) = (src + src^H)/2 (src n x n, lds), col-major.
+hipError_t launch_hermitise_copy(const double2 *src, long lds, double2 *dst, long ldd, int n,
+                                 hipStream_t s);
+// finite check: flag[0] |= any non-finite in x[0..n) (doubles)
+hipError_t launch_check_finite(const double *x, long n, int *flag, hipStream_t s);
+
+}  // namespace qeh

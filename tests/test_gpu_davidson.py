@@ -1,0 +1,88 @@
+"""GPU block Davidson (qeh_davidson through the C ABI) against references that
+do not come from the HIP path:
+
+* LAPACK's dense eigensolver on the oracle's dense H (C1, a served cell);
+* the closed-form free-electron shells (V = 0, no projectors);
+* the oracle's own Davidson eigenvalues for the full C2 cell, stored in
+  tests/golden/c2_eigs.txt by tests/golden/make_golden.py.
+
+Bars: FP64 form max |eps - ref| <= 1e-9 Ry; mixed form <= 1e-6 Ry.
+"""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import cellgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _q():
+    import paper_2104_10502_amd as q
+    return q
+
+
+def _solve(cell, nb, prec, block, nvecx=0, rtol=1e-9, seed=10502, maxiter=0):
+    q = _q()
+    ctx = q.Context.from_cell(cell, precision=prec, block=block)
+    psi = torch.from_numpy(cellgen.make_psi0(cell.npw, nb, seed=seed)).cuda()
+    eig, info = ctx.davidson(psi, nvecx=nvecx, rtol=rtol, maxiter=maxiter)
+    print("davidson", cell.name, "prec", prec, {k: info[k] for k in
+          ("iters", "band_applies", "restarts", "resid_max", "t_total")}, flush=True)
+    return eig, psi.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-6)])
+def test_davidson_c1_vs_lapack(prec, tol):
+    cell = cellgen.make_cell("c1")
+    ref = sla.eigh(oracle.dense_h(cell), eigvals_only=True, subset_by_index=[0, 15])
+    eig, psi, info = _solve(cell, 16, prec, 16)
+    assert np.abs(eig - ref).max() < tol, np.abs(eig - ref).max()
+    # returned Ritz vectors: orthonormal, and eigenvectors of the oracle's H
+    gram = psi.conj() @ psi.T
+    assert np.abs(gram - np.eye(16)).max() < (1e-10 if prec == 0 else 1e-8)
+    r = oracle.apply_h(cell, psi) - eig[:, None] * psi
+    assert np.linalg.norm(r, axis=1).max() < (1e-8 if prec == 0 else 1e-4)
+
+
+def test_davidson_ragged_blocks_restarts():
+    # H applied in blocks of 5 (ragged), small basis -> many restarts
+    cell = cellgen.make_cell("c1")
+    ref = sla.eigh(oracle.dense_h(cell), eigvals_only=True, subset_by_index=[0, 11])
+    eig, _, info = _solve(cell, 12, 0, 5, nvecx=24)
+    assert info["restarts"] > 0
+    assert np.abs(eig - ref).max() < 1e-9
+
+
+def test_davidson_free_electron_shells():
+    cell = cellgen.make_cell("c1", vzero=True, nobeta=True)
+    s = 0.39478417604357434   # (2 pi / 10)^2
+    ref = np.array([0.0] + [s] * 6 + [2 * s] * 9)
+    eig, _, _ = _solve(cell, 16, 0, 16, nvecx=64)
+    assert np.abs(eig - ref).max() < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-6)])
+def test_davidson_served_cell_vs_lapack(prec, tol):
+    cell = cellgen.random_served_cell(nat=10, ecutwfc=25.0, kidx=2, seed=77)
+    nb = cell.nbnd
+    ref = sla.eigh(oracle.dense_h(cell), eigvals_only=True, subset_by_index=[0, nb - 1])
+    eig, _, _ = _solve(cell, nb, prec, nb, nvecx=4 * nb)
+    assert np.abs(eig - ref).max() < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-9), (1, 1e-6)])
+def test_davidson_c2_vs_oracle_golden(prec, tol):
+    path = os.path.join(GOLDEN, "c2_eigs.txt")
+    ref = np.loadtxt(path)
+    cell = cellgen.make_cell("c2")
+    eig, _, info = _solve(cell, 128, prec, 128, nvecx=512)
+    assert info["status"] == 0
+    assert np.abs(eig - ref).max() < tol, np.abs(eig - ref).max()
