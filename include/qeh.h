@@ -149,6 +149,58 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
 qeh_status qeh_ctx_profile(qeh_ctx *ctx, int enable);
 qeh_status qeh_ctx_stage_times(qeh_ctx *ctx, double *ms, long *launches, int nstages);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of Davidson solves.
+ *
+ * The paper expects exascale throughput to come from many independent
+ * (high-throughput / ensemble) calculations and notes that oversubscribing a
+ * GPU with several small runs pays off (sections "Outlook and conclusions"
+ * and "Evolution of the GPU-enabled version").  A server owns a device arena
+ * (the HBM budget) and max_slots HIP streams.  A request is a cell at nk
+ * k-points with nb bands; each k-point is one job.  Requests are admitted
+ * first-come first-served as soon as their whole footprint fits in the free
+ * arena and nk slots are free (smaller later requests may pass a head request
+ * that has waited < 0.25 s); every admitted job runs its Davidson on its own
+ * stream, so work of different requests overlaps on the device.  Results do
+ * not depend on what else is running.
+ * ------------------------------------------------------------------------- */
+typedef struct qeh_server qeh_server;
+
+/* arena: DEVICE memory (256-byte aligned) used for every admitted job; the
+ * server never allocates device memory.  max_slots in [1, 64]. */
+qeh_status qeh_server_create(void *arena, size_t arena_bytes, int max_slots,
+                             qeh_server **out);
+
+/* Queue a request.  cells: nk HOST cell descriptors (same nb for all);
+ * psi0: HOST complex start vectors, k-point after k-point, each nb x npw_k.
+ * Everything is copied before return.  Returns QEH_ERR_REJECTED if the
+ * request could never fit (footprint > arena or nk > max_slots).
+ * Thread-safe. */
+qeh_status qeh_submit(qeh_server *srv, const qeh_cell *cells, int nk, int nb,
+                      const double *psi0, const qeh_dav_opts *opts, uint64_t *ticket);
+
+/* Results of a finished request: eig (HOST, nk*nb, k-point-major), info
+ * (HOST, nk entries, may be NULL), t_stamps[4] = arrive, admit, start,
+ * finish (seconds since server creation; may be NULL).  Returns
+ * QEH_ERR_BUSY while queued or running, QEH_ERR_INVALID for an unknown
+ * ticket, otherwise the request's status; the request is forgotten after a
+ * non-busy poll.  Thread-safe. */
+qeh_status qeh_poll(qeh_server *srv, uint64_t ticket, double *eig, qeh_dav_info *info,
+                    double *t_stamps);
+
+/* Drop a request that has not been admitted yet (QEH_ERR_BUSY if it is
+ * already running); a later poll returns QEH_ERR_REJECTED. */
+qeh_status qeh_cancel(qeh_server *srv, uint64_t ticket);
+
+/* out[0..n): queued requests, running jobs, finished requests, arena bytes in
+ * use, arena bytes, peak running jobs, seconds with >= 1 job running,
+ * seconds since creation. */
+qeh_status qeh_server_stats(qeh_server *srv, double *out, int n);
+
+/* Stops the server thread after the running jobs finish; queued requests
+ * are dropped. */
+qeh_status qeh_server_destroy(qeh_server *srv);
+
 /* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
  * precision, plane path (0 fused in one kernel, 1 split through HBM)]. */
 qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);

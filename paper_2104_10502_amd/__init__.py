@@ -80,6 +80,15 @@ _SIGS = {
     "qeh_ctx_stage_times": ([_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_long), ctypes.c_int],
                             ctypes.c_int),
     "qeh_ctx_info": ([_vp, ctypes.POINTER(ctypes.c_long), ctypes.c_int], ctypes.c_int),
+    "qeh_server_create": ([_vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)],
+                          ctypes.c_int),
+    "qeh_submit": ([_vp, ctypes.POINTER(QehCell), ctypes.c_int, ctypes.c_int, _c_dbl_p,
+                    ctypes.POINTER(DavOpts), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+    "qeh_poll": ([_vp, ctypes.c_uint64, _c_dbl_p, ctypes.POINTER(DavInfo), _c_dbl_p],
+                 ctypes.c_int),
+    "qeh_cancel": ([_vp, ctypes.c_uint64], ctypes.c_int),
+    "qeh_server_stats": ([_vp, _c_dbl_p, ctypes.c_int], ctypes.c_int),
+    "qeh_server_destroy": ([_vp], ctypes.c_int),
     "qeh_status_str": ([ctypes.c_int], ctypes.c_char_p),
     "qeh_last_error": ([], ctypes.c_char_p),
 }
@@ -118,6 +127,96 @@ def _stream_ptr(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return _vp(stream.cuda_stream)
+
+
+def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block, keep):
+    """Fill a QehCell from host arrays; ``keep`` collects the arrays it points to."""
+    k = dict(miller=np.ascontiguousarray(miller, dtype=np.int32),
+             vloc=np.ascontiguousarray(vloc, dtype=np.float64),
+             nproj=np.ascontiguousarray(nproj, dtype=np.int32),
+             beta=np.ascontiguousarray(beta, dtype=np.complex128),
+             dmat=np.ascontiguousarray(dmat, dtype=np.complex128))
+    keep.append(k)
+    c = QehCell()
+    c.lattice[:] = [float(x) for x in np.asarray(lattice, dtype=np.float64).ravel()]
+    c.fft[:] = [int(x) for x in fft]
+    c.kpt[:] = [float(x) for x in np.asarray(kpt, dtype=np.float64).ravel()]
+    c.npw = int(k["miller"].shape[0])
+    c.miller = k["miller"].ctypes.data_as(_c_int_p)
+    c.vloc = k["vloc"].ctypes.data_as(_c_dbl_p)
+    c.nat = int(k["nproj"].shape[0])
+    c.nproj = k["nproj"].ctypes.data_as(_c_int_p)
+    c.beta = k["beta"].ctypes.data_as(_c_dbl_p)
+    c.dmat = k["dmat"].ctypes.data_as(_c_dbl_p)
+    c.precision = int(precision)
+    c.block = int(block)
+    return c
+
+
+class Server:
+    """Continuous-batching Davidson server over a device arena of ``arena_bytes``."""
+
+    def __init__(self, arena_bytes, max_slots=16, device=None):
+        torch = _torch()
+        self.device = torch.device(device if device is not None else "cuda")
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
+        h = _vp()
+        _check(_lib.qeh_server_create(_vp(self.arena.data_ptr()), int(arena_bytes),
+                                      int(max_slots), ctypes.byref(h)), "qeh_server_create")
+        self._h = h
+        self._nk = {}
+
+    def submit(self, cells, psi0s, nb, precision=QEH_MIXED, block=None, nvecx=0, rtol=1e-8,
+               maxiter=0):
+        """cells: list of cell-like objects (one per k-point); psi0s: list of (nb, npw)."""
+        keep = []
+        arr = (QehCell * len(cells))()
+        for i, c in enumerate(cells):
+            arr[i] = _cell_struct(c.lattice, c.fft, c.kpt, c.miller, c.vloc, c.nproj, c.beta,
+                                  c.dmat, precision, block or nb, keep)
+        psi = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).ravel()
+                                                   for p in psi0s]))
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
+        t = ctypes.c_uint64()
+        _check(_lib.qeh_submit(self._h, arr, len(cells), int(nb), psi.ctypes.data_as(_c_dbl_p),
+                               ctypes.byref(o), ctypes.byref(t)), "qeh_submit")
+        self._nk[t.value] = (len(cells), int(nb))
+        return t.value
+
+    def poll(self, ticket):
+        """None while busy; else dict(status, eig (nk, nb), info list, stamps)."""
+        nk, nb = self._nk[ticket]
+        eig = np.zeros(nk * nb)
+        info = (DavInfo * nk)()
+        ts = (ctypes.c_double * 4)()
+        st = _lib.qeh_poll(self._h, ticket, eig.ctypes.data_as(_c_dbl_p), info, ts)
+        if st == QEH_ERR_BUSY:
+            return None
+        del self._nk[ticket]
+        err = _lib.qeh_last_error().decode(errors="replace") if st != QEH_OK else ""
+        return dict(status=st, error=err, eig=eig.reshape(nk, nb),
+                    info=[info[i].as_dict() for i in range(nk)], stamps=list(ts))
+
+    def cancel(self, ticket):
+        return _lib.qeh_cancel(self._h, ticket)
+
+    def stats(self):
+        out = (ctypes.c_double * 8)()
+        _check(_lib.qeh_server_stats(self._h, out, 8), "qeh_server_stats")
+        keys = ["queued", "running", "finished", "bytes_in_use", "arena_bytes", "peak_running",
+                "busy_s", "uptime_s"]
+        return dict(zip(keys, list(out)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.qeh_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:

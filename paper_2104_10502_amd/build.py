@@ -35,7 +35,7 @@ def _hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     is_hip = src.endswith(".hip")
-    cmd = [_hipcc()] + COMMON + (HIP_FLAGS if is_hip else ["-D__HIP_PLATFORM_AMD__"]) + \
+    cmd = [_hipcc()] + COMMON + (HIP_FLAGS if is_hip else ["--offload-arch=gfx950", "-D__HIP_PLATFORM_AMD__"]) + \
         ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

@@ -112,7 +112,18 @@ __global__ void check_finite_kernel(const double *x, long n, int *flag) {
   if (bad) flag[0] = 1;   // plain store: any writer sets the same value
 }
 
+__global__ void fill_int_kernel(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 }  // namespace
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
 
 hipError_t launch_resid_norms(const double2 *P, const double2 *Q, long ld, int npw, int nb,
                               const double *eps, double *norms, hipStream_t s) {

@@ -1,7 +1,7 @@
 // Block Davidson eigensolver on one GPU.
 //
 // The paper names the Davidson method among the GPU-accelerated iterative
-// solvers, runs the small dense generalized eigenproblem on a GPU dense
+// solvers, solves the small dense generalized eigenproblem with a GPU dense
 // solver, and keeps the iterative solver separate from the Hamiltonian
 // builder it calls (sections "Evolution of the GPU-enabled version" and
 // "Domain-specific mathematical libraries").  It gives no algorithm; this is
@@ -19,31 +19,24 @@
 // the library's MFMA complex GEMMs in FP64; the dense Hermitian generalized
 // eigensolve of the reduced pair uses rocSOLVER (the GPU counterpart of the
 // dense solver library the paper uses for this step), with its workspace
-// taken from the caller's work area so the library allocates nothing.
-#include <rocblas/rocblas.h>
+// taken from the caller's work area so the library allocates no device
+// memory.  Small pinned host buffers hold the per-iteration readback.
+#include "davidson.h"
+
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cmath>
-#include <vector>
-
-#include "qeh_internal.h"
+#include <map>
+#include <mutex>
 
 namespace qeh {
 qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldpsi,
                         double *hpsi, int ldh);
-}
-
-using namespace qeh;
 
 namespace {
 
-struct DavLayout {
-  size_t V, W, P, Q, Hr, Sr, Hw, Sw, eps, E, norms, idx, info, flag, solver;
-  size_t solver_bytes;
-  size_t total;
-};
+constexpr int kMaxSplit = 32;
 
 size_t bump2(size_t *cur, size_t bytes) {
   const size_t o = *cur;
@@ -52,6 +45,17 @@ size_t bump2(size_t *cur, size_t bytes) {
 }
 
 qeh_status solver_bytes(int n, size_t *out) {
+  // the answer depends on n only: cache it (the query needs a handle)
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(n);
+    if (it != cache.end()) {
+      *out = it->second;
+      return QEH_OK;
+    }
+  }
   rocblas_handle h;
   if (rocblas_create_handle(&h) != rocblas_status_success) {
     set_error("rocblas_create_handle failed");
@@ -64,58 +68,23 @@ qeh_status solver_bytes(int n, size_t *out) {
   rocblas_stop_device_memory_size_query(h, &sz);
   rocblas_destroy_handle(h);
   *out = sz;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[n] = sz;
   return QEH_OK;
 }
 
-qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
-  size_t cur = 0;
-  const size_t row = 16 * (size_t)c->npw;
-  L->V = bump2(&cur, row * nvecx);
-  L->W = bump2(&cur, row * nvecx);
-  L->P = bump2(&cur, row * nb);
-  L->Q = bump2(&cur, row * nb);
-  const size_t mat = 16 * (size_t)nvecx * nvecx;
-  L->Hr = bump2(&cur, mat);
-  L->Sr = bump2(&cur, mat);
-  L->Hw = bump2(&cur, mat);
-  L->Sw = bump2(&cur, mat);
-  L->eps = bump2(&cur, 8 * (size_t)nvecx);
-  L->E = bump2(&cur, 8 * (size_t)nvecx);
-  L->norms = bump2(&cur, 8 * (size_t)nb);
-  L->idx = bump2(&cur, 4 * (size_t)nb);
-  L->info = bump2(&cur, 4);
-  L->flag = bump2(&cur, 4);
-  qeh_status st = solver_bytes(nvecx, &L->solver_bytes);
-  if (st != QEH_OK) return st;
-  L->solver = bump2(&cur, std::max<size_t>(L->solver_bytes, 256));
-  L->total = cur;
-  return QEH_OK;
-}
-
-qeh_status check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *nvecx, double *rtol,
-                      int *maxiter) {
-  if (!c) {
-    set_error("ctx is null");
-    return QEH_ERR_INVALID;
-  }
-  if (nb < 1 || nb > c->npw) {
-    set_error("nb must be in [1, npw]");
-    return QEH_ERR_INVALID;
-  }
-  *nvecx = (o && o->nvecx > 0) ? o->nvecx : 2 * nb;
-  *rtol = (o && o->rtol > 0) ? o->rtol : 1e-8;
-  *maxiter = (o && o->maxiter > 0) ? o->maxiter : 200;
-  if (*nvecx < 2 * nb || *nvecx > c->npw) {
-    set_error("nvecx must be in [2 nb, npw]");
-    return QEH_ERR_INVALID;
-  }
-  return QEH_OK;
-}
-
-// C[j][i] style reduction: out(i, j0+j) = sum_G conj(X_i[G]) Y_j[G],
-// i < nrow, j < ncol; out col-major with ld.
+// out(i, j) = sum_G conj(X_i[G]) Y_j[G] for i < nrow, j < ncol; out col-major
+// with ld.  K = npw is long: split into fixed chunks whose partial products
+// go to `part` and are summed in double in a fixed order.
 hipError_t reduce_cols(const qeh_ctx *c, const double2 *X, int nrow, const double2 *Y, int ncol,
-                       double2 *out, int ld) {
+                       double2 *out, int ld, double2 *part) {
+  const int tiles = ((ncol + 63) / 64) * ((nrow + 63) / 64);
+  int ns = std::max(1, (512 + tiles - 1) / tiles);
+  ns = std::min(ns, std::max(1, c->npw / 256));
+  ns = std::min(ns, kMaxSplit);
+  int kc = (c->npw + ns - 1) / ns;
+  kc = (kc + 7) / 8 * 8;
+  ns = (c->npw + kc - 1) / kc;
   GemmDesc g{};
   g.A = Y;
   g.lda = c->npw;
@@ -125,16 +94,27 @@ hipError_t reduce_cols(const qeh_ctx *c, const double2 *X, int nrow, const doubl
   g.tb = T_D2;
   g.bmode = 0;
   g.conjB = 1;
-  g.C = out;
-  g.ldc = ld;
   g.tc = T_D2;
   g.M = ncol;
   g.N = nrow;
   g.K = c->npw;
-  g.nsplit = 1;
-  g.kchunk = c->npw;
   g.prec = G_F64;
-  return launch_cgemm(g, c->stream);
+  if (ns == 1) {
+    g.C = out;
+    g.ldc = ld;
+    g.nsplit = 1;
+    g.kchunk = c->npw;
+    return launch_cgemm(g, c->stream);
+  }
+  g.C = part;
+  g.ldc = nrow;
+  g.nsplit = ns;
+  g.kchunk = kc;
+  g.split_stride = (long)ncol * nrow;
+  hipError_t e = launch_cgemm(g, c->stream);
+  if (e != hipSuccess) return e;
+  return launch_splitk_reduce(part, T_D2, (long)ncol * nrow, ns, ncol, nrow, nrow, out, ld, 0,
+                              c->stream);
 }
 
 // rows b < nb: out_b = sum_j Y(j, b) X_j  (Y col-major ld, j < n)
@@ -160,68 +140,90 @@ hipError_t rotate(const qeh_ctx *c, const double2 *Y, int ld, int n, int nb, con
   return launch_cgemm(g, c->stream);
 }
 
-// Device-time accumulator: event pairs are recorded around enqueued work and
-// read back only after the host has synchronised the stream.
-struct EvPool {
-  std::vector<hipEvent_t> ev;
-  size_t used = 0;
-  double acc = 0.0;
-  void start(hipStream_t s) {
-    while (ev.size() < used + 2) {
-      hipEvent_t x;
-      if (hipEventCreate(&x) != hipSuccess) return;
-      ev.push_back(x);
-    }
-    (void)hipEventRecord(ev[used], s);
-  }
-  void stop(hipStream_t s) {
-    if (ev.size() < used + 2) return;
-    (void)hipEventRecord(ev[used + 1], s);
-    used += 2;
-  }
-  void harvest() {   // call after a stream synchronisation
-    for (size_t i = 0; i + 1 < used; i += 2) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc += ms * 1e-3;
-    }
-    used = 0;
-  }
-  void destroy() {
-    for (auto x : ev) (void)hipEventDestroy(x);
-    ev.clear();
-  }
-};
-
 }  // namespace
 
-extern "C" {
+void EvPool::start(hipStream_t s) {
+  while (ev.size() < used + 2) {
+    hipEvent_t x;
+    if (hipEventCreate(&x) != hipSuccess) return;
+    ev.push_back(x);
+  }
+  (void)hipEventRecord(ev[used], s);
+}
 
-qeh_status qeh_davidson_plan(const qeh_ctx *c, int nb, const qeh_dav_opts *o,
-                             size_t *work_bytes) {
-  if (!work_bytes) {
-    set_error("work_bytes is null");
+void EvPool::stop(hipStream_t s) {
+  if (ev.size() < used + 2) return;
+  (void)hipEventRecord(ev[used + 1], s);
+  used += 2;
+}
+
+void EvPool::harvest() {
+  for (size_t i = 0; i + 1 < used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) acc += ms * 1e-3;
+  }
+  used = 0;
+}
+
+void EvPool::destroy() {
+  for (auto x : ev) (void)hipEventDestroy(x);
+  ev.clear();
+  used = 0;
+}
+
+qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *nvecx,
+                          double *rtol, int *maxiter) {
+  if (!c) {
+    set_error("ctx is null");
     return QEH_ERR_INVALID;
   }
-  int nvecx, maxiter;
-  double rtol;
-  qeh_status st = check_opts(c, nb, o, &nvecx, &rtol, &maxiter);
-  if (st != QEH_OK) return st;
-  DavLayout L;
-  st = dav_layout(c, nb, nvecx, &L);
-  if (st != QEH_OK) return st;
-  *work_bytes = L.total;
+  if (nb < 1 || nb > c->npw) {
+    set_error("nb must be in [1, npw]");
+    return QEH_ERR_INVALID;
+  }
+  *nvecx = (o && o->nvecx > 0) ? o->nvecx : 2 * nb;
+  *rtol = (o && o->rtol > 0) ? o->rtol : 1e-8;
+  *maxiter = (o && o->maxiter > 0) ? o->maxiter : 200;
+  if (*nvecx < 2 * nb || *nvecx > c->npw) {
+    set_error("nvecx must be in [2 nb, npw]");
+    return QEH_ERR_INVALID;
+  }
   return QEH_OK;
 }
 
-qeh_status qeh_davidson(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double *eig,
-                        const qeh_dav_opts *o, void *work, size_t work_bytes,
-                        qeh_dav_info *info) {
-  const auto t0 = std::chrono::steady_clock::now();
-  int nvecx, maxiter;
-  double rtol;
-  qeh_status st = check_opts(c, nb, o, &nvecx, &rtol, &maxiter);
+qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
+  size_t cur = 0;
+  const size_t row = 16 * (size_t)c->npw;
+  L->V = bump2(&cur, row * nvecx);
+  L->W = bump2(&cur, row * nvecx);
+  L->P = bump2(&cur, row * nb);
+  L->Q = bump2(&cur, row * nb);
+  const size_t mat = 16 * (size_t)nvecx * nvecx;
+  L->Hr = bump2(&cur, mat);
+  L->Sr = bump2(&cur, mat);
+  L->Hw = bump2(&cur, mat);
+  L->Sw = bump2(&cur, mat);
+  L->part = bump2(&cur, 16 * (size_t)kMaxSplit * nb * nvecx);
+  L->eps = bump2(&cur, 8 * (size_t)nvecx);
+  L->E = bump2(&cur, 8 * (size_t)nvecx);
+  L->norms = bump2(&cur, 8 * (size_t)nb);
+  L->idx = bump2(&cur, 4 * (size_t)nb);
+  L->info = bump2(&cur, 4);
+  L->flag = bump2(&cur, 4);
+  qeh_status st = solver_bytes(nvecx, &L->solver_bytes);
   if (st != QEH_OK) return st;
-  if (!psi_inout || !eig || !work) {
+  L->solver = bump2(&cur, std::max<size_t>(L->solver_bytes, 256));
+  L->total = cur;
+  return QEH_OK;
+}
+
+qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig,
+                        const qeh_dav_opts *o, void *work, size_t work_bytes) {
+  t0_ = std::chrono::steady_clock::now();
+  double rtol;
+  qeh_status st = dav_check_opts(c, nb, o, &nvecx_, &rtol, &maxiter_);
+  if (st != QEH_OK) return st;
+  if (!psi || !eig || !work) {
     set_error("psi_inout, eig and work must be non-null");
     return QEH_ERR_INVALID;
   }
@@ -233,219 +235,309 @@ qeh_status qeh_davidson(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double
     set_error("work not 256-byte aligned");
     return QEH_ERR_INVALID;
   }
-  DavLayout L;
-  st = dav_layout(c, nb, nvecx, &L);
+  st = dav_layout(c, nb, nvecx_, &L_);
   if (st != QEH_OK) return st;
-  if (work_bytes < L.total) {
+  if (work_bytes < L_.total) {
     set_error("work area has " + std::to_string(work_bytes) + " bytes, plan needs " +
-              std::to_string(L.total));
+              std::to_string(L_.total));
     return QEH_ERR_NOMEM;
   }
-  const bool mixed = c->prec == QEH_MIXED;
-  const double thr = mixed ? std::max(rtol, 1e-5) : rtol;
-  const int npw = c->npw;
-  hipStream_t s = c->stream;
+  c_ = c;
+  nb_ = nb;
+  psi_ = psi;
+  ldpsi_ = ldpsi;
+  eig_ = eig;
+  npw_ = c->npw;
+  mixed_ = c->prec == QEH_MIXED;
+  thr_ = mixed_ ? std::max(rtol, 1e-5) : rtol;
   char *w = reinterpret_cast<char *>(work);
-  double2 *V = reinterpret_cast<double2 *>(w + L.V);
-  double2 *W = reinterpret_cast<double2 *>(w + L.W);
-  double2 *P = reinterpret_cast<double2 *>(w + L.P);
-  double2 *Q = reinterpret_cast<double2 *>(w + L.Q);
-  double2 *Hr = reinterpret_cast<double2 *>(w + L.Hr);
-  double2 *Sr = reinterpret_cast<double2 *>(w + L.Sr);
-  double2 *Hw = reinterpret_cast<double2 *>(w + L.Hw);
-  double2 *Sw = reinterpret_cast<double2 *>(w + L.Sw);
-  double *eps_d = reinterpret_cast<double *>(w + L.eps);
-  double *E_d = reinterpret_cast<double *>(w + L.E);
-  double *norms_d = reinterpret_cast<double *>(w + L.norms);
-  int *idx_d = reinterpret_cast<int *>(w + L.idx);
-  int *info_d = reinterpret_cast<int *>(w + L.info);
-  int *flag_d = reinterpret_cast<int *>(w + L.flag);
-  double2 *psi = reinterpret_cast<double2 *>(psi_inout);
-
-  rocblas_handle rh = nullptr;
-  if (rocblas_create_handle(&rh) != rocblas_status_success) {
+  V_ = reinterpret_cast<double2 *>(w + L_.V);
+  W_ = reinterpret_cast<double2 *>(w + L_.W);
+  P_ = reinterpret_cast<double2 *>(w + L_.P);
+  Q_ = reinterpret_cast<double2 *>(w + L_.Q);
+  Hr_ = reinterpret_cast<double2 *>(w + L_.Hr);
+  Sr_ = reinterpret_cast<double2 *>(w + L_.Sr);
+  Hw_ = reinterpret_cast<double2 *>(w + L_.Hw);
+  Sw_ = reinterpret_cast<double2 *>(w + L_.Sw);
+  part_ = reinterpret_cast<double2 *>(w + L_.part);
+  eps_d_ = reinterpret_cast<double *>(w + L_.eps);
+  E_d_ = reinterpret_cast<double *>(w + L_.E);
+  norms_d_ = reinterpret_cast<double *>(w + L_.norms);
+  idx_d_ = reinterpret_cast<int *>(w + L_.idx);
+  info_d_ = reinterpret_cast<int *>(w + L_.info);
+  flag_d_ = reinterpret_cast<int *>(w + L_.flag);
+  // pinned host readback: eps, norms (nb doubles each), idx (nb ints), 2 ints
+  void *h = nullptr;
+  const size_t hb = 16 * (size_t)nb + 4 * (size_t)nb + 16;
+  hipError_t e = hipHostMalloc(&h, hb, hipHostMallocDefault);
+  if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
+  h_eps_ = reinterpret_cast<double *>(h);
+  h_nrm_ = h_eps_ + nb;
+  h_idx_ = reinterpret_cast<int *>(h_nrm_ + nb);
+  h_int_ = h_idx_ + nb;
+  eps_prev_.assign(nb, INFINITY);
+  if (rocblas_create_handle(&rh_) != rocblas_status_success) {
+    rh_ = nullptr;
+    release();
     set_error("rocblas_create_handle failed");
     return QEH_ERR_DEVICE;
   }
-  rocblas_set_stream(rh, s);
-  if (rocblas_set_workspace(rh, w + L.solver, std::max<size_t>(L.solver_bytes, 256)) !=
+  rocblas_set_stream(rh_, c->stream);
+  if (rocblas_set_workspace(rh_, w + L_.solver, std::max<size_t>(L_.solver_bytes, 256)) !=
       rocblas_status_success) {
-    rocblas_destroy_handle(rh);
+    release();
     set_error("rocblas_set_workspace failed");
     return QEH_ERR_DEVICE;
   }
-  EvPool ev_h, ev_s;
-  auto cleanup = [&]() {
-    ev_h.destroy();
-    ev_s.destroy();
-    rocblas_destroy_handle(rh);
-  };
+  phase_ = kStart;
+  notconv_ = nb;
+  resid_max_ = INFINITY;
+  return QEH_OK;
+}
 
-  hipError_t e = hipSuccess;
-  auto ok = [&](hipError_t x) {
-    if (e == hipSuccess) e = x;
-  };
-  long band_applies = 0;
-  auto hpsi = [&](const double2 *x, double2 *y, int n) -> qeh_status {
-    ev_h.start(s);
-    qeh_status r = apply_h_impl(c, 2, n, reinterpret_cast<const double *>(x), npw,
-                                reinterpret_cast<double *>(y), npw);
-    ev_h.stop(s);
-    band_applies += n;
-    return r;
-  };
+void DavRun::release() {
+  ev_h_.destroy();
+  ev_s_.destroy();
+  if (rh_) rocblas_destroy_handle(rh_);
+  rh_ = nullptr;
+  if (h_eps_) (void)hipHostFree(h_eps_);
+  h_eps_ = nullptr;
+}
 
-  // ---- start: finiteness of psi0, V = psi0, W = H V
-  ok(hipMemsetAsync(flag_d, 0, 4, s));
-  for (int b = 0; b < nb; ++b)
-    ok(launch_check_finite(psi_inout + 2 * (size_t)b * ldpsi, 2 * (long)npw, flag_d, s));
-  ok(launch_copy_rows(psi, ldpsi, V, npw, npw, nb, s));
-  int hflag = 0;
-  ok(hipMemcpyAsync(&hflag, flag_d, 4, hipMemcpyDeviceToHost, s));
-  ok(hipStreamSynchronize(s));
-  if (e != hipSuccess) {
-    cleanup();
-    return hip_fail(e, "davidson start");
-  }
-  if (hflag) {
-    cleanup();
-    set_error("psi0 has a non-finite value");
-    return QEH_ERR_NUMERIC;
-  }
-  st = hpsi(V, W, nb);
-  if (st != QEH_OK) {
-    cleanup();
-    return st;
-  }
-  ok(reduce_cols(c, V, nb, W, nb, Hr, nvecx));
-  ok(reduce_cols(c, V, nb, V, nb, Sr, nvecx));
-  int nbase = nb;
+qeh_status DavRun::hpsi(const double2 *x, double2 *y, int n) {
+  ev_h_.start(c_->stream);
+  qeh_status r = apply_h_impl(c_, 2, n, reinterpret_cast<const double *>(x), npw_,
+                              reinterpret_cast<double *>(y), npw_);
+  ev_h_.stop(c_->stream);
+  band_applies_ += n;
+  return r;
+}
 
-  std::vector<double> eps(nb), eps_prev(nb, INFINITY), nrm(nb);
-  std::vector<int> idx(nb);
-  int it = 0, restarts = 0, notconv = nb;
-  bool chol_prev = false, have_ritz = false;
-  double resid_max = INFINITY;
-  qeh_status result = QEH_OK;
+bool DavRun::fail_device(const char *what) {
+  result_ = hip_fail(err_, what);
+  phase_ = kDone;
+  return true;
+}
+
+bool DavRun::advance() {
+  hipStream_t s = c_->stream;
+  const int nb = nb_, npw = npw_, nvecx = nvecx_;
   while (true) {
-    ++it;
-    // ---- Rayleigh-Ritz on the reduced pair
-    ev_s.start(s);
-    ok(launch_hermitise_copy(Hr, nvecx, Hw, nvecx, nbase, s));
-    ok(launch_hermitise_copy(Sr, nvecx, Sw, nvecx, nbase, s));
-    rocblas_status rs = rocsolver_zhegvd(
-        rh, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, nbase,
-        reinterpret_cast<rocblas_double_complex *>(Hw), nvecx,
-        reinterpret_cast<rocblas_double_complex *>(Sw), nvecx, eps_d, E_d, info_d);
-    if (rs != rocblas_status_success) {
-      cleanup();
-      set_error("rocsolver_zhegvd failed to launch");
-      return QEH_ERR_DEVICE;
-    }
-    int hinfo = 0;
-    ok(hipMemcpyAsync(&hinfo, info_d, 4, hipMemcpyDeviceToHost, s));
-    ok(hipStreamSynchronize(s));
-    if (e != hipSuccess) break;
-    if (hinfo != 0) {
-      ev_s.stop(s);
-      // overlap matrix not positive definite (or no convergence of the solver)
-      if (chol_prev || !have_ritz) {
-        result = QEH_ERR_CHOLESKY;
-        set_error("reduced overlap matrix not positive definite");
+    if (err_ != hipSuccess) return fail_device("davidson");
+    switch (phase_) {
+      case kStart: {
+        // finiteness of psi0, V = psi0
+        ok(launch_fill_int(flag_d_, 1, 0, s));
+        for (int b = 0; b < nb; ++b)
+          ok(launch_check_finite(reinterpret_cast<const double *>(psi_ + (size_t)b * ldpsi_),
+                                 2 * (long)npw, flag_d_, s));
+        ok(launch_copy_rows(psi_, ldpsi_, V_, npw, npw, nb, s));
+        ok(hipMemcpyAsync(h_int_, flag_d_, 4, hipMemcpyDeviceToHost, s));
+        phase_ = kCheckInput;
+        return false;
+      }
+      case kCheckInput: {
+        if (h_int_[0]) {
+          set_error("psi0 has a non-finite value");
+          result_ = QEH_ERR_NUMERIC;
+          phase_ = kDone;
+          return true;
+        }
+        qeh_status st = hpsi(V_, W_, nb);
+        if (st != QEH_OK) {
+          result_ = st;
+          phase_ = kDone;
+          return true;
+        }
+        ok(reduce_cols(c_, V_, nb, W_, nb, Hr_, nvecx, part_));
+        ok(reduce_cols(c_, V_, nb, V_, nb, Sr_, nvecx, part_));
+        nbase_ = nb;
+        phase_ = kRR;
         break;
       }
-      chol_prev = true;
-      ++restarts;
-      ok(launch_copy_rows(P, npw, V, npw, npw, nb, s));
-      ok(launch_copy_rows(Q, npw, W, npw, npw, nb, s));
-      nbase = nb;
-      ok(reduce_cols(c, V, nb, W, nb, Hr, nvecx));
-      ok(reduce_cols(c, V, nb, V, nb, Sr, nvecx));
-      continue;
-    }
-    chol_prev = false;
-    // ---- Ritz vectors, residual norms
-    ok(rotate(c, Hw, nvecx, nbase, nb, V, P));
-    ok(rotate(c, Hw, nvecx, nbase, nb, W, Q));
-    ok(launch_resid_norms(P, Q, npw, npw, nb, eps_d, norms_d, s));
-    ev_s.stop(s);
-    have_ritz = true;
-    ok(hipMemcpyAsync(eps.data(), eps_d, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
-    ok(hipMemcpyAsync(nrm.data(), norms_d, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
-    ok(hipStreamSynchronize(s));
-    if (e != hipSuccess) break;
-    ev_h.harvest();
-    ev_s.harvest();
-    int nc = 0;
-    resid_max = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double r = std::sqrt(std::max(nrm[b], 0.0));
-      if (!std::isfinite(r)) {
-        result = QEH_ERR_NUMERIC;
-        set_error("non-finite residual");
+      case kRR: {
+        ++it_;
+        ev_s_.start(s);
+        ok(launch_hermitise_copy(Hr_, nvecx, Hw_, nvecx, nbase_, s));
+        ok(launch_hermitise_copy(Sr_, nvecx, Sw_, nvecx, nbase_, s));
+        rocblas_status rs = rocsolver_zhegvd(
+            rh_, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, nbase_,
+            reinterpret_cast<rocblas_double_complex *>(Hw_), nvecx,
+            reinterpret_cast<rocblas_double_complex *>(Sw_), nvecx, eps_d_, E_d_, info_d_);
+        ev_s_.stop(s);
+        if (rs != rocblas_status_success) {
+          set_error("rocsolver_zhegvd failed to launch");
+          result_ = QEH_ERR_DEVICE;
+          phase_ = kDone;
+          return true;
+        }
+        ok(hipMemcpyAsync(h_int_ + 1, info_d_, 4, hipMemcpyDeviceToHost, s));
+        phase_ = kRRCheck;
+        return false;
       }
-      resid_max = std::max(resid_max, r);
-      bool conv = r <= thr;
-      if (mixed && std::fabs(eps[b] - eps_prev[b]) <= 1e-8) conv = true;
-      if (!conv) idx[nc++] = b;
+      case kRRCheck: {
+        if (h_int_[1] != 0) {
+          // reduced overlap not positive definite (or solver failure)
+          if (chol_prev_ || !have_ritz_) {
+            set_error("reduced overlap matrix not positive definite");
+            result_ = QEH_ERR_CHOLESKY;
+            if (!have_ritz_) {
+              phase_ = kDone;
+              return true;
+            }
+            ok(launch_copy_rows(P_, npw, psi_, ldpsi_, npw, nb, s));
+            phase_ = kFinish;
+            return false;
+          }
+          // restart from the last Ritz vectors (orthonormal)
+          chol_prev_ = true;
+          ++restarts_;
+          ok(launch_copy_rows(P_, npw, V_, npw, npw, nb, s));
+          ok(launch_copy_rows(Q_, npw, W_, npw, npw, nb, s));
+          nbase_ = nb;
+          ok(reduce_cols(c_, V_, nb, W_, nb, Hr_, nvecx, part_));
+          ok(reduce_cols(c_, V_, nb, V_, nb, Sr_, nvecx, part_));
+          phase_ = kRR;
+          break;
+        }
+        chol_prev_ = false;
+        ev_s_.start(s);
+        ok(rotate(c_, Hw_, nvecx, nbase_, nb, V_, P_));
+        ok(rotate(c_, Hw_, nvecx, nbase_, nb, W_, Q_));
+        ok(launch_resid_norms(P_, Q_, npw, npw, nb, eps_d_, norms_d_, s));
+        ev_s_.stop(s);
+        have_ritz_ = true;
+        ok(hipMemcpyAsync(h_eps_, eps_d_, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
+        ok(hipMemcpyAsync(h_nrm_, norms_d_, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
+        phase_ = kConverge;
+        return false;
+      }
+      case kConverge: {
+        ev_h_.harvest();
+        ev_s_.harvest();
+        int nc = 0;
+        resid_max_ = 0.0;
+        bool finite = true;
+        for (int b = 0; b < nb; ++b) {
+          const double r = std::sqrt(std::max(h_nrm_[b], 0.0));
+          if (!std::isfinite(r) || !std::isfinite(h_eps_[b])) finite = false;
+          resid_max_ = std::max(resid_max_, r);
+          bool conv = r <= thr_;
+          if (mixed_ && std::fabs(h_eps_[b] - eps_prev_[b]) <= 1e-8) conv = true;
+          if (!conv) h_idx_[nc++] = b;
+        }
+        for (int b = 0; b < nb; ++b) eps_prev_[b] = h_eps_[b];
+        notconv_ = nc;
+        if (!finite) {
+          set_error("non-finite residual or eigenvalue");
+          result_ = QEH_ERR_NUMERIC;
+        } else if (nc > 0 && it_ >= maxiter_) {
+          set_error("Davidson reached maxiter");
+          result_ = QEH_ERR_NOT_CONVERGED;
+        }
+        if (nc == 0 || result_ != QEH_OK) {
+          ok(launch_copy_rows(P_, npw, psi_, ldpsi_, npw, nb, s));
+          phase_ = kFinish;
+          return false;
+        }
+        ok(hipMemcpyAsync(idx_d_, h_idx_, 4 * (size_t)nc, hipMemcpyHostToDevice, s));
+        if (nbase_ + nc > nvecx) {
+          ++restarts_;
+          ok(launch_copy_rows(P_, npw, V_, npw, npw, nb, s));
+          ok(launch_copy_rows(Q_, npw, W_, npw, npw, nb, s));
+          ok(launch_set_diag(Hr_, nvecx, nb, eps_d_, s));
+          ok(launch_set_diag(Sr_, nvecx, nb, nullptr, s));
+          nbase_ = nb;
+        }
+        ok(launch_precond(P_, Q_, npw, npw, idx_d_, nc, eps_d_, c_->d.hdiag,
+                          V_ + (size_t)nbase_ * npw, npw, s));
+        qeh_status st = hpsi(V_ + (size_t)nbase_ * npw, W_ + (size_t)nbase_ * npw, nc);
+        if (st != QEH_OK) {
+          result_ = st;
+          phase_ = kDone;
+          return true;
+        }
+        ev_s_.start(s);
+        ok(reduce_cols(c_, V_, nbase_ + nc, W_ + (size_t)nbase_ * npw, nc,
+                       Hr_ + (size_t)nbase_ * nvecx, nvecx, part_));
+        ok(reduce_cols(c_, V_, nbase_ + nc, V_ + (size_t)nbase_ * npw, nc,
+                       Sr_ + (size_t)nbase_ * nvecx, nvecx, part_));
+        ok(launch_herm_fill(Hr_, nvecx, nbase_, nbase_ + nc, s));
+        ok(launch_herm_fill(Sr_, nvecx, nbase_, nbase_ + nc, s));
+        ev_s_.stop(s);
+        nbase_ += nc;
+        phase_ = kRR;
+        break;
+      }
+      case kFinish: {
+        ev_h_.harvest();
+        ev_s_.harvest();
+        for (int b = 0; b < nb; ++b) eig_[b] = h_eps_[b];
+        t_total_ = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0_).count();
+        phase_ = kDone;
+        return true;
+      }
+      case kDone:
+        return true;
     }
-    eps_prev = eps;
-    notconv = nc;
-    if (result != QEH_OK) break;
-    if (nc == 0) break;
-    if (it >= maxiter) {
-      result = QEH_ERR_NOT_CONVERGED;
-      set_error("Davidson reached maxiter");
-      break;
-    }
-    ok(hipMemcpyAsync(idx_d, idx.data(), 4 * (size_t)nc, hipMemcpyHostToDevice, s));
-    if (nbase + nc > nvecx) {
-      ++restarts;
-      ok(launch_copy_rows(P, npw, V, npw, npw, nb, s));
-      ok(launch_copy_rows(Q, npw, W, npw, npw, nb, s));
-      ok(launch_set_diag(Hr, nvecx, nb, eps_d, s));
-      ok(launch_set_diag(Sr, nvecx, nb, nullptr, s));
-      nbase = nb;
-    }
-    ok(launch_precond(P, Q, npw, npw, idx_d, nc, eps_d, c->d.hdiag, V + (size_t)nbase * npw, npw,
-                      s));
-    st = hpsi(V + (size_t)nbase * npw, W + (size_t)nbase * npw, nc);
-    if (st != QEH_OK) {
-      result = st;
-      break;
-    }
-    ev_s.start(s);
-    ok(reduce_cols(c, V, nbase + nc, W + (size_t)nbase * npw, nc, Hr + (size_t)nbase * nvecx,
-                   nvecx));
-    ok(reduce_cols(c, V, nbase + nc, V + (size_t)nbase * npw, nc, Sr + (size_t)nbase * nvecx,
-                   nvecx));
-    ok(launch_herm_fill(Hr, nvecx, nbase, nbase + nc, s));
-    ok(launch_herm_fill(Sr, nvecx, nbase, nbase + nc, s));
-    ev_s.stop(s);
-    nbase += nc;
-    if (e != hipSuccess) break;
   }
-  if (e == hipSuccess && have_ritz) {
-    ok(launch_copy_rows(P, npw, psi, ldpsi, npw, nb, s));
-    ok(hipStreamSynchronize(s));
-    for (int b = 0; b < nb; ++b) eig[b] = eps[b];
+}
+
+void DavRun::fill_info(qeh_dav_info *info) const {
+  if (!info) return;
+  info->iters = it_;
+  info->notconv = notconv_;
+  info->restarts = restarts_;
+  info->band_applies = band_applies_;
+  info->resid_max = resid_max_;
+  info->t_hpsi = ev_h_.acc;
+  info->t_subspace = ev_s_.acc;
+  info->t_total = t_total_ > 0.0 ? t_total_
+                                 : std::chrono::duration<double>(
+                                       std::chrono::steady_clock::now() - t0_).count();
+}
+
+}  // namespace qeh
+
+using namespace qeh;
+
+extern "C" {
+
+qeh_status qeh_davidson_plan(const qeh_ctx *c, int nb, const qeh_dav_opts *o,
+                             size_t *work_bytes) {
+  if (!work_bytes) {
+    set_error("work_bytes is null");
+    return QEH_ERR_INVALID;
   }
-  ev_h.harvest();
-  ev_s.harvest();
-  if (info) {
-    info->iters = it;
-    info->notconv = notconv;
-    info->restarts = restarts;
-    info->band_applies = band_applies;
-    info->resid_max = resid_max;
-    info->t_hpsi = ev_h.acc;
-    info->t_subspace = ev_s.acc;
-    info->t_total =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int nvecx, maxiter;
+  double rtol;
+  qeh_status st = dav_check_opts(c, nb, o, &nvecx, &rtol, &maxiter);
+  if (st != QEH_OK) return st;
+  DavLayout L;
+  st = dav_layout(c, nb, nvecx, &L);
+  if (st != QEH_OK) return st;
+  *work_bytes = L.total;
+  return QEH_OK;
+}
+
+qeh_status qeh_davidson(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double *eig,
+                        const qeh_dav_opts *o, void *work, size_t work_bytes,
+                        qeh_dav_info *info) {
+  DavRun run;
+  qeh_status st = run.init(c, nb, reinterpret_cast<double2 *>(psi_inout), ldpsi, eig, o, work,
+                           work_bytes);
+  if (st != QEH_OK) return st;
+  while (!run.advance()) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      run.release();
+      return hip_fail(e, "davidson sync");
+    }
   }
-  cleanup();
-  if (e != hipSuccess) return hip_fail(e, "davidson");
-  return result;
+  run.fill_info(info);
+  const qeh_status r = run.result();
+  run.release();
+  return r;
 }
 
 }  // extern "C"

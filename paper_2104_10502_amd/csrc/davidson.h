@@ -1,0 +1,86 @@
+// Resumable block-Davidson run (internal).  advance() enqueues device work on
+// the context stream up to the next point where the host needs device
+// results, and returns false; after the stream has drained the caller calls
+// advance() again.  It returns true once the run is finished.  The blocking
+// qeh_davidson() and the request server both drive this one state machine.
+#pragma once
+
+#include <rocblas/rocblas.h>
+
+#include <chrono>
+#include <vector>
+
+#include "qeh_internal.h"
+
+namespace qeh {
+
+struct DavLayout {
+  size_t V, W, P, Q, Hr, Sr, Hw, Sw, part, eps, E, norms, idx, info, flag, solver;
+  size_t solver_bytes;
+  size_t total;
+};
+
+// Device-time accumulator: event pairs recorded around enqueued work, read
+// back only after the host has seen the stream drain.
+struct EvPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  double acc = 0.0;
+  void start(hipStream_t s);
+  void stop(hipStream_t s);
+  void harvest();
+  void destroy();
+};
+
+qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *nvecx,
+                          double *rtol, int *maxiter);
+qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L);
+
+class DavRun {
+ public:
+  // Validates and binds; nothing is enqueued yet.  eig is a host array of nb.
+  qeh_status init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig,
+                  const qeh_dav_opts *o, void *work, size_t work_bytes);
+  bool advance();
+  qeh_status result() const { return result_; }
+  void fill_info(qeh_dav_info *info) const;
+  void release();
+  ~DavRun() { release(); }
+
+ private:
+  enum Phase { kStart, kCheckInput, kRR, kRRCheck, kConverge, kFinish, kDone };
+  qeh_status hpsi(const double2 *x, double2 *y, int n);
+  void ok(hipError_t e) {
+    if (err_ == hipSuccess) err_ = e;
+  }
+  bool fail_device(const char *what);
+
+  qeh_ctx *c_ = nullptr;
+  int nb_ = 0, ldpsi_ = 0, nvecx_ = 0, maxiter_ = 0, npw_ = 0;
+  double thr_ = 0.0;
+  bool mixed_ = false;
+  double2 *psi_ = nullptr;
+  double *eig_ = nullptr;
+  DavLayout L_{};
+  double2 *V_ = nullptr, *W_ = nullptr, *P_ = nullptr, *Q_ = nullptr;
+  double2 *Hr_ = nullptr, *Sr_ = nullptr, *Hw_ = nullptr, *Sw_ = nullptr, *part_ = nullptr;
+  double *eps_d_ = nullptr, *E_d_ = nullptr, *norms_d_ = nullptr;
+  int *idx_d_ = nullptr, *info_d_ = nullptr, *flag_d_ = nullptr;
+  // pinned host mirrors of the per-iteration readback
+  double *h_eps_ = nullptr, *h_nrm_ = nullptr;
+  int *h_idx_ = nullptr, *h_int_ = nullptr;   // h_int_[0] flag, [1] solver info
+  std::vector<double> eps_prev_;
+  rocblas_handle rh_ = nullptr;
+  EvPool ev_h_, ev_s_;
+  Phase phase_ = kStart;
+  int it_ = 0, restarts_ = 0, notconv_ = 0, nbase_ = 0;
+  bool chol_prev_ = false, have_ritz_ = false;
+  double resid_max_ = 0.0;
+  long band_applies_ = 0;
+  qeh_status result_ = QEH_OK;
+  hipError_t err_ = hipSuccess;
+  std::chrono::steady_clock::time_point t0_;
+  double t_total_ = 0.0;
+};
+
+}  // namespace qeh

@@ -13,6 +13,8 @@
 // (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
 // split into fixed chunks whose partial results are summed in double by a
 // separate kernel in a fixed order (deterministic, no atomics).
+#include <algorithm>
+
 #include "cplx.h"
 #include "qeh_internal.h"
 
@@ -48,6 +50,16 @@ __device__ __forceinline__ void ld_elem(const T *p, bool valid, bool cj, R &re, 
   }
 }
 
+template <typename T> __device__ __forceinline__ T zero_of() {
+  T z;
+  z.x = 0;
+  z.y = 0;
+  return z;
+}
+
+// One workgroup: a BM x BN tile of C over the K slice [kbeg, kend).  Global
+// tiles are prefetched into registers while the MFMAs consume the LDS copy of
+// the previous slice (two LDS buffers, one barrier per slice).
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
 __global__ __launch_bounds__(kGT) void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
@@ -57,8 +69,11 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
   constexpr int BKP = BK + 1;
   constexpr int TM = BM / 32;
   constexpr int TN = BN / 32;
-  __shared__ R As[2][BM * BKP];
-  __shared__ R Bs[2][BN * BKP];
+  constexpr int NA = BM * BK / kGT;
+  constexpr int NB = BN * BK / kGT;
+  static_assert(NA * kGT == BM * BK && NB * kGT == BN * BK, "tile / thread mismatch");
+  __shared__ R As[2][2][BM * BKP];   // [buffer][re, im]
+  __shared__ R Bs[2][2][BN * BKP];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -71,6 +86,8 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
   TC *Cz = C + (long)kz * split_stride;
+  const R sa = conjA ? R(-1) : R(1);
+  const R sb = conjB ? R(-1) : R(1);
 
   ACC acc_r[TM][TN], acc_i[TM][TN];
 #pragma unroll
@@ -81,55 +98,81 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
       acc_i[i][j] = ACC{0, 0, 0, 0};
     }
 
+  TA ra[NA];
+  TB rb[NB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * kGT;
+      const int r = e / BK, k = e % BK;
+      const int gm = m0 + r, gk = k0 + k;
+      ra[u] = (gm < M && gk < kend) ? A[(long)gm * lda + gk] : zero_of<TA>();
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * kGT;
+      if (BMODE == 0) {
+        const int r = e / BK, k = e % BK;
+        const int gn = n0 + r, gk = k0 + k;
+        rb[u] = (gn < N && gk < kend) ? B[(long)gn * ldb + gk] : zero_of<TB>();
+      } else {
+        const int k = e / BN, r = e % BN;
+        const int gn = n0 + r, gk = k0 + k;
+        rb[u] = (gn < N && gk < kend) ? B[(long)gk * ldb + gn] : zero_of<TB>();
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int e = tid + u * kGT;
+      const int r = e / BK, k = e % BK;
+      As[buf][0][r * BKP + k] = static_cast<R>(ra[u].x);
+      As[buf][1][r * BKP + k] = sa * static_cast<R>(ra[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int e = tid + u * kGT;
+      int r, k;
+      if (BMODE == 0) {
+        r = e / BK;
+        k = e % BK;
+      } else {
+        k = e / BN;
+        r = e % BN;
+      }
+      Bs[buf][0][r * BKP + k] = static_cast<R>(rb[u].x);
+      Bs[buf][1][r * BKP + k] = sb * static_cast<R>(rb[u].y);
+    }
+  };
+
   const int lr = lane & 15;   // row (A) / column (B) inside a 16-block
   const int lk = lane >> 4;   // k inside a 4-step
 
+  if (kbeg < kend) {
+    gload(kbeg);
+    sstore(0);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    // ---- global -> LDS (planar re / im, K contiguous per row)
-    for (int e = tid; e < BM * BK; e += kGT) {
-      const int r = e / BK, k = e - (e / BK) * BK;
-      const int gm = m0 + r, gk = k0 + k;
-      R re, im;
-      ld_elem<R, TA>(A + (long)gm * lda + gk, gm < M && gk < kend, conjA != 0, re, im);
-      As[0][r * BKP + k] = re;
-      As[1][r * BKP + k] = im;
-    }
-    if (BMODE == 0) {
-      for (int e = tid; e < BN * BK; e += kGT) {
-        const int r = e / BK, k = e - (e / BK) * BK;
-        const int gn = n0 + r, gk = k0 + k;
-        R re, im;
-        ld_elem<R, TB>(B + (long)gn * ldb + gk, gn < N && gk < kend, conjB != 0, re, im);
-        Bs[0][r * BKP + k] = re;
-        Bs[1][r * BKP + k] = im;
-      }
-    } else {
-      for (int e = tid; e < BN * BK; e += kGT) {
-        const int k = e / BN, r = e - (e / BN) * BN;
-        const int gn = n0 + r, gk = k0 + k;
-        R re, im;
-        ld_elem<R, TB>(B + (long)gk * ldb + gn, gn < N && gk < kend, conjB != 0, re, im);
-        Bs[0][r * BKP + k] = re;
-        Bs[1][r * BKP + k] = im;
-      }
-    }
-    __syncthreads();
-    // ---- MFMA over the staged K slice
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       R ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int off = (wm0 + i * 16 + lr) * BKP + kk + lk;
-        ar[i] = As[0][off];
-        ai[i] = As[1][off];
+        ar[i] = As[buf][0][off];
+        ai[i] = As[buf][1][off];
         nai[i] = -ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int off = (wn0 + j * 16 + lr) * BKP + kk + lk;
-        br[j] = Bs[0][off];
-        bi[j] = Bs[1][off];
+        br[j] = Bs[buf][0][off];
+        bi[j] = Bs[buf][1][off];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -141,7 +184,9 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
           mfma(ai[i], br[j], acc_i[i][j]);
         }
     }
+    if (more) sstore(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
 
   // ---- epilogue.  Column lane%16 of each 16x16 block; accumulator entry r
@@ -175,9 +220,8 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
       }
 }
 
-template <typename R, typename TA, typename TB, typename TC, int BMODE>
-hipError_t run(const GemmDesc &g, hipStream_t s) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
+hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
   dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nsplit);
   const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
   hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK>), grid, dim3(kGT), 0, s,
@@ -187,18 +231,47 @@ hipError_t run(const GemmDesc &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <typename R, typename TA, typename TB, typename TC>
-hipError_t run_b(const GemmDesc &g, hipStream_t s) {
-  return g.bmode == 0 ? run<R, TA, TB, TC, 0>(g, s) : run<R, TA, TB, TC, 1>(g, s);
+// FP64: 64 x 64 tiles, K slices of 8.  FP32: 128 x 64 tiles (a whole band
+// block shares one read of the projector table) unless M <= 64.
+template <typename TA, typename TC, int BMODE>
+hipError_t run_f32(const GemmDesc &g, hipStream_t s) {
+  if (g.M > 64) return run_tile<float, TA, float2, TC, BMODE, 128, 64, 16>(g, s);
+  return run_tile<float, TA, float2, TC, BMODE, 64, 64, 16>(g, s);
 }
 
-template <typename R, typename TA, typename TB>
-hipError_t run_c(const GemmDesc &g, hipStream_t s) {
-  return g.tc == T_D2 ? run_b<R, TA, TB, double2>(g, s) : run_b<R, TA, TB, float2>(g, s);
+template <typename TA, typename TC> hipError_t run_f32_b(const GemmDesc &g, hipStream_t s) {
+  return g.bmode == 0 ? run_f32<TA, TC, 0>(g, s) : run_f32<TA, TC, 1>(g, s);
 }
 
-template <typename R, typename TA> hipError_t run_bt(const GemmDesc &g, hipStream_t s) {
-  return g.tb == T_D2 ? run_c<R, TA, double2>(g, s) : run_c<R, TA, float2>(g, s);
+template <typename TA> hipError_t run_f32_c(const GemmDesc &g, hipStream_t s) {
+  return g.tc == T_D2 ? run_f32_b<TA, double2>(g, s) : run_f32_b<TA, float2>(g, s);
+}
+
+template <typename TP, typename TC>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP *__restrict__ part,
+                                                            long stride, int nsplit, int M, int N,
+                                                            long ldp, TC *__restrict__ C, long ldc,
+                                                            int accumulate) {
+  const long total = (long)M * N;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
+       t += (long)gridDim.x * blockDim.x) {
+    const int m = (int)(t / N), n = (int)(t % N);
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      const TP v = part[(long)s * stride + (long)m * ldp + n];
+      sr += static_cast<double>(v.x);
+      si += static_cast<double>(v.y);
+    }
+    TC *p = C + (long)m * ldc + n;
+    if (accumulate) {
+      sr += static_cast<double>(p->x);
+      si += static_cast<double>(p->y);
+    }
+    TC o;
+    o.x = static_cast<typename real_of<TC>::type>(sr);
+    o.y = static_cast<typename real_of<TC>::type>(si);
+    *p = o;
+  }
 }
 
 // ---------------------------------------------------------------- D scaling
@@ -246,9 +319,27 @@ hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
   if (g.prec == G_F64) {
     if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
-    return run_b<double, double2, double2, double2>(g, s);
+    return g.bmode == 0 ? run_tile<double, double2, double2, double2, 0, 64, 64, 8>(g, s)
+                        : run_tile<double, double2, double2, double2, 1, 64, 64, 8>(g, s);
   }
-  return g.ta == T_D2 ? run_bt<float, double2>(g, s) : run_bt<float, float2>(g, s);
+  if (g.tb != T_F2) return hipErrorInvalidValue;
+  return g.ta == T_D2 ? run_f32_c<double2>(g, s) : run_f32_c<float2>(g, s);
+}
+
+hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nsplit, int M, int N,
+                                long ldp, double2 *C, long ldc, int accumulate, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const long total = (long)M * N;
+  const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+  if (tp == T_D2)
+    hipLaunchKernelGGL((splitk_reduce_kernel<double2, double2>), dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const double2 *>(part), stride, nsplit, M, N, ldp, C, ldc,
+                       accumulate);
+  else
+    hipLaunchKernelGGL((splitk_reduce_kernel<float2, double2>), dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const float2 *>(part), stride, nsplit, M, N, ldp, C, ldc,
+                       accumulate);
+  return hipGetLastError();
 }
 
 hipError_t launch_dscale(const qeh_ctx *c, int nbk) {

@@ -127,6 +127,9 @@ struct GemmDesc {
   int prec;
 };
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
+// C[m][n] (+)= sum_s part[s*stride + m*ldp + n], summed in double in split order.
+hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nsplit, int M, int N,
+                                long ldp, double2 *C, long ldc, int accumulate, hipStream_t s);
 
 // Sum split-K partials (double2 or float2 partials, double accumulation) and
 // apply the block-diagonal D: ps[b][i] = sum_j D_ij sum_s part[s][b][j].
@@ -152,6 +155,8 @@ hipError_t launch_set_diag(double2 *M, long ld, int n, const double *d, hipStrea
 // dst (n x n, ldd) = (src + src^H)/2 (src n x n, lds), col-major.
 hipError_t launch_hermitise_copy(const double2 *src, long lds, double2 *dst, long ldd, int n,
                                  hipStream_t s);
+// p[0..n) = v (a kernel, not a memset, so the call can sit in captured graphs)
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
 // finite check: flag[0] |= any non-finite in x[0..n) (doubles)
 hipError_t launch_check_finite(const double *x, long n, int *flag, hipStream_t s);
 

@@ -1,0 +1,146 @@
+"""The C-ABI library without a GPU: it loads, exports every function that
+include/qeh.h declares, the binding's structs match the header's layout (a
+gcc-compiled probe prints sizeof/offsetof), and host-side validation in
+qeh_ctx_plan (which makes no device call) rejects malformed cells with the
+documented status codes.
+"""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import cellgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qeh.h")
+
+
+def _q():
+    import paper_2104_10502_amd as q
+    return q
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(qeh_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    q = _q()
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(q.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) <= set(q.exported_symbols())
+
+
+def test_struct_layout_matches_header(tmp_path):
+    q = _q()
+    probe = tmp_path / "probe.c"
+    probe.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "qeh.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell), offsetof(qeh_cell, npw),
+         offsetof(qeh_cell, miller), offsetof(qeh_cell, beta), offsetof(qeh_cell, block),
+         sizeof(qeh_dav_opts), sizeof(qeh_dav_info));
+  return 0;
+}
+''')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(probe), "-o", str(exe)],
+                   check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    C = q.QehCell
+    assert vals == [ctypes.sizeof(C), C.npw.offset, C.miller.offset, C.beta.offset,
+                    C.block.offset, ctypes.sizeof(q.DavOpts), ctypes.sizeof(q.DavInfo)]
+
+
+def _plan(cell, **kw):
+    q = _q()
+    miller = np.ascontiguousarray(kw.get("miller", cell.miller), dtype=np.int32)
+    vloc = np.ascontiguousarray(kw.get("vloc", cell.vloc), dtype=np.float64)
+    nproj = np.ascontiguousarray(cell.nproj, dtype=np.int32)
+    beta = np.ascontiguousarray(cell.beta, dtype=np.complex128)
+    dmat = np.ascontiguousarray(cell.dmat, dtype=np.complex128)
+    c = q.QehCell()
+    c.lattice[:] = list(np.asarray(cell.lattice).ravel())
+    c.fft[:] = list(kw.get("fft", cell.fft))
+    c.kpt[:] = list(cell.kpt)
+    c.npw = miller.shape[0]
+    c.miller = miller.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    c.vloc = vloc.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.nat = nproj.shape[0]
+    c.nproj = nproj.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+    c.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.dmat = dmat.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.precision = kw.get("precision", 0)
+    c.block = kw.get("block", 16)
+    n = ctypes.c_size_t()
+    st = q._lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(n))
+    return st, n.value, q._lib.qeh_last_error().decode()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return cellgen.make_cell("c1")
+
+
+def test_plan_ok(c1):
+    st, n, _ = _plan(c1)
+    assert st == 0 and n > 16 * c1.npw * c1.nkb
+    st32, n32, _ = _plan(c1, precision=1)
+    assert st32 == 0 and n32 < n
+
+
+def test_plan_rejects_unsorted_miller(c1):
+    m = c1.miller.copy()
+    m[[3, 4]] = m[[4, 3]]
+    st, _, msg = _plan(c1, miller=m)
+    assert st == -1 and "lexicographic" in msg
+
+
+def test_plan_rejects_gap_in_stick(c1):
+    m = c1.miller
+    # an element whose neighbours on both sides belong to the same (h, k) stick
+    same = (m[1:-1, :2] == m[:-2, :2]).all(1) & (m[1:-1, :2] == m[2:, :2]).all(1)
+    g = 1 + int(np.nonzero(same)[0][0])
+    m = np.delete(m, g, axis=0)
+    st, _, msg = _plan(c1, miller=m)
+    assert st == -1 and "contiguous" in msg
+
+
+def test_plan_rejects_box_too_small(c1):
+    st, _, msg = _plan(c1, fft=(12, 30, 30), vloc=np.zeros((30, 30, 12)))
+    assert st == -1 and "box" in msg
+
+
+def test_plan_rejects_prime_11(c1):
+    st, _, msg = _plan(c1, fft=(33, 30, 30), vloc=np.zeros((30, 30, 33)))
+    assert st == -1 and "prime" in msg
+
+
+def test_plan_rejects_nonfinite_vloc(c1):
+    v = c1.vloc.copy()
+    v[1, 2, 3] = np.nan
+    st, _, msg = _plan(c1, vloc=v)
+    assert st == -3
+
+
+def test_plan_rejects_bad_block_and_precision(c1):
+    assert _plan(c1, block=0)[0] == -1
+    assert _plan(c1, precision=7)[0] == -1
+
+
+def test_status_strings():
+    q = _q()
+    for s in range(-8, 1):
+        assert q._lib.qeh_status_str(s)

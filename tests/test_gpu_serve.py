@@ -1,0 +1,95 @@
+"""GPU request server (qeh_submit / qeh_poll through the C ABI).
+
+* Each request's eigenvalues are identical (bitwise) whether it runs alone or
+  among other requests that overlap it on the device, and they match LAPACK's
+  dense eigensolver on the oracle's H within the mixed-form bar (1e-6 Ry).
+* Admission by footprint: a request larger than the whole arena is rejected
+  at submit; requests that do not fit together wait and still finish.
+* A queued request can be cancelled.
+"""
+
+import time
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import cellgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _q():
+    import paper_2104_10502_amd as q
+    return q
+
+
+def _req(nat, ecut, nk, seed):
+    cells = [cellgen.random_served_cell(nat, ecut, k, seed) for k in range(nk)]
+    psi = [cellgen.make_psi0(c.npw, c.nbnd, seed=10502 + k) for k, c in enumerate(cells)]
+    return cells, psi
+
+
+def _wait(srv, tickets, timeout=240):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            r = srv.poll(t)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "server did not finish in time"
+        time.sleep(0.002)
+    return out
+
+
+def test_alone_equals_mix_and_lapack():
+    q = _q()
+    reqs = [_req(8, 20.0, 2, 101), _req(12, 25.0, 1, 102), _req(10, 30.0, 3, 103),
+            _req(9, 20.0, 1, 104)]
+    kw = dict(precision=q.QEH_MIXED, nvecx=0, rtol=1e-8)
+    srv = q.Server(2 << 30, max_slots=8)
+    alone = []
+    for cells, psi in reqs:
+        t = srv.submit(cells, psi, cells[0].nbnd, **kw)
+        r = _wait(srv, [t])[t]
+        assert r["status"] == 0, r["error"]
+        alone.append(r["eig"])
+    ts = [srv.submit(cells, psi, cells[0].nbnd, **kw) for cells, psi in reqs]
+    res = _wait(srv, ts)
+    st = srv.stats()
+    print("server stats", st, flush=True)
+    assert st["peak_running"] >= 2
+    for (cells, _), a, t in zip(reqs, alone, ts):
+        assert res[t]["status"] == 0
+        assert np.array_equal(res[t]["eig"], a)
+        # and the values are right: k-point 0 against LAPACK
+        c = cells[0]
+        ref = sla.eigh(oracle.dense_h(c), eigvals_only=True, subset_by_index=[0, c.nbnd - 1])
+        assert np.abs(a[0] - ref).max() < 1e-6
+    srv.close()
+
+
+def test_admission_reject_wait_cancel():
+    q = _q()
+    cells, psi = _req(8, 20.0, 1, 201)
+    small = q.Server(64 << 20, max_slots=2)
+    big_cells, big_psi = _req(40, 30.0, 1, 202)
+    with pytest.raises(q.QehError) as ei:
+        small.submit(big_cells, big_psi, big_cells[0].nbnd)
+    assert ei.value.status == q.QEH_ERR_REJECTED
+    # three requests, two slots: the third waits, all finish
+    ts = [small.submit(cells, psi, cells[0].nbnd) for _ in range(3)]
+    t_extra = small.submit(cells, psi, cells[0].nbnd)
+    assert small.cancel(t_extra) in (0, q.QEH_ERR_BUSY)
+    res = _wait(small, ts)
+    for t in ts:
+        assert res[t]["status"] == 0
+        a, s, b, f = res[t]["stamps"]
+        assert a <= s <= b <= f
+    assert all(np.array_equal(res[ts[0]]["eig"], res[t]["eig"]) for t in ts)
+    small.close()
