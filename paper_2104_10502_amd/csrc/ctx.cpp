@@ -38,6 +38,15 @@ static qeh_status invalid(const std::string &m) {
   return QEH_ERR_INVALID;
 }
 
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  f.s = 0;
+  while ((1ull << f.s) < d) ++f.s;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << f.s) - d)) / d + 1);
+  return f;
+}
+
 bool make_fft_dim(int n, FftDim *d) {
   if (n < 1 || n > 1024) return false;
   int e[8] = {0};
@@ -75,6 +84,8 @@ bool make_fft_dim(int n, FftDim *d) {
   for (int p = 0; p < d->npass; ++p) {
     d->radix[p] = rad[p];
     d->span[p] = span;
+    d->nbf_div[p] = make_fastdiv(n / rad[p]);
+    d->span_div[p] = make_fastdiv(span);
     span *= rad[p];
   }
   return span == n;
@@ -188,7 +199,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 
 // Arena layout, shared by plan and create.
 struct Layout {
-  size_t off_stick_off, off_gmap, off_tidx, off_xpos, off_kin, off_hdiag, off_vs, off_tw,
+  size_t off_stick_off, off_gmap, off_tidx, off_xin, off_kin, off_hdiag, off_vs, off_tw,
       off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part, off_ps;
   size_t total;
 };
@@ -225,19 +236,29 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
   S = std::max(1, std::min(64, S));
   g->sg.S = S;
   g->sg.lds_bytes = stick_lds_bytes(prec, n3, g->sg);
+  g->sg.s_div = make_fastdiv(S);
+  g->sg.slast_div = make_fastdiv(hm.nst % S ? hm.nst % S : S);
   // plane: x-extent columns of odd stride + a few full rows
   g->pg.ldT = n2 | 1;
   g->pg.ldR = n1 | 1;
   g->plane_path = 1;
-  for (int rc = std::min(n2, 8); rc >= 1; rc = rc / 2) {
-    g->pg.rc = rc;
-    g->pg.lds_bytes = plane_lds_bytes(prec, hm.ext, n1, n2, g->pg);
-    if (g->pg.lds_bytes <= (size_t)kLdsMax) {
-      g->plane_path = 0;
-      break;
+  // rows per chunk: as many as fit in 80 KB (two workgroups per CU) keeping at
+  // least min(N2, 16) rows, else as many as fit in the whole LDS
+  const int rmin = std::min(n2, 16);
+  for (int pass = 0; pass < 2 && g->plane_path; ++pass) {
+    const size_t cap = pass == 0 ? (size_t)80 * 1024 : (size_t)kLdsMax;
+    for (int rc = n2; rc >= (pass == 0 ? rmin : 1); --rc) {
+      g->pg.rc = rc;
+      g->pg.lds_bytes = plane_lds_bytes(prec, hm.ext, n1, n2, g->pg);
+      if (g->pg.lds_bytes <= cap) {
+        g->plane_path = 0;
+        break;
+      }
     }
-    if (rc == 1) break;
   }
+  g->pg.ext_div = make_fastdiv(hm.ext);
+  g->pg.rc_div = make_fastdiv(g->pg.rc);
+  g->pg.rlast_div = make_fastdiv(n2 % g->pg.rc ? n2 % g->pg.rc : g->pg.rc);
   // D-scaling chunks: whole atoms, <= 256 projectors each
   g->nchunk = 0;
   {
@@ -274,7 +295,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   L.off_stick_off = bump(&cur, 4 * (hm.nst + 1));
   L.off_gmap = bump(&cur, 4 * (size_t)c->npw);
   L.off_tidx = bump(&cur, 4 * (size_t)hm.nst);
-  L.off_xpos = bump(&cur, 4 * (size_t)hm.ext);
+  L.off_xin = bump(&cur, 4 * (size_t)c->fft[0]);
   L.off_kin = bump(&cur, 8 * (size_t)c->npw);
   L.off_hdiag = bump(&cur, 8 * (size_t)c->npw);
   L.off_vs = bump(&cur, rs * nfft);
@@ -394,7 +415,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.stick_off = reinterpret_cast<int *>(A + L.off_stick_off);
   c->d.gmap = reinterpret_cast<int *>(A + L.off_gmap);
   c->d.tidx = reinterpret_cast<int *>(A + L.off_tidx);
-  c->d.xpos = reinterpret_cast<int *>(A + L.off_xpos);
+  c->d.xin = reinterpret_cast<int *>(A + L.off_xin);
   c->d.kin = reinterpret_cast<double *>(A + L.off_kin);
   c->d.hdiag = reinterpret_cast<double *>(A + L.off_hdiag);
   c->d.vs = A + L.off_vs;
@@ -413,13 +434,13 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   const size_t nfft = (size_t)n1 * n2 * n3;
   const bool f64 = c->prec == QEH_FP64;
   // ---- host-side maps
-  std::vector<int> gmap(npw), tidx(hm.nst), xpos(hm.ext);
+  std::vector<int> gmap(npw), tidx(hm.nst), xin(n1, -1);
   for (int s = 0; s < hm.nst; ++s) {
     for (int gg = hm.stick_off[s]; gg < hm.stick_off[s + 1]; ++gg)
       gmap[gg] = s * c->sg.ldz + fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3));
     tidx[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, imod(hm.stick_k[s], n2));
   }
-  for (int cc = 0; cc < hm.ext; ++cc) xpos[cc] = fft_digit_pos(c->dx, imod(hm.hmin + cc, n1));
+  for (int cc = 0; cc < hm.ext; ++cc) xin[fft_digit_pos(c->dx, imod(hm.hmin + cc, n1))] = cc;
   double b[9];
   reciprocal(cell->lattice, b);
   std::vector<double> kin(npw), hdiag(npw);
@@ -497,7 +518,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   up(c->d.stick_off, hm.stick_off.data(), 4 * hm.stick_off.size());
   up(c->d.gmap, gmap.data(), 4 * gmap.size());
   up(c->d.tidx, tidx.data(), 4 * tidx.size());
-  up(c->d.xpos, xpos.data(), 4 * xpos.size());
+  up(c->d.xin, xin.data(), 4 * xin.size());
   up(c->d.kin, kin.data(), 8 * kin.size());
   up(c->d.hdiag, hdiag.data(), 8 * hdiag.size());
   up(c->d.pj0, pj0.data(), 4 * pj0.size());

@@ -112,12 +112,31 @@ __global__ void check_finite_kernel(const double *x, long n, int *flag) {
   if (bad) flag[0] = 1;   // plain store: any writer sets the same value
 }
 
+// From M (lower triangle valid, col-major ld): L = tril(M), LH = L^H.
+__global__ void tril_and_adjoint_kernel(const double2 *M, double2 *L, double2 *LH, long ld,
+                                        int n) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double2 a = i >= j ? M[i + (long)j * ld] : make_double2(0.0, 0.0);
+    L[i + (long)j * ld] = a;
+    LH[j + (long)i * ld] = make_double2(a.x, -a.y);
+  }
+}
+
 __global__ void fill_int_kernel(int *p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 }  // namespace
+
+hipError_t launch_tril_adjoint(const double2 *M, double2 *L, double2 *LH, long ld, int n,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(tril_and_adjoint_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, M, L,
+                     LH, ld, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s) {
   if (n <= 0) return hipSuccess;

@@ -62,8 +62,10 @@ qeh_status solver_bytes(int n, size_t *out) {
     return QEH_ERR_DEVICE;
   }
   rocblas_start_device_memory_size_query(h);
-  rocsolver_zhegvd(h, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, n, nullptr,
-                   n, nullptr, n, nullptr, nullptr, nullptr);
+  rocsolver_zpotrf(h, rocblas_fill_lower, n, nullptr, n, nullptr);
+  rocsolver_ztrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
+  rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
+                   nullptr);
   size_t sz = 0;
   rocblas_stop_device_memory_size_query(h, &sz);
   rocblas_destroy_handle(h);
@@ -115,6 +117,55 @@ hipError_t reduce_cols(const qeh_ctx *c, const double2 *X, int nrow, const doubl
   if (e != hipSuccess) return e;
   return launch_splitk_reduce(part, T_D2, (long)ncol * nrow, ns, ncol, nrow, nrow, out, ld, 0,
                               c->stream);
+}
+
+// Column-major products of n x n matrices (ld): out = P Q with P given by
+// its columns: out(i,j) = sum_k P(i,k) Q(k,j).  In the GEMM's row-major view
+// out^T[j][i] = sum_k Q^T[j][k] P^T... -> A = Q (element (j,k) at Q[j*ld+k]),
+// B(k,i) = P(i,k) at P[k*ld+i].
+hipError_t square_product(const qeh_ctx *c, const double2 *Qm, const double2 *Pm, double2 *out,
+                          int n, int ld) {
+  GemmDesc g{};
+  g.A = Qm;
+  g.lda = ld;
+  g.ta = T_D2;
+  g.B = Pm;
+  g.ldb = ld;
+  g.tb = T_D2;
+  g.bmode = 1;
+  g.C = out;
+  g.ldc = ld;
+  g.tc = T_D2;
+  g.M = n;
+  g.N = n;
+  g.K = n;
+  g.nsplit = 1;
+  g.kchunk = n;
+  g.prec = G_F64;
+  return launch_cgemm(g, c->stream);
+}
+
+// out(:, 0:ncol) = P Q(:, 0:ncol), P n x n, Q n x ncol (column-major, ld).
+hipError_t square_product_cols(const qeh_ctx *c, const double2 *Qm, const double2 *Pm,
+                               double2 *out, int n, int ncol, int ld) {
+  GemmDesc g{};
+  g.A = Qm;
+  g.lda = ld;
+  g.ta = T_D2;
+  g.B = Pm;
+  g.ldb = ld;
+  g.tb = T_D2;
+  g.bmode = 1;
+  g.C = out;
+  g.ldc = ld;
+  g.tc = T_D2;
+  g.M = ncol;
+  g.N = n;
+  g.K = n;
+  g.nsplit = 1;
+  g.kchunk = n;
+  g.prec = G_F64;
+  return launch_cgemm(g, c->stream);
 }
 
 // rows b < nb: out_b = sum_j Y(j, b) X_j  (Y col-major ld, j < n)
@@ -203,12 +254,16 @@ qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
   L->Sr = bump2(&cur, mat);
   L->Hw = bump2(&cur, mat);
   L->Sw = bump2(&cur, mat);
+  L->X = bump2(&cur, mat);
+  L->Lc = bump2(&cur, mat);
+  L->LcH = bump2(&cur, mat);
+  L->Y = bump2(&cur, mat);
   L->part = bump2(&cur, 16 * (size_t)kMaxSplit * nb * nvecx);
   L->eps = bump2(&cur, 8 * (size_t)nvecx);
   L->E = bump2(&cur, 8 * (size_t)nvecx);
   L->norms = bump2(&cur, 8 * (size_t)nb);
   L->idx = bump2(&cur, 4 * (size_t)nb);
-  L->info = bump2(&cur, 4);
+  L->info = bump2(&cur, 16);
   L->flag = bump2(&cur, 4);
   qeh_status st = solver_bytes(nvecx, &L->solver_bytes);
   if (st != QEH_OK) return st;
@@ -260,6 +315,10 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   Hw_ = reinterpret_cast<double2 *>(w + L_.Hw);
   Sw_ = reinterpret_cast<double2 *>(w + L_.Sw);
   part_ = reinterpret_cast<double2 *>(w + L_.part);
+  X_ = reinterpret_cast<double2 *>(w + L_.X);
+  Lc_ = reinterpret_cast<double2 *>(w + L_.Lc);
+  LcH_ = reinterpret_cast<double2 *>(w + L_.LcH);
+  Y_ = reinterpret_cast<double2 *>(w + L_.Y);
   eps_d_ = reinterpret_cast<double *>(w + L_.eps);
   E_d_ = reinterpret_cast<double *>(w + L_.E);
   norms_d_ = reinterpret_cast<double *>(w + L_.norms);
@@ -268,7 +327,7 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   flag_d_ = reinterpret_cast<int *>(w + L_.flag);
   // pinned host readback: eps, norms (nb doubles each), idx (nb ints), 2 ints
   void *h = nullptr;
-  const size_t hb = 16 * (size_t)nb + 4 * (size_t)nb + 16;
+  const size_t hb = 16 * (size_t)nb + 4 * (size_t)nb + 32;
   hipError_t e = hipHostMalloc(&h, hb, hipHostMallocDefault);
   if (e != hipSuccess) return hip_fail(e, "pinned host buffer");
   h_eps_ = reinterpret_cast<double *>(h);
@@ -356,27 +415,61 @@ bool DavRun::advance() {
         break;
       }
       case kRR: {
+        // Hr y = eps Sr y: Sr = L L^H (Cholesky; its status is checked on the
+        // host before anything consumes L), A = L^-1 Hr L^-H (two MFMA
+        // products with the explicit inverse), A z = eps z (Hermitian
+        // eigensolver), y = L^-H z (one more product).
         ++it_;
         ev_s_.start(s);
-        ok(launch_hermitise_copy(Hr_, nvecx, Hw_, nvecx, nbase_, s));
-        ok(launch_hermitise_copy(Sr_, nvecx, Sw_, nvecx, nbase_, s));
-        rocblas_status rs = rocsolver_zhegvd(
-            rh_, rocblas_eform_ax, rocblas_evect_original, rocblas_fill_upper, nbase_,
-            reinterpret_cast<rocblas_double_complex *>(Hw_), nvecx,
-            reinterpret_cast<rocblas_double_complex *>(Sw_), nvecx, eps_d_, E_d_, info_d_);
+        const int n = nbase_;
+        ok(launch_hermitise_copy(Hr_, nvecx, Hw_, nvecx, n, s));
+        ok(launch_hermitise_copy(Sr_, nvecx, Sw_, nvecx, n, s));
+        rocblas_status rs = rocsolver_zpotrf(rh_, rocblas_fill_lower, n,
+                                             reinterpret_cast<rocblas_double_complex *>(Sw_),
+                                             nvecx, info_d_ + 1);
         ev_s_.stop(s);
         if (rs != rocblas_status_success) {
-          set_error("rocsolver_zhegvd failed to launch");
+          set_error("rocsolver_zpotrf failed to launch");
           result_ = QEH_ERR_DEVICE;
           phase_ = kDone;
           return true;
         }
-        ok(hipMemcpyAsync(h_int_ + 1, info_d_, 4, hipMemcpyDeviceToHost, s));
+        h_int_[2] = h_int_[3] = 0;
+        ok(hipMemcpyAsync(h_int_ + 1, info_d_ + 1, 4, hipMemcpyDeviceToHost, s));
+        phase_ = kRRSolve;
+        return false;
+      }
+      case kRRSolve: {
+        if (h_int_[1] != 0) {   // not positive definite: handled in kRRCheck
+          phase_ = kRRCheck;
+          break;
+        }
+        const int n = nbase_;
+        ev_s_.start(s);
+        rocblas_status rs = rocsolver_ztrtri(rh_, rocblas_fill_lower, rocblas_diagonal_non_unit,
+                                             n, reinterpret_cast<rocblas_double_complex *>(Sw_),
+                                             nvecx, info_d_ + 2);
+        ok(launch_tril_adjoint(Sw_, Lc_, LcH_, nvecx, n, s));
+        ok(square_product(c_, Hw_, Lc_, X_, n, nvecx));     // X = L^-1 Hr
+        ok(square_product(c_, LcH_, X_, Hw_, n, nvecx));    // A = X L^-H
+        if (rs == rocblas_status_success)
+          rs = rocsolver_zheevd(rh_, rocblas_evect_original, rocblas_fill_upper, n,
+                                reinterpret_cast<rocblas_double_complex *>(Hw_), nvecx, eps_d_,
+                                E_d_, info_d_ + 3);
+        ok(square_product_cols(c_, Hw_, LcH_, Y_, n, nb, nvecx));   // Y = L^-H Z
+        ev_s_.stop(s);
+        if (rs != rocblas_status_success) {
+          set_error("rocSOLVER call failed to launch");
+          result_ = QEH_ERR_DEVICE;
+          phase_ = kDone;
+          return true;
+        }
+        ok(hipMemcpyAsync(h_int_ + 2, info_d_ + 2, 8, hipMemcpyDeviceToHost, s));
         phase_ = kRRCheck;
         return false;
       }
       case kRRCheck: {
-        if (h_int_[1] != 0) {
+        if (h_int_[1] != 0 || h_int_[2] != 0 || h_int_[3] != 0) {
           // reduced overlap not positive definite (or solver failure)
           if (chol_prev_ || !have_ritz_) {
             set_error("reduced overlap matrix not positive definite");
@@ -402,8 +495,8 @@ bool DavRun::advance() {
         }
         chol_prev_ = false;
         ev_s_.start(s);
-        ok(rotate(c_, Hw_, nvecx, nbase_, nb, V_, P_));
-        ok(rotate(c_, Hw_, nvecx, nbase_, nb, W_, Q_));
+        ok(rotate(c_, Y_, nvecx, nbase_, nb, V_, P_));
+        ok(rotate(c_, Y_, nvecx, nbase_, nb, W_, Q_));
         ok(launch_resid_norms(P_, Q_, npw, npw, nb, eps_d_, norms_d_, s));
         ev_s_.stop(s);
         have_ritz_ = true;

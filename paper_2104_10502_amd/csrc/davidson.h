@@ -15,7 +15,8 @@
 namespace qeh {
 
 struct DavLayout {
-  size_t V, W, P, Q, Hr, Sr, Hw, Sw, part, eps, E, norms, idx, info, flag, solver;
+  size_t V, W, P, Q, Hr, Sr, Hw, Sw, X, Lc, LcH, Y, part, eps, E, norms, idx, info, flag,
+      solver;
   size_t solver_bytes;
   size_t total;
 };
@@ -48,7 +49,7 @@ class DavRun {
   ~DavRun() { release(); }
 
  private:
-  enum Phase { kStart, kCheckInput, kRR, kRRCheck, kConverge, kFinish, kDone };
+  enum Phase { kStart, kCheckInput, kRR, kRRSolve, kRRCheck, kConverge, kFinish, kDone };
   qeh_status hpsi(const double2 *x, double2 *y, int n);
   void ok(hipError_t e) {
     if (err_ == hipSuccess) err_ = e;
@@ -64,11 +65,12 @@ class DavRun {
   DavLayout L_{};
   double2 *V_ = nullptr, *W_ = nullptr, *P_ = nullptr, *Q_ = nullptr;
   double2 *Hr_ = nullptr, *Sr_ = nullptr, *Hw_ = nullptr, *Sw_ = nullptr, *part_ = nullptr;
+  double2 *X_ = nullptr, *Lc_ = nullptr, *LcH_ = nullptr, *Y_ = nullptr;
   double *eps_d_ = nullptr, *E_d_ = nullptr, *norms_d_ = nullptr;
   int *idx_d_ = nullptr, *info_d_ = nullptr, *flag_d_ = nullptr;
   // pinned host mirrors of the per-iteration readback
   double *h_eps_ = nullptr, *h_nrm_ = nullptr;
-  int *h_idx_ = nullptr, *h_int_ = nullptr;   // h_int_[0] flag, [1] solver info
+  int *h_idx_ = nullptr, *h_int_ = nullptr;   // [0] flag, [1..3] potrf/trtri/heevd info
   std::vector<double> eps_prev_;
   rocblas_handle rh_ = nullptr;
   EvPool ev_h_, ev_s_;

@@ -24,16 +24,30 @@ namespace {
 // ---------------------------------------------------------------- passes
 // tw[t] = exp(-2 pi i t / n); the inverse uses the conjugate.
 
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+  return (__umulhi(n, f.m) + n) >> f.s;
+}
+
 template <typename C, int R, bool INV, bool DIT>
-__device__ __forceinline__ void radix_pass(C *buf, int nlines, int ld, int n, int L,
-                                           const C *tw, int tid, int nthr) {
+__device__ __forceinline__ void radix_pass(C *buf, const FastDiv &lines, int ld, int n, int L,
+                                           const FastDiv &nbfd, const FastDiv &Ld, const C *tw,
+                                           int tid, int nthr) {
+  const int nlines = (int)lines.d;
   const int nbf = n / R;
   const int total = nlines * nbf;
   const int tstep = n / (L * R);
   for (int t = tid; t < total; t += nthr) {
-    const int line = t / nbf;
-    const int u = t - line * nbf;
-    const int blk = u / L;
+    // L == 1: neighbouring threads take neighbouring lines (odd line stride,
+    // no LDS bank conflicts); otherwise neighbouring j within a line.
+    int line, u;
+    if (L == 1) {
+      u = (int)fdiv(t, lines);
+      line = t - u * nlines;
+    } else {
+      line = (int)fdiv(t, nbfd);
+      u = t - line * nbf;
+    }
+    const int blk = (int)fdiv(u, Ld);
     const int j = u - blk * L;
     C *p = buf + line * ld + blk * (L * R) + j;
     C v[R];
@@ -62,35 +76,40 @@ __device__ __forceinline__ void radix_pass(C *buf, int nlines, int ld, int n, in
 }
 
 template <typename C, bool INV, bool DIT>
-__device__ __forceinline__ void one_pass(C *buf, int nlines, int ld, int n, int R, int L,
-                                         const C *tw, int tid, int nthr) {
-  switch (R) {
-    case 2: radix_pass<C, 2, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
-    case 3: radix_pass<C, 3, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
-    case 4: radix_pass<C, 4, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
-    case 5: radix_pass<C, 5, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
-    case 7: radix_pass<C, 7, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
-    case 8: radix_pass<C, 8, INV, DIT>(buf, nlines, ld, n, L, tw, tid, nthr); break;
+__device__ __forceinline__ void one_pass(C *buf, const FastDiv &lines, int ld, const FftDim &d,
+                                         int p, const C *tw, int tid, int nthr) {
+  const int n = d.n, L = d.span[p];
+#define QEH_PASS(RR)                                                                     \
+  radix_pass<C, RR, INV, DIT>(buf, lines, ld, n, L, d.nbf_div[p], d.span_div[p], tw, tid, \
+                              nthr)
+  switch (d.radix[p]) {
+    case 2: QEH_PASS(2); break;
+    case 3: QEH_PASS(3); break;
+    case 4: QEH_PASS(4); break;
+    case 5: QEH_PASS(5); break;
+    case 7: QEH_PASS(7); break;
+    case 8: QEH_PASS(8); break;
     default: break;
   }
+#undef QEH_PASS
 }
 
-// Inverse transform of nlines lines (stride ld), digit-reversed in, natural out.
+// Inverse transform of the lines (stride ld), digit-reversed in, natural out.
 template <typename C>
-__device__ void fft_inv_dit(C *buf, int nlines, int ld, const FftDim &d, const C *tw,
+__device__ void fft_inv_dit(C *buf, const FastDiv &lines, int ld, const FftDim &d, const C *tw,
                             int tid, int nthr) {
   for (int p = 0; p < d.npass; ++p) {
-    one_pass<C, true, true>(buf, nlines, ld, d.n, d.radix[p], d.span[p], tw, tid, nthr);
+    one_pass<C, true, true>(buf, lines, ld, d, p, tw, tid, nthr);
     __syncthreads();
   }
 }
 
 // Forward transform, natural in, digit-reversed out.
 template <typename C>
-__device__ void fft_fwd_dif(C *buf, int nlines, int ld, const FftDim &d, const C *tw,
+__device__ void fft_fwd_dif(C *buf, const FastDiv &lines, int ld, const FftDim &d, const C *tw,
                             int tid, int nthr) {
   for (int p = d.npass - 1; p >= 0; --p) {
-    one_pass<C, false, false>(buf, nlines, ld, d.n, d.radix[p], d.span[p], tw, tid, nthr);
+    one_pass<C, false, false>(buf, lines, ld, d, p, tw, tid, nthr);
     __syncthreads();
   }
 }
@@ -105,7 +124,8 @@ template <typename C>
 __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
     const double2 *__restrict__ psi, int ldpsi, C *__restrict__ sbuf,
     const int *__restrict__ stick_off, const int *__restrict__ gmap,
-    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz) {
+    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, FastDiv sdiv,
+    FastDiv slast) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tile = reinterpret_cast<C *>(smem_raw);
   C *tw = tile + S * ldz;
@@ -123,7 +143,7 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
   const int base = s0 * ldz;
   for (int g = g0 + tid; g < g1; g += kNT) tile[gmap[g] - base] = ccast<C>(pb[g]);
   __syncthreads();
-  fft_inv_dit<C>(tile, ns, ldz, dz, tw, tid, kNT);
+  fft_inv_dit<C>(tile, ns == S ? sdiv : slast, ldz, dz, tw, tid, kNT);
   C *out = sbuf + (size_t)b * n3 * nst + s0;
   for (int i = tid; i < ns * n3; i += kNT) {
     const int z = i / ns;
@@ -138,7 +158,8 @@ __global__ __launch_bounds__(kNT) void k3_zfwd_gather(
     const C *__restrict__ sbuf, const double2 *__restrict__ psi, int ldpsi,
     double2 *__restrict__ hpsi, int ldh, const double *__restrict__ kin,
     const int *__restrict__ stick_off, const int *__restrict__ gmap,
-    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, int add_kin) {
+    const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, int add_kin, FastDiv sdiv,
+    FastDiv slast) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tile = reinterpret_cast<C *>(smem_raw);
   C *tw = tile + S * ldz;
@@ -155,7 +176,7 @@ __global__ __launch_bounds__(kNT) void k3_zfwd_gather(
     tile[s * ldz + z] = in[(size_t)z * nst + s];
   }
   __syncthreads();
-  fft_fwd_dif<C>(tile, ns, ldz, dz, tw, tid, kNT);
+  fft_fwd_dif<C>(tile, ns == S ? sdiv : slast, ldz, dz, tw, tid, kNT);
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
   const int base = s0 * ldz;
   const double2 *pb = psi + (size_t)b * ldpsi;
@@ -173,26 +194,158 @@ __global__ __launch_bounds__(kNT) void k3_zfwd_gather(
 }
 
 // ---------------------------------------------------------------- K2
+// Row operations of the plane pass.  A row line (length n = N1) lives in RB;
+// the first inverse pass reads its input straight from the column tile T
+// (xin[p] = column whose h-index sits at DIT input position p, or -1 for a
+// zero), the last inverse pass is fused with the V multiply and the first
+// forward pass (both touch the same R positions), and the last forward pass
+// writes the x-extent outputs straight back into T.
+template <typename C, int R, bool DIT, bool DIF, bool IN_T, bool OUT_T>
+__device__ __forceinline__ void row_op(C *RB, int ldR, C *T, int ldT, int y0,
+                                       const FastDiv &rows, const int *xin, int n, int L,
+                                       const FastDiv &nbfd, const FastDiv &Ld, const C *tw,
+                                       const typename real_of<C>::type *vrow, int tid,
+                                       int nthr) {
+  const int nr = (int)rows.d;
+  const int nbf = n / R;
+  const int total = nr * nbf;
+  const int tstep = n / (L * R);
+  const C zero = cmk<C>(0, 0);
+  for (int t = tid; t < total; t += nthr) {
+    int r, u;
+    if (L == 1) {
+      u = (int)fdiv(t, rows);
+      r = t - u * nr;
+    } else {
+      r = (int)fdiv(t, nbfd);
+      u = t - r * nbf;
+    }
+    const int blk = (int)fdiv(u, Ld);
+    const int j = u - blk * L;
+    const int p0 = blk * (L * R) + j;
+    C v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int pos = p0 + q * L;
+      if (IN_T) {
+        const int c = xin[pos];
+        v[q] = c >= 0 ? T[c * ldT + y0 + r] : zero;
+      } else {
+        v[q] = RB[r * ldR + pos];
+      }
+    }
+    if (DIT) {
+      if (L > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) {
+          C w = tw[q * j * tstep];
+          w.y = -w.y;
+          v[q] = cmul(v[q], w);
+        }
+      }
+      dftR<C, R, true>(v);
+    }
+    if (DIT && DIF) {
+      // natural x order here: multiply by V(r)/N of this row
+#pragma unroll
+      for (int q = 0; q < R; ++q) v[q] = cscale(v[q], vrow[r * n + p0 + q * L]);
+    }
+    if (DIF) {
+      dftR<C, R, false>(v);
+      if (L > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) v[q] = cmul(v[q], tw[q * j * tstep]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int pos = p0 + q * L;
+      if (OUT_T) {
+        const int c = xin[pos];
+        if (c >= 0) T[c * ldT + y0 + r] = v[q];
+      } else {
+        RB[r * ldR + pos] = v[q];
+      }
+    }
+  }
+}
+
+template <typename C, bool DIT, bool DIF, bool IN_T, bool OUT_T>
+__device__ __forceinline__ void row_op_r(const FftDim &d, int p, C *RB, int ldR, C *T, int ldT,
+                                         int y0, const FastDiv &rows, const int *xin,
+                                         const C *tw, const typename real_of<C>::type *vrow,
+                                         int tid, int nthr) {
+#define QEH_ROW(RR)                                                                        \
+  row_op<C, RR, DIT, DIF, IN_T, OUT_T>(RB, ldR, T, ldT, y0, rows, xin, d.n, d.span[p],    \
+                                       d.nbf_div[p], d.span_div[p], tw, vrow, tid, nthr)
+  switch (d.radix[p]) {
+    case 2: QEH_ROW(2); break;
+    case 3: QEH_ROW(3); break;
+    case 4: QEH_ROW(4); break;
+    case 5: QEH_ROW(5); break;
+    case 7: QEH_ROW(7); break;
+    case 8: QEH_ROW(8); break;
+    default: break;
+  }
+#undef QEH_ROW
+}
+
+// Rows y0 .. y0+nr of the plane: x inverse, V multiply, x forward, in place
+// on the column tile T.  Ends with a barrier.
+template <typename C>
+__device__ void row_phase(C *RB, int ldR, C *T, int ldT, int y0, const FastDiv &rows,
+                          const int *xin, const FftDim &d, const C *tw,
+                          const typename real_of<C>::type *vrow, int tid, int nthr) {
+  const int m = d.npass;
+  if (m == 1) {
+    row_op_r<C, true, true, true, true>(d, 0, RB, ldR, T, ldT, y0, rows, xin, tw, vrow, tid,
+                                        nthr);
+    __syncthreads();
+    return;
+  }
+  row_op_r<C, true, false, true, false>(d, 0, RB, ldR, T, ldT, y0, rows, xin, tw, vrow, tid,
+                                        nthr);
+  __syncthreads();
+  for (int p = 1; p < m - 1; ++p) {
+    row_op_r<C, true, false, false, false>(d, p, RB, ldR, T, ldT, y0, rows, xin, tw, vrow, tid,
+                                           nthr);
+    __syncthreads();
+  }
+  row_op_r<C, true, true, false, false>(d, m - 1, RB, ldR, T, ldT, y0, rows, xin, tw, vrow,
+                                        tid, nthr);
+  __syncthreads();
+  for (int p = m - 2; p >= 1; --p) {
+    row_op_r<C, false, true, false, false>(d, p, RB, ldR, T, ldT, y0, rows, xin, tw, vrow, tid,
+                                           nthr);
+    __syncthreads();
+  }
+  row_op_r<C, false, true, false, true>(d, 0, RB, ldR, T, ldT, y0, rows, xin, tw, vrow, tid,
+                                        nthr);
+  __syncthreads();
+}
+
 // One workgroup: one z-plane of one band.  T holds the x-extent columns of the
 // plane (column c = h - hmin, y along the column); rc rows at a time are
 // expanded to full x lines in RB for the x transforms and the V multiply.
 // Workgroup ids are remapped so that each XCD (ids are dealt round-robin to
 // the 8 XCDs) walks a contiguous range of (z, band) with band fastest: the
 // bands of one plane share that plane's V in the XCD's L2.
+constexpr int kPT = 512;   // plane workgroup: 8 waves
+
 template <typename C>
-__global__ __launch_bounds__(kNT) void k2_plane(
+__global__ __launch_bounds__(kPT) void k2_plane(
     C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
-    const int *__restrict__ tidx, const int *__restrict__ xpos_g,
+    const int *__restrict__ tidx, const int *__restrict__ xin_g,
     const C *__restrict__ twx_g, const C *__restrict__ twy_g, FftDim dx, FftDim dy,
-    int nst, int n3, int ext, int ldT, int rc, int ldR, int nbk, int per_xcd) {
-  using R = typename real_of<C>::type;
+    int nst, int n3, int ext, int ldT, int rc, int ldR, int nbk, int per_xcd, FastDiv extd,
+    FastDiv rcd, FastDiv rlastd) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int n1 = dx.n, n2 = dy.n;
   C *T = reinterpret_cast<C *>(smem_raw);
   C *RB = T + ext * ldT;
   C *twx = RB + rc * ldR;
   C *twy = twx + n1;
-  int *xp = reinterpret_cast<int *>(twy + n2);
+  int *xin = reinterpret_cast<int *>(twy + n2);
   const int id = blockIdx.x;
   const int logical = (id & 7) * per_xcd + (id >> 3);
   if (logical >= nbk * n3) return;
@@ -201,44 +354,24 @@ __global__ __launch_bounds__(kNT) void k2_plane(
   const int tid = threadIdx.x;
   const C zero = cmk<C>(0, 0);
 
-  for (int i = tid; i < ext * ldT; i += kNT) T[i] = zero;
-  for (int i = tid; i < n1; i += kNT) twx[i] = twx_g[i];
-  for (int i = tid; i < n2; i += kNT) twy[i] = twy_g[i];
-  for (int i = tid; i < ext; i += kNT) xp[i] = xpos_g[i];
+  for (int i = tid; i < ext * ldT; i += kPT) T[i] = zero;
+  for (int i = tid; i < n1; i += kPT) {
+    twx[i] = twx_g[i];
+    xin[i] = xin_g[i];
+  }
+  for (int i = tid; i < n2; i += kPT) twy[i] = twy_g[i];
   __syncthreads();
   C *plane = sbuf + ((size_t)b * n3 + z) * nst;
-  for (int s = tid; s < nst; s += kNT) T[tidx[s]] = plane[s];
+  for (int s = tid; s < nst; s += kPT) T[tidx[s]] = plane[s];
   __syncthreads();
-  fft_inv_dit<C>(T, ext, ldT, dy, twy, tid, kNT);
-
+  fft_inv_dit<C>(T, extd, ldT, dy, twy, tid, kPT);
   for (int y0 = 0; y0 < n2; y0 += rc) {
-    const int nr = min(rc, n2 - y0);
-    for (int i = tid; i < nr * ldR; i += kNT) RB[i] = zero;
-    __syncthreads();
-    for (int i = tid; i < nr * ext; i += kNT) {
-      const int r = i / ext;
-      const int c = i - r * ext;
-      RB[r * ldR + xp[c]] = T[c * ldT + y0 + r];
-    }
-    __syncthreads();
-    fft_inv_dit<C>(RB, nr, ldR, dx, twx, tid, kNT);
-    const R *vrow = vs + ((size_t)z * n2 + y0) * n1;
-    for (int i = tid; i < nr * n1; i += kNT) {
-      const int r = i / n1;
-      const int x = i - r * n1;
-      RB[r * ldR + x] = cscale(RB[r * ldR + x], vrow[i]);
-    }
-    __syncthreads();
-    fft_fwd_dif<C>(RB, nr, ldR, dx, twx, tid, kNT);
-    for (int i = tid; i < nr * ext; i += kNT) {
-      const int r = i / ext;
-      const int c = i - r * ext;
-      T[c * ldT + y0 + r] = RB[r * ldR + xp[c]];
-    }
-    __syncthreads();
+    const FastDiv &rows = (y0 + rc <= n2) ? rcd : rlastd;
+    row_phase<C>(RB, ldR, T, ldT, y0, rows, xin, dx, twx, vs + ((size_t)z * n2 + y0) * n1, tid,
+                 kPT);
   }
-  fft_fwd_dif<C>(T, ext, ldT, dy, twy, tid, kNT);
-  for (int s = tid; s < nst; s += kNT) plane[s] = T[tidx[s]];
+  fft_fwd_dif<C>(T, extd, ldT, dy, twy, tid, kPT);
+  for (int s = tid; s < nst; s += kPT) plane[s] = T[tidx[s]];
 }
 
 template <typename K> void allow_lds(K kern, size_t bytes) {
@@ -254,7 +387,7 @@ hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
   allow_lds(k1_scatter_zinv<C>, c->sg.lds_bytes);
   hipLaunchKernelGGL(k1_scatter_zinv<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream, psi,
                      ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
-                     c->dz, c->nst, c->sg.S, c->sg.ldz);
+                     c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div);
   return hipGetLastError();
 }
 
@@ -266,7 +399,8 @@ hipError_t k3_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, dou
   allow_lds(k3_zfwd_gather<C>, c->sg.lds_bytes);
   hipLaunchKernelGGL(k3_zfwd_gather<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream,
                      reinterpret_cast<const C *>(c->d.sbuf), psi, ldpsi, hpsi, ldh, c->d.kin,
-                     c->d.stick_off, c->d.gmap, tw, c->dz, c->nst, c->sg.S, c->sg.ldz, add_kin);
+                     c->d.stick_off, c->d.gmap, tw, c->dz, c->nst, c->sg.S, c->sg.ldz, add_kin,
+                     c->sg.s_div, c->sg.slast_div);
   return hipGetLastError();
 }
 
@@ -276,10 +410,11 @@ template <typename C> hipError_t k2_impl(const qeh_ctx *c, int nbk) {
   const int total = nbk * c->n3;
   const int per_xcd = (total + 7) / 8;
   allow_lds(k2_plane<C>, c->pg.lds_bytes);
-  hipLaunchKernelGGL(k2_plane<C>, dim3(8 * per_xcd), dim3(kNT), c->pg.lds_bytes, c->stream,
+  hipLaunchKernelGGL(k2_plane<C>, dim3(8 * per_xcd), dim3(kPT), c->pg.lds_bytes, c->stream,
                      reinterpret_cast<C *>(c->d.sbuf), reinterpret_cast<const R *>(c->d.vs),
-                     c->d.tidx, c->d.xpos, tw + c->tw_off[0], tw + c->tw_off[1], c->dx, c->dy,
-                     c->nst, c->n3, c->ext, c->pg.ldT, c->pg.rc, c->pg.ldR, nbk, per_xcd);
+                     c->d.tidx, c->d.xin, tw + c->tw_off[0], tw + c->tw_off[1], c->dx, c->dy,
+                     c->nst, c->n3, c->ext, c->pg.ldT, c->pg.rc, c->pg.ldR, nbk, per_xcd,
+                     c->pg.ext_div, c->pg.rc_div, c->pg.rlast_div);
   return hipGetLastError();
 }
 
@@ -287,7 +422,7 @@ template <typename C> hipError_t k2_impl(const qeh_ctx *c, int nbk) {
 
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
   const size_t c = prec == QEH_FP64 ? 16 : 8;
-  return c * ((size_t)ext * g.ldT + (size_t)g.rc * g.ldR + n1 + n2) + 4 * (size_t)ext;
+  return c * ((size_t)ext * g.ldT + (size_t)g.rc * g.ldR + n1 + n2) + 4 * (size_t)n1;
 }
 
 size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {

@@ -13,9 +13,16 @@
 
 namespace qeh {
 
-constexpr int kMaxPass = 12;
+constexpr int kMaxPass = 8;
 constexpr size_t kAlign = 256;
 constexpr int kLdsMax = 160 * 1024;   // LDS per workgroup on gfx950
+
+// Division by a fixed divisor d as q = (umulhi(n, m) + n) >> s, exact for
+// n < 2^31 (round-up multiplier); built on the host, used in kernel index math.
+struct FastDiv {
+  uint32_t m, s, d;
+};
+FastDiv make_fastdiv(uint32_t d);
 
 // One 1D mixed-radix transform of length n = prod radix[p].  Pass p combines
 // radix[p] sub-transforms of length span[p] (span[0] = 1).  The decimation-
@@ -26,6 +33,8 @@ struct FftDim {
   int npass;
   int radix[kMaxPass];
   int span[kMaxPass];
+  FastDiv nbf_div[kMaxPass];    // n / radix[p]
+  FastDiv span_div[kMaxPass];   // span[p]
 };
 
 bool make_fft_dim(int n, FftDim *d);
@@ -38,12 +47,14 @@ struct PlaneGeom {
   int rc;    // rows processed together in the row phase
   int ldR;   // row stride of the row buffer (>= N1, odd)
   size_t lds_bytes;
+  FastDiv ext_div, rc_div, rlast_div;   // ext, rc, rows of the last chunk
 };
 
 struct StickGeom {
   int ldz;   // z-line stride (>= N3, odd)
   int S;     // sticks per workgroup
   size_t lds_bytes;
+  FastDiv s_div, slast_div;   // S, sticks of the last workgroup
 };
 
 // Device arrays of one context, all inside the caller's arena.
@@ -51,7 +62,7 @@ struct DevMaps {
   int *stick_off;    // [nst+1] first G of each stick
   int *gmap;         // [npw] s*ldz + digit-reversed z position
   int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2)
-  int *xpos;         // [ext] digit-reversed x position of column c
+  int *xin;          // [N1] column c whose h sits at x-DIT input position p, or -1
   double *kin;       // [npw] |k+G|^2
   double *hdiag;     // [npw] diag(H)
   void *vs;          // [N3][N2][N1] V/N (double or float)
@@ -155,6 +166,9 @@ hipError_t launch_set_diag(double2 *M, long ld, int n, const double *d, hipStrea
 // dst (n x n, ldd) = (src + src^H)/2 (src n x n, lds), col-major.
 hipError_t launch_hermitise_copy(const double2 *src, long lds, double2 *dst, long ldd, int n,
                                  hipStream_t s);
+// L = lower triangle of M (zeros above), LH = L^H; all n x n col-major, ld.
+hipError_t launch_tril_adjoint(const double2 *M, double2 *L, double2 *LH, long ld, int n,
+                               hipStream_t s);
 // p[0..n) = v (a kernel, not a memset, so the call can sit in captured graphs)
 hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s);
 // finite check: flag[0] |= any non-finite in x[0..n) (doubles)

@@ -77,8 +77,8 @@ def test_alone_equals_mix_and_lapack():
 def test_admission_reject_wait_cancel():
     q = _q()
     cells, psi = _req(8, 20.0, 1, 201)
-    small = q.Server(64 << 20, max_slots=2)
-    big_cells, big_psi = _req(40, 30.0, 1, 202)
+    small = q.Server(24 << 20, max_slots=2)
+    big_cells, big_psi = _req(64, 30.0, 1, 202)     # Davidson basis alone > 24 MiB
     with pytest.raises(q.QehError) as ei:
         small.submit(big_cells, big_psi, big_cells[0].nbnd)
     assert ei.value.status == q.QEH_ERR_REJECTED
