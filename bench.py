@@ -13,7 +13,8 @@ stream during the timed steps; ``roofline`` reports the dominant kernel.
 ``cpu_baseline`` times the FP64 oracle's H|psi> on a bounded band sample on
 the host cores.  Davidson time-to-solution is reported when --davidson is set.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--davidson] [--no-cpu]
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--davidson] [--serve SECONDS]
+                      [--no-cpu]
 """
 
 from __future__ import annotations
@@ -121,6 +122,79 @@ def cpu_baseline(cell, budget_s=12.0):
                        "cell, %.1f s" % (done, dt))
 
 
+def _make_request(r):
+    import cellgen
+    cells = [cellgen.random_served_cell(r["nat"], r["ecutwfc"], k, r["seed"]) for k in range(r["nk"])]
+    psis = [cellgen.make_psi0(c.npw, c.nbnd, seed=10502 + k) for k, c in enumerate(cells)]
+    return cells, psis
+
+
+def make_trace(duration, rate, seed=2104):
+    """Generate the served requests (host only; called before any GPU use, in a
+    pool of spawned processes)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import cellgen
+    trace = [r for r in cellgen.served_trace(int(rate * duration * 2) + 10, rate=rate, seed=seed)
+             if r["t_arrive"] <= duration]
+    t_gen = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4),
+                                mp_context=mp.get_context("spawn")) as ex:
+        reqs = list(ex.map(_make_request, trace, chunksize=4))
+    return trace, reqs, time.perf_counter() - t_gen
+
+
+def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
+    """Replay a Poisson trace of Davidson requests (random cubic cells, 8-128 atoms,
+    ecutwfc in {20,25,30} Ry, 1-4 k-points, nb = 2 nat, mixed form) against the server."""
+    srv = q.Server(int(arena_gib) << 30, max_slots=slots)
+    # warm-up request (kernel loading, solver workspace queries), not measured
+    w = _make_request(dict(nat=8, ecutwfc=20.0, nk=1, seed=1))
+    tw = srv.submit(w[0], w[1], w[0][0].nbnd, precision=q.QEH_MIXED)
+    while srv.poll(tw) is None:
+        time.sleep(0.01)
+    t0 = time.perf_counter()
+    lag = 0.0
+    tickets = []
+    for r, (cells, psis) in zip(trace, reqs):
+        delay = r["t_arrive"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        else:
+            lag = max(lag, -delay)
+        tickets.append(srv.submit(cells, psis, cells[0].nbnd, precision=q.QEH_MIXED))
+    res = {}
+    while len(res) < len(tickets):
+        for t in tickets:
+            if t not in res:
+                o = srv.poll(t)
+                if o is not None:
+                    res[t] = o
+        time.sleep(0.005)
+    st = srv.stats()
+    srv.close()
+    out = [res[t] for t in tickets]
+    bad = sum(1 for o in out if o["status"] != 0)
+    errors = sorted({"%d: %s" % (o["status"], o["error"]) for o in out if o["status"] != 0})
+    lat = np.array([o["stamps"][3] - o["stamps"][0] for o in out])
+    queue = np.array([o["stamps"][1] - o["stamps"][0] for o in out])
+    arrive = min(o["stamps"][0] for o in out)
+    finish = max(o["stamps"][3] for o in out)
+    span = finish - arrive
+    kpts = sum(len(o["eig"]) for o in out)
+    run = sum(o["stamps"][3] - o["stamps"][2] for o in out)
+    return dict(requests=len(out), failed=bad, errors=errors[:5], rate_offered=rate,
+                duration_s=duration,
+                p50_latency_s=float(np.percentile(lat, 50)),
+                p99_latency_s=float(np.percentile(lat, 99)),
+                p50_queue_s=float(np.percentile(queue, 50)),
+                solves_per_s=len(out) / span, kpoint_solves_per_s=kpts / span,
+                mean_running_requests=run / span, peak_running_jobs=st["peak_running"],
+                gpu_busy_fraction=st["busy_s"] / max(st["uptime_s"], 1e-9),
+                max_submit_lag_s=lag, slots=slots, arena_gib=arena_gib,
+                generation_s=t_gen)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,11 +202,21 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve", type=float, default=0.0,
+                    help="seconds of the served Poisson trace to replay (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.serve > 0:
+        # one hardware queue per few job streams, so that a long dense eigensolve
+        # on one stream does not hold up the jobs sharing its queue (HIP reads
+        # this at initialisation; <= 32)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+    served = make_trace(a.serve, a.serve_rate) if a.serve > 0 else None
     import torch
     import cellgen
     import paper_2104_10502_amd as q
@@ -194,6 +278,10 @@ def main():
                 eig_min=float(eig[0]), eig_max=float(eig[-1]))
             ctx.close()
         out["davidson"] = dav
+    if a.serve > 0:
+        out["serve"] = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate,
+                                   slots=a.serve_slots)
+        print("# serve: %s" % json.dumps(out["serve"]), file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cell)
     print(json.dumps(out))

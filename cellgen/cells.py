@@ -151,9 +151,14 @@ def vloc_fourier(lattice, fft, positions) -> np.ndarray:
     g = (m1[..., None] * b[0] + m2[..., None] * b[1] + m3[..., None] * b[2])
     g2 = np.einsum("...i,...i->...", g, g)
     vt = VLOC_AMP * (TWO_PI * VLOC_WIDTH ** 2) ** 1.5 * np.exp(-0.5 * g2 * VLOC_WIDTH ** 2)
-    s = np.zeros(g2.shape, dtype=np.complex128)
-    for tau in positions:
-        s += np.exp(-1j * (g @ tau))
+    # structure factor S(G) = sum_a exp(-i G.tau_a), G.tau = sum_i m_i (b_i.tau):
+    # separable per axis, so S = sum_a e3[a,m3] e2[a,m2] e1[a,m1] (one contraction)
+    pos = np.asarray(positions, dtype=np.float64)
+    e1 = np.exp(-1j * np.outer(pos @ b[0], f1))     # (nat, n1)
+    e2 = np.exp(-1j * np.outer(pos @ b[1], f2))
+    e3 = np.exp(-1j * np.outer(pos @ b[2], f3))
+    e21 = (e2[:, :, None] * e1[:, None, :]).reshape(pos.shape[0], -1)
+    s = (e3.T @ e21).reshape(n3, n2, n1)
     c = vt * s / omega
     v = np.fft.ifftn(c) * (n1 * n2 * n3)
     return np.ascontiguousarray(v.real)

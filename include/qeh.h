@@ -202,7 +202,10 @@ qeh_status qeh_server_stats(qeh_server *srv, double *out, int n);
 qeh_status qeh_server_destroy(qeh_server *srv);
 
 /* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
- * precision, plane path (0 fused in one kernel, 1 split through HBM)]. */
+ * precision, plane path (0 fused in one kernel, 1 split through HBM)].
+ * The plane path is chosen by LDS fit; the environment variable
+ * QEH_FORCE_SPLIT_PLANE=1, read by qeh_ctx_plan / qeh_ctx_create, forces the
+ * split path (a test hook). */
 qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);
 
 const char *qeh_status_str(qeh_status s);

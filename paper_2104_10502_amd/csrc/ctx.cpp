@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -200,7 +201,8 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 // Arena layout, shared by plan and create.
 struct Layout {
   size_t off_stick_off, off_gmap, off_tidx, off_xin, off_kin, off_hdiag, off_vs, off_tw,
-      off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part, off_ps;
+      off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part, off_ps,
+      off_big, off_colstart;
   size_t total;
 };
 
@@ -214,6 +216,7 @@ struct Geometry {
   int nkb, nd, nchunk, nsplit, kchunk, plane_path;
   FftDim dx, dy, dz;
   PlaneGeom pg;
+  SplitGeom spg;
   StickGeom sg;
 };
 
@@ -255,6 +258,23 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
         break;
       }
     }
+  }
+  // split path geometry (used when the column tile does not fit in LDS)
+  {
+    SplitGeom &q = g->spg;
+    q.cg = std::min(16, hm.ext);
+    q.rg = std::min(16, n2);
+    q.ldl = q.rg | 1;
+    q.lds_col = cs * ((size_t)q.cg * g->pg.ldT + n2);
+    q.lds_row = cs * ((size_t)hm.ext * q.ldl + (size_t)q.rg * g->pg.ldR + n1) + 4 * (size_t)n1;
+    q.cg_div = make_fastdiv(q.cg);
+    q.cglast_div = make_fastdiv(hm.ext % q.cg ? hm.ext % q.cg : q.cg);
+    q.rg_div = make_fastdiv(q.rg);
+    q.rglast_div = make_fastdiv(n2 % q.rg ? n2 % q.rg : q.rg);
+    // test hook: QEH_FORCE_SPLIT_PLANE=1 sends every plane through the split path
+    const char *force = std::getenv("QEH_FORCE_SPLIT_PLANE");
+    if (force && force[0] == '1') g->plane_path = 1;
+    if (g->plane_path == 1) g->pg.rc = 1;   // unused by the split path
   }
   g->pg.ext_div = make_fastdiv(hm.ext);
   g->pg.rc_div = make_fastdiv(g->pg.rc);
@@ -309,6 +329,10 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   L.off_sbuf = bump(&cur, cs * (size_t)c->block * c->fft[2] * hm.nst);
   L.off_part = bump(&cur, cs * (size_t)g.nsplit * c->block * g.nkb);
   L.off_ps = bump(&cur, cs * (size_t)c->block * g.nkb);
+  L.off_big = bump(&cur, g.plane_path == 1 ? cs * (size_t)c->block * c->fft[2] * hm.ext *
+                                               c->fft[1]
+                                         : 0);
+  L.off_colstart = bump(&cur, 4 * (size_t)(hm.ext + 1));
   L.total = cur;
   return L;
 }
@@ -362,8 +386,8 @@ qeh_status qeh_ctx_plan(const qeh_cell *cell, size_t *arena_bytes) {
   if (st != QEH_OK) return st;
   Geometry g;
   geometry(cell, hm, &g);
-  if (g.plane_path != 0)
-    return invalid("FFT plane does not fit in LDS for this precision (split plane path not available)");
+  if (g.plane_path != 0 && (g.spg.lds_col > (size_t)kLdsMax || g.spg.lds_row > (size_t)kLdsMax))
+    return invalid("FFT plane too large for both plane paths");
   *arena_bytes = layout(cell, hm, g).total;
   return QEH_OK;
 }
@@ -377,8 +401,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   if (st != QEH_OK) return st;
   Geometry g;
   geometry(cell, hm, &g);
-  if (g.plane_path != 0)
-    return invalid("FFT plane does not fit in LDS for this precision (split plane path not available)");
+  if (g.plane_path != 0 && (g.spg.lds_col > (size_t)kLdsMax || g.spg.lds_row > (size_t)kLdsMax))
+    return invalid("FFT plane too large for both plane paths");
   Layout L = layout(cell, hm, g);
   if (!arena) return invalid("arena is null");
   if (reinterpret_cast<uintptr_t>(arena) % kAlign) return invalid("arena not 256-byte aligned");
@@ -407,6 +431,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->dy = g.dy;
   c->dz = g.dz;
   c->pg = g.pg;
+  c->spg = g.spg;
   c->sg = g.sg;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->arena = reinterpret_cast<char *>(arena);
@@ -429,6 +454,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.sbuf = A + L.off_sbuf;
   c->d.part = A + L.off_part;
   c->d.ps = A + L.off_ps;
+  c->d.big = g.plane_path == 1 ? A + L.off_big : nullptr;
+  c->d.colstart = reinterpret_cast<int *>(A + L.off_colstart);
 
   const int npw = cell->npw, n1 = c->n1, n2 = c->n2, n3 = c->n3;
   const size_t nfft = (size_t)n1 * n2 * n3;
@@ -441,6 +468,9 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
     tidx[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, imod(hm.stick_k[s], n2));
   }
   for (int cc = 0; cc < hm.ext; ++cc) xin[fft_digit_pos(c->dx, imod(hm.hmin + cc, n1))] = cc;
+  std::vector<int> colstart(hm.ext + 1, hm.nst);
+  for (int s2 = hm.nst - 1; s2 >= 0; --s2) colstart[hm.stick_h[s2] - hm.hmin] = s2;
+  for (int cc = hm.ext - 1; cc >= 0; --cc) colstart[cc] = std::min(colstart[cc], colstart[cc + 1]);
   double b[9];
   reciprocal(cell->lattice, b);
   std::vector<double> kin(npw), hdiag(npw);
@@ -519,6 +549,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   up(c->d.gmap, gmap.data(), 4 * gmap.size());
   up(c->d.tidx, tidx.data(), 4 * tidx.size());
   up(c->d.xin, xin.data(), 4 * xin.size());
+  up(c->d.colstart, colstart.data(), 4 * colstart.size());
   up(c->d.kin, kin.data(), 8 * kin.size());
   up(c->d.hdiag, hdiag.data(), 8 * hdiag.size());
   up(c->d.pj0, pj0.data(), 4 * pj0.size());

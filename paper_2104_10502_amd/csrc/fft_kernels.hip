@@ -374,6 +374,105 @@ __global__ __launch_bounds__(kPT) void k2_plane(
   for (int s = tid; s < nst; s += kPT) plane[s] = T[tidx[s]];
 }
 
+// ---------------------------------------------------------------- K2, split
+// Planes whose column tile does not fit in LDS go through an HBM scratch
+// big[b][z][c][y] (one x-extent column of N2 values after another):
+//   k2a: a group of columns of one plane: sticks -> inverse y transforms -> big
+//   k2b: a group of rows of one plane: big -> x inverse, V, x forward -> big
+//   k2c: a group of columns: big -> forward y transforms -> sticks
+// The transforms are the same device routines as in the fused kernel.
+template <typename C>
+__global__ __launch_bounds__(kNT) void k2a_columns_inv(
+    const C *__restrict__ sbuf, C *__restrict__ big, const int *__restrict__ tidx,
+    const int *__restrict__ colstart, const C *__restrict__ twy_g, FftDim dy, int nst, int n3,
+    int ext, int ldT, int cg, int ngroups, FastDiv cgd, FastDiv cglast) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n2 = dy.n;
+  C *T = reinterpret_cast<C *>(smem_raw);
+  C *twy = T + cg * ldT;
+  const int g = blockIdx.x % ngroups;
+  const int bz = blockIdx.x / ngroups;   // b * n3 + z
+  const int c0 = g * cg;
+  const int nc = min(cg, ext - c0);
+  const int tid = threadIdx.x;
+  const C zero = cmk<C>(0, 0);
+  for (int i = tid; i < nc * ldT; i += kNT) T[i] = zero;
+  for (int i = tid; i < n2; i += kNT) twy[i] = twy_g[i];
+  __syncthreads();
+  const C *plane = sbuf + (size_t)bz * nst;
+  for (int s = colstart[c0] + tid; s < colstart[c0 + nc]; s += kNT)
+    T[tidx[s] - c0 * ldT] = plane[s];
+  __syncthreads();
+  fft_inv_dit<C>(T, nc == cg ? cgd : cglast, ldT, dy, twy, tid, kNT);
+  C *out = big + ((size_t)bz * ext + c0) * n2;
+  for (int i = tid; i < nc * n2; i += kNT) {
+    const int c = i / n2, y = i - (i / n2) * n2;
+    out[i] = T[c * ldT + y];
+  }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k2b_rows(
+    C *__restrict__ big, const typename real_of<C>::type *__restrict__ vs,
+    const int *__restrict__ xin_g, const C *__restrict__ twx_g, FftDim dx, int n2, int n3,
+    int ext, int rg, int ldl, int ldR, int ngroups, FastDiv rgd, FastDiv rglast) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = dx.n;
+  C *Tl = reinterpret_cast<C *>(smem_raw);
+  C *RB = Tl + ext * ldl;
+  C *twx = RB + rg * ldR;
+  int *xin = reinterpret_cast<int *>(twx + n1);
+  const int g = blockIdx.x % ngroups;
+  const int bz = blockIdx.x / ngroups;
+  const int z = bz % n3;
+  const int y0 = g * rg;
+  const int nr = min(rg, n2 - y0);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n1; i += kNT) {
+    twx[i] = twx_g[i];
+    xin[i] = xin_g[i];
+  }
+  C *col = big + (size_t)bz * ext * n2;
+  for (int i = tid; i < ext * nr; i += kNT) {
+    const int c = i / nr, r = i - (i / nr) * nr;
+    Tl[c * ldl + r] = col[(size_t)c * n2 + y0 + r];
+  }
+  __syncthreads();
+  row_phase<C>(RB, ldR, Tl, ldl, 0, nr == rg ? rgd : rglast, xin, dx, twx,
+               vs + ((size_t)z * n2 + y0) * n1, tid, kNT);
+  for (int i = tid; i < ext * nr; i += kNT) {
+    const int c = i / nr, r = i - (i / nr) * nr;
+    col[(size_t)c * n2 + y0 + r] = Tl[c * ldl + r];
+  }
+}
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k2c_columns_fwd(
+    C *__restrict__ sbuf, const C *__restrict__ big, const int *__restrict__ tidx,
+    const int *__restrict__ colstart, const C *__restrict__ twy_g, FftDim dy, int nst, int n3,
+    int ext, int ldT, int cg, int ngroups, FastDiv cgd, FastDiv cglast) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n2 = dy.n;
+  C *T = reinterpret_cast<C *>(smem_raw);
+  C *twy = T + cg * ldT;
+  const int g = blockIdx.x % ngroups;
+  const int bz = blockIdx.x / ngroups;
+  const int c0 = g * cg;
+  const int nc = min(cg, ext - c0);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < n2; i += kNT) twy[i] = twy_g[i];
+  const C *in = big + ((size_t)bz * ext + c0) * n2;
+  for (int i = tid; i < nc * n2; i += kNT) {
+    const int c = i / n2, y = i - (i / n2) * n2;
+    T[c * ldT + y] = in[i];
+  }
+  __syncthreads();
+  fft_fwd_dif<C>(T, nc == cg ? cgd : cglast, ldT, dy, twy, tid, kNT);
+  C *plane = sbuf + (size_t)bz * nst;
+  for (int s = colstart[c0] + tid; s < colstart[c0 + nc]; s += kNT)
+    plane[s] = T[tidx[s] - c0 * ldT];
+}
+
 template <typename K> void allow_lds(K kern, size_t bytes) {
   if (bytes > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -401,6 +500,34 @@ hipError_t k3_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, dou
                      reinterpret_cast<const C *>(c->d.sbuf), psi, ldpsi, hpsi, ldh, c->d.kin,
                      c->d.stick_off, c->d.gmap, tw, c->dz, c->nst, c->sg.S, c->sg.ldz, add_kin,
                      c->sg.s_div, c->sg.slast_div);
+  return hipGetLastError();
+}
+
+template <typename C> hipError_t k2_split_impl(const qeh_ctx *c, int nbk) {
+  using R = typename real_of<C>::type;
+  const C *tw = reinterpret_cast<const C *>(c->d.tw);
+  const SplitGeom &g = c->spg;
+  C *big = reinterpret_cast<C *>(c->d.big);
+  C *sb = reinterpret_cast<C *>(c->d.sbuf);
+  const int ncg = (c->ext + g.cg - 1) / g.cg;
+  const int nrg = (c->n2 + g.rg - 1) / g.rg;
+  const unsigned planes = (unsigned)nbk * c->n3;
+  allow_lds(k2a_columns_inv<C>, g.lds_col);
+  hipLaunchKernelGGL(k2a_columns_inv<C>, dim3(planes * ncg), dim3(kNT), g.lds_col, c->stream, sb,
+                     big, c->d.tidx, c->d.colstart, tw + c->tw_off[1], c->dy, c->nst, c->n3,
+                     c->ext, c->pg.ldT, g.cg, ncg, g.cg_div, g.cglast_div);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  allow_lds(k2b_rows<C>, g.lds_row);
+  hipLaunchKernelGGL(k2b_rows<C>, dim3(planes * nrg), dim3(kNT), g.lds_row, c->stream, big,
+                     reinterpret_cast<const R *>(c->d.vs), c->d.xin, tw + c->tw_off[0], c->dx,
+                     c->n2, c->n3, c->ext, g.rg, g.ldl, c->pg.ldR, nrg, g.rg_div, g.rglast_div);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  allow_lds(k2c_columns_fwd<C>, g.lds_col);
+  hipLaunchKernelGGL(k2c_columns_fwd<C>, dim3(planes * ncg), dim3(kNT), g.lds_col, c->stream, sb,
+                     big, c->d.tidx, c->d.colstart, tw + c->tw_off[1], c->dy, c->nst, c->n3,
+                     c->ext, c->pg.ldT, g.cg, ncg, g.cg_div, g.cglast_div);
   return hipGetLastError();
 }
 
@@ -436,7 +563,8 @@ hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
 }
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {
-  if (c->plane_path != 0) return hipErrorInvalidValue;
+  if (c->plane_path != 0)
+    return c->prec == QEH_FP64 ? k2_split_impl<double2>(c, nbk) : k2_split_impl<float2>(c, nbk);
   return c->prec == QEH_FP64 ? k2_impl<double2>(c, nbk) : k2_impl<float2>(c, nbk);
 }
 

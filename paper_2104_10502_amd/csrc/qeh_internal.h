@@ -50,6 +50,14 @@ struct PlaneGeom {
   FastDiv ext_div, rc_div, rlast_div;   // ext, rc, rows of the last chunk
 };
 
+// Split plane path (planes too large for LDS): column groups of cg columns,
+// row groups of rg rows (local column stride ldl).
+struct SplitGeom {
+  int cg, rg, ldl;
+  size_t lds_col, lds_row;
+  FastDiv cg_div, cglast_div, rg_div, rglast_div;
+};
+
 struct StickGeom {
   int ldz;   // z-line stride (>= N3, odd)
   int S;     // sticks per workgroup
@@ -77,6 +85,7 @@ struct DevMaps {
   void *part;        // [nsplit][block][nkb] split-K partials
   void *ps;          // [block][nkb] D * becp (working complex type)
   void *big;         // split plane path: [block][N3][ext][N2] (or null)
+  int *colstart;     // [ext+1] first stick of each x-extent column
 };
 
 }  // namespace qeh
@@ -90,6 +99,7 @@ struct qeh_ctx {
   int nchunk = 0;
   qeh::FftDim dx{}, dy{}, dz{};
   qeh::PlaneGeom pg{};
+  qeh::SplitGeom spg{};
   qeh::StickGeom sg{};
   int tw_off[3] = {0, 0, 0};
   hipStream_t stream = nullptr;

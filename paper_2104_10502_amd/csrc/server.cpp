@@ -10,10 +10,12 @@
 //   as the free arena (first-fit over an offset free list) and nk free slots
 //   allow; a request that fits may pass a head request that has waited less
 //   than kBackfillWindow seconds.
-// * Every admitted k-point (job) owns a slot = a HIP stream and drives its own
-//   DavRun state machine: advance() enqueues work up to the next host
-//   decision, an event marks that point, and the thread polls the events of
-//   all jobs, so the device interleaves kernels of every running request.
+// * Every admitted k-point (job) owns a slot = a HIP stream and a worker
+//   thread that drives its DavRun state machine (advance() enqueues work up
+//   to the next host decision, then the worker waits for its own stream).
+//   Jobs therefore never wait on each other's host-side synchronisation (the
+//   dense eigensolver synchronises its calling thread), and the device
+//   interleaves the kernels of every running request.
 // * Finished jobs release their arena range and slot immediately.
 #include <algorithm>
 #include <atomic>
@@ -66,7 +68,8 @@ struct Job {
   int slot = -1;
   qeh_ctx *ctx = nullptr;
   std::unique_ptr<DavRun> run;
-  bool waiting = false, started = false, finished = false;
+  bool started = false, finished = false, reaped = false;
+  std::thread th;
   std::vector<double> eig;
   qeh_dav_info info{};
   qeh_status st = QEH_OK;
@@ -103,7 +106,7 @@ struct qeh_server {
   std::condition_variable cv_work, cv_done;
   std::deque<qeh::Request *> queue;                       // submitted, not admitted
   std::map<uint64_t, std::unique_ptr<qeh::Request>> all;  // every live request
-  std::vector<qeh::Job *> running;                        // server-thread only
+  std::vector<qeh::Job *> running;                        // admitted, not reaped
   uint64_t next_id = 1;
   bool stop = false;
   long finished = 0;
@@ -179,7 +182,8 @@ bool try_admit(qeh_server *s, Request *r) {
 }
 
 // Set up a job on its stream: context, psi0 upload, Davidson init.
-void start_job(qeh_server *s, Job *j) {
+// Returns false (status in j->st) on failure.
+bool start_job(qeh_server *s, Job *j) {
   hipStream_t st = s->streams[j->slot];
   char *base = s->arena + j->off;
   j->started = true;
@@ -187,15 +191,13 @@ void start_job(qeh_server *s, Job *j) {
   qeh_status rc = qeh_ctx_create(&j->hc.cell, base, j->ctx_bytes, st, &j->ctx);
   if (rc != QEH_OK) {
     j->st = rc;
-    j->finished = true;
-    return;
+    return false;
   }
   double2 *psi = reinterpret_cast<double2 *>(base + j->ctx_bytes);
   hipError_t e = hipMemcpyAsync(psi, j->hc.psi0.data(), j->psi_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) {
     j->st = hip_fail(e, "psi0 upload");
-    j->finished = true;
-    return;
+    return false;
   }
   j->eig.assign(j->req->nb, 0.0);
   j->run.reset(new DavRun());
@@ -203,32 +205,16 @@ void start_job(qeh_server *s, Job *j) {
                     base + j->ctx_bytes + j->psi_bytes, j->dav_bytes);
   if (rc != QEH_OK) {
     j->st = rc;
-    j->finished = true;
-    return;
+    return false;
   }
+  std::lock_guard<std::mutex> lk(s->mu);
   if (j->req->t[2] == 0.0) j->req->t[2] = now_s(s->t0);
-}
-
-void step_job(qeh_server *s, Job *j) {
-  if (j->finished) return;
-  if (j->run->advance()) {
-    j->run->fill_info(&j->info);
-    j->st = j->run->result();
-    j->finished = true;
-    return;
-  }
-  hipError_t e = hipEventRecord(s->events[j->slot], s->streams[j->slot]);
-  if (e != hipSuccess) {
-    j->st = hip_fail(e, "event record");
-    j->finished = true;
-    return;
-  }
-  j->waiting = true;
+  return true;
 }
 
 void finish_job(qeh_server *s, Job *j) {
   // make sure nothing of this job is still in flight before its range is reused
-  (void)hipStreamSynchronize(s->streams[j->slot]);
+  if (j->slot >= 0) (void)hipStreamSynchronize(s->streams[j->slot]);
   if (j->run) j->run->release();
   j->run.reset();
   if (j->ctx) qeh_ctx_destroy(j->ctx);
@@ -241,81 +227,94 @@ void finish_job(qeh_server *s, Job *j) {
     r->st = j->st;
     r->msg = qeh_last_error();   // thread-local text of this (server) thread
   }
-  if (--r->remaining == 0) {
-    r->done = true;
-    r->t[3] = now_s(s->t0);
-    s->finished++;
-    // host copies are no longer needed
-    for (auto &jj : r->jobs) jj->hc = HostCell();
-    s->cv_done.notify_all();
+  if (--r->remaining == 0) r->t[3] = now_s(s->t0);   // results ready
+  j->finished = true;
+  s->cv_work.notify_all();
+}
+
+// Coordinator, lock held, after joining j's worker: a request becomes visible
+// to qeh_poll only once every worker thread of it has been joined.
+void reap_job(qeh_server *s, Job *j) {
+  j->reaped = true;
+  Request *r = j->req;
+  if (r->remaining != 0) return;
+  for (auto &jj : r->jobs)
+    if (!jj->reaped) return;
+  r->done = true;
+  s->finished++;
+  for (auto &jj : r->jobs) jj->hc = HostCell();   // host copies no longer needed
+  s->cv_done.notify_all();
+}
+
+// Worker thread of one job: set up, drive the Davidson state machine to the
+// end (waiting on this job's stream between steps), release.
+void job_main(qeh_server *s, Job *j) {
+  if (start_job(s, j)) {
+    hipStream_t st = s->streams[j->slot];
+    while (!j->run->advance()) {
+      hipError_t e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        j->st = hip_fail(e, "device work of a served job");
+        break;
+      }
+    }
+    if (j->st == QEH_OK) {
+      j->run->fill_info(&j->info);
+      j->st = j->run->result();
+    }
   }
+  finish_job(s, j);
 }
 
 void server_loop(qeh_server *s) {
   auto last = std::chrono::steady_clock::now();
+  std::unique_lock<std::mutex> lk(s->mu);
   while (true) {
-    std::vector<Job *> fresh;
-    {
-      std::unique_lock<std::mutex> lk(s->mu);
-      if (s->running.empty() && s->queue.empty())
-        s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-      if (s->stop && s->running.empty()) break;
-      if (!s->stop) {
-        const double t = now_s(s->t0);
-        bool head_blocked = false;
-        for (auto it = s->queue.begin(); it != s->queue.end();) {
-          Request *r = *it;
-          if (r->cancelled) {
-            it = s->queue.erase(it);
-            continue;
-          }
-          if (head_blocked && t - s->queue.front()->t[0] >= kBackfillWindow) break;
-          if (try_admit(s, r)) {
-            for (auto &j : r->jobs) fresh.push_back(j.get());
-            it = s->queue.erase(it);
-          } else {
-            if (it == s->queue.begin()) head_blocked = true;
-            ++it;
-          }
-        }
-      }
-    }
-    for (Job *j : fresh) {
-      start_job(s, j);
-      s->running.push_back(j);
-      if (!j->finished) step_job(s, j);
-    }
-    bool progressed = !fresh.empty();
-    for (Job *j : s->running) {
-      if (j->finished || !j->waiting) continue;
-      hipError_t q = hipEventQuery(s->events[j->slot]);
-      if (q == hipErrorNotReady) continue;
-      j->waiting = false;
-      progressed = true;
-      if (q != hipSuccess) {
-        j->st = hip_fail(q, "device work of a served job");
-        j->finished = true;
-        continue;
-      }
-      step_job(s, j);
-    }
+    // reap finished workers
     for (auto it = s->running.begin(); it != s->running.end();) {
-      if ((*it)->finished) {
-        finish_job(s, *it);
+      Job *j = *it;
+      if (j->finished) {
+        lk.unlock();
+        if (j->th.joinable()) j->th.join();
+        lk.lock();
+        reap_job(s, j);
         it = s->running.erase(it);
-        progressed = true;
       } else {
         ++it;
       }
     }
     const auto tn = std::chrono::steady_clock::now();
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      if (!s->running.empty()) s->busy_s += std::chrono::duration<double>(tn - last).count();
-      s->peak_running = std::max<int>(s->peak_running, (int)s->running.size());
-    }
+    if (!s->running.empty()) s->busy_s += std::chrono::duration<double>(tn - last).count();
     last = tn;
-    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    if (s->stop && s->running.empty()) break;
+    // admit: first come first served, backfill while the head is young
+    std::vector<Job *> fresh;
+    if (!s->stop) {
+      const double t = now_s(s->t0);
+      bool head_blocked = false;
+      for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Request *r = *it;
+        if (r->cancelled) {
+          it = s->queue.erase(it);
+          continue;
+        }
+        if (head_blocked && t - s->queue.front()->t[0] >= kBackfillWindow) break;
+        if (try_admit(s, r)) {
+          for (auto &j : r->jobs) fresh.push_back(j.get());
+          it = s->queue.erase(it);
+        } else {
+          if (it == s->queue.begin()) head_blocked = true;
+          ++it;
+        }
+      }
+    }
+    for (Job *j : fresh) {
+      s->running.push_back(j);
+      j->th = std::thread(job_main, s, j);
+    }
+    s->peak_running = std::max<int>(s->peak_running, (int)s->running.size());
+    // sleep until a submission or a job end; wake periodically for backfill
+    s->cv_work.wait_for(lk, std::chrono::milliseconds(5));
   }
 }
 

@@ -120,3 +120,31 @@ def test_hermiticity_and_linearity_gpu():
     assert abs(np.vdot(a[0], h[1]) - np.conj(np.vdot(a[1], h[0]))) < 1e-13
     lin = ctx.apply_h(torch.from_numpy((0.5 - 2j) * a[:1] + 3j * a[1:2]).cuda()).cpu().numpy()
     assert np.abs(lin[0] - ((0.5 - 2j) * h[0] + 3j * h[1])).max() < 1e-13 * np.abs(h).max() * 10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h_split_plane_path(prec, monkeypatch):
+    # the HBM-staged plane path (used when a plane's column tile exceeds LDS),
+    # forced on a small anisotropic cell with ragged column / row groups
+    monkeypatch.setenv("QEH_FORCE_SPLIT_PLANE", "1")
+    c = cellgen.make_cell("t", lattice=np.diag([9.0, 8.0, 9.5]), frac=np.array(
+        [[0.1, 0.2, 0.3], [0.6, 0.5, 0.9]]), kpt=(0.11, -0.07, 0.23), ecutwfc=40.0,
+        fft=(40, 35, 42), proj="s2pd", dfixed=False, nbnd=5)
+    psi = cellgen.make_psi0(c.npw, 5, seed=6)
+    got, ctx = run(c, psi, prec, 3)
+    assert ctx.info()["plane_path"] == 1 and ctx.info()["ext"] > 16
+    ref = oracle.apply_h(c, psi)
+    assert _rel_l2(got, ref).max() < (1e-12 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_apply_h_c2_bench_launch(prec):
+    # the benchmark's launch configuration: all 128 bands in one block;
+    # sampled bands against the oracle
+    c = cell("c2")
+    psi = cellgen.make_psi0(c.npw, 128, seed=10502)
+    got, _ = run(c, psi, prec, 128)
+    idx = [0, 57, 127]
+    ref = oracle.apply_h(c, psi[idx])
+    err = _rel_l2(got[idx], ref)
+    assert err.max() < (1e-12 if prec == 0 else 1e-5), err
