@@ -183,6 +183,7 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
     span = finish - arrive
     kpts = sum(len(o["eig"]) for o in out)
     run = sum(o["stamps"][3] - o["stamps"][2] for o in out)
+    iters = [i["iters"] for o in out for i in o["info"]]
     return dict(requests=len(out), failed=bad, errors=errors[:5], rate_offered=rate,
                 duration_s=duration,
                 p50_latency_s=float(np.percentile(lat, 50)),
@@ -190,6 +191,7 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
                 p50_queue_s=float(np.percentile(queue, 50)),
                 solves_per_s=len(out) / span, kpoint_solves_per_s=kpts / span,
                 mean_running_requests=run / span, peak_running_jobs=st["peak_running"],
+                mean_davidson_iters=float(np.mean(iters)), max_davidson_iters=int(max(iters)),
                 gpu_busy_fraction=st["busy_s"] / max(st["uptime_s"], 1e-9),
                 max_submit_lag_s=lag, slots=slots, arena_gib=arena_gib,
                 generation_s=t_gen)

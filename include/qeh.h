@@ -109,7 +109,9 @@ qeh_status qeh_apply_h_part(qeh_ctx *ctx, int part, int nb, const double *psi,
  * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
  * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single
  * precision limits how small the residual can get; a band also counts as
- * converged there when its Ritz value moved by <= 1e-8 Ry in one iteration. */
+ * converged there when its Ritz value moved by <= 1e-8 Ry in one iteration,
+ * or when its residual (<= 10x that threshold) has not dropped by 10% in 3
+ * iterations. */
 typedef struct {
   int nvecx;
   double rtol;

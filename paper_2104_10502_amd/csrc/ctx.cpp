@@ -202,7 +202,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 struct Layout {
   size_t off_stick_off, off_gmap, off_tidx, off_xin, off_kin, off_hdiag, off_vs, off_tw,
       off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part, off_ps,
-      off_big, off_colstart;
+      off_big, off_colstart, off_psi32;
   size_t total;
 };
 
@@ -292,13 +292,16 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
       cur += c->nproj[a];
     }
   }
-  // split-K of beta^H psi: enough workgroups to fill the chip, fixed chunks
+  // split-K of beta^H psi: enough workgroups to fill the chip (~4 per CU),
+  // fixed chunks of >= 256 plane waves.  Tiles: 128 x 64 for blocks > 64 bands
+  // in the mixed form, else 64 x 64.
   g->nsplit = 1;
   g->kchunk = c->npw;
   if (g->nkb > 0) {
-    const int tiles = ((c->block + 63) / 64) * ((g->nkb + 63) / 64);
+    const int bm = (prec == QEH_MIXED && c->block > 64) ? 128 : 64;
+    const int tiles = ((c->block + bm - 1) / bm) * ((g->nkb + 63) / 64);
     int ns = std::max(1, (1024 + tiles - 1) / tiles);
-    ns = std::min(ns, std::max(1, c->npw / 512));
+    ns = std::min(ns, std::max(1, c->npw / 256));
     int kc = (c->npw + ns - 1) / ns;
     kc = (kc + 15) / 16 * 16;
     g->kchunk = kc;
@@ -333,6 +336,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
                                                c->fft[1]
                                          : 0);
   L.off_colstart = bump(&cur, 4 * (size_t)(hm.ext + 1));
+  L.off_psi32 = bump(&cur, c->precision == QEH_MIXED ? 8 * (size_t)c->block * c->npw : 0);
   L.total = cur;
   return L;
 }
@@ -456,6 +460,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.ps = A + L.off_ps;
   c->d.big = g.plane_path == 1 ? A + L.off_big : nullptr;
   c->d.colstart = reinterpret_cast<int *>(A + L.off_colstart);
+  c->d.psi32 = c->prec == QEH_MIXED ? reinterpret_cast<float2 *>(A + L.off_psi32) : nullptr;
 
   const int npw = cell->npw, n1 = c->n1, n2 = c->n2, n3 = c->n3;
   const size_t nfft = (size_t)n1 * n2 * n3;
@@ -651,9 +656,11 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
   }
   if ((part == 1 || part == 2) && c->nkb > 0) {
     GemmDesc g1{};
-    g1.A = psi;
-    g1.lda = ldpsi;
-    g1.ta = T_D2;
+    const bool use32 = !f64 && part == 2;   // K1 has just written psi32
+    g1.A = use32 ? static_cast<const void *>(c->d.psi32) : static_cast<const void *>(psi);
+    g1.lda = use32 ? c->npw : ldpsi;
+    g1.ta = use32 ? T_F2 : T_D2;
+    g1.tile = 1;
     g1.B = c->d.beta;
     g1.ldb = c->npw;
     g1.tb = f64 ? T_D2 : T_F2;

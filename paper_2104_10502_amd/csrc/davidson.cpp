@@ -335,6 +335,8 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   h_idx_ = reinterpret_cast<int *>(h_nrm_ + nb);
   h_int_ = h_idx_ + nb;
   eps_prev_.assign(nb, INFINITY);
+  best_res_.assign(nb, INFINITY);
+  stall_.assign(nb, 0);
   if (rocblas_create_handle(&rh_) != rocblas_status_success) {
     rh_ = nullptr;
     release();
@@ -516,7 +518,17 @@ bool DavRun::advance() {
           if (!std::isfinite(r) || !std::isfinite(h_eps_[b])) finite = false;
           resid_max_ = std::max(resid_max_, r);
           bool conv = r <= thr_;
+          if (r < 0.9 * best_res_[b]) {
+            best_res_[b] = r;
+            stall_[b] = 0;
+          } else {
+            ++stall_[b];
+          }
+          // mixed form: the single-precision floor stops the residual; accept a
+          // band whose Ritz value has settled or whose small residual has not
+          // improved by 10% in 3 iterations
           if (mixed_ && std::fabs(h_eps_[b] - eps_prev_[b]) <= 1e-8) conv = true;
+          if (mixed_ && stall_[b] >= 3 && r <= 10.0 * thr_) conv = true;
           if (!conv) h_idx_[nc++] = b;
         }
         for (int b = 0; b < nb; ++b) eps_prev_[b] = h_eps_[b];

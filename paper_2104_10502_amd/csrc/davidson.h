@@ -71,7 +71,8 @@ class DavRun {
   // pinned host mirrors of the per-iteration readback
   double *h_eps_ = nullptr, *h_nrm_ = nullptr;
   int *h_idx_ = nullptr, *h_int_ = nullptr;   // [0] flag, [1..3] potrf/trtri/heevd info
-  std::vector<double> eps_prev_;
+  std::vector<double> eps_prev_, best_res_;
+  std::vector<int> stall_;
   rocblas_handle rh_ = nullptr;
   EvPool ev_h_, ev_s_;
   Phase phase_ = kStart;

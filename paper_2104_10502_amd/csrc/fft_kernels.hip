@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
     const double2 *__restrict__ psi, int ldpsi, C *__restrict__ sbuf,
     const int *__restrict__ stick_off, const int *__restrict__ gmap,
     const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, FastDiv sdiv,
-    FastDiv slast) {
+    FastDiv slast, float2 *__restrict__ psi32, int npw) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tile = reinterpret_cast<C *>(smem_raw);
   C *tw = tile + S * ldz;
@@ -141,7 +141,17 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
   const double2 *pb = psi + (size_t)b * ldpsi;
   const int base = s0 * ldz;
-  for (int g = g0 + tid; g < g1; g += kNT) tile[gmap[g] - base] = ccast<C>(pb[g]);
+  // mixed form: also leave a single-precision copy of psi for the projector GEMM
+  if (psi32) {
+    float2 *p32 = psi32 + (size_t)b * npw;
+    for (int g = g0 + tid; g < g1; g += kNT) {
+      const double2 v = pb[g];
+      tile[gmap[g] - base] = ccast<C>(v);
+      p32[g] = make_float2((float)v.x, (float)v.y);
+    }
+  } else {
+    for (int g = g0 + tid; g < g1; g += kNT) tile[gmap[g] - base] = ccast<C>(pb[g]);
+  }
   __syncthreads();
   fft_inv_dit<C>(tile, ns == S ? sdiv : slast, ldz, dz, tw, tid, kNT);
   C *out = sbuf + (size_t)b * n3 * nst + s0;
@@ -486,7 +496,8 @@ hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
   allow_lds(k1_scatter_zinv<C>, c->sg.lds_bytes);
   hipLaunchKernelGGL(k1_scatter_zinv<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream, psi,
                      ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
-                     c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div);
+                     c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div,
+                     c->prec == QEH_MIXED ? c->d.psi32 : nullptr, c->npw);
   return hipGetLastError();
 }
 

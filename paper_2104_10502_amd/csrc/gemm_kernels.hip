@@ -231,11 +231,11 @@ hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
   return hipGetLastError();
 }
 
-// FP64: 64 x 64 tiles, K slices of 8.  FP32: 128 x 64 tiles (a whole band
-// block shares one read of the projector table) unless M <= 64.
+// FP64: 64 x 64 tiles, K slices of 8.  FP32: 64 x 64 tiles, or 128 x 64
+// (a whole band block shares one read of the second operand) on request.
 template <typename TA, typename TC, int BMODE>
 hipError_t run_f32(const GemmDesc &g, hipStream_t s) {
-  if (g.M > 64) return run_tile<float, TA, float2, TC, BMODE, 128, 64, 16>(g, s);
+  if (g.tile == 1 && g.M > 64) return run_tile<float, TA, float2, TC, BMODE, 128, 64, 16>(g, s);
   return run_tile<float, TA, float2, TC, BMODE, 64, 64, 16>(g, s);
 }
 

@@ -84,6 +84,7 @@ struct DevMaps {
   void *sbuf;        // [block][N3][nst] stick buffer (working complex type)
   void *part;        // [nsplit][block][nkb] split-K partials
   void *ps;          // [block][nkb] D * becp (working complex type)
+  float2 *psi32;     // mixed form: [block][npw] single-precision copy of psi (K1)
   void *big;         // split plane path: [block][N3][ext][N2] (or null)
   int *colstart;     // [ext+1] first stick of each x-extent column
 };
@@ -146,6 +147,7 @@ struct GemmDesc {
   int conjA, conjB, accumulate;
   int nsplit, kchunk; long split_stride;
   int prec;
+  int tile;   // FP32 tiles: 0 = 64 x 64, 1 = 128 x 64
 };
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
 // C[m][n] (+)= sum_s part[s*stride + m*ldp + n], summed in double in split order.
