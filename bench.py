@@ -41,8 +41,8 @@ def algorithmic(stage, shape, prec, nb):
     npw, nst, nkb, n1, n2, n3 = (shape[k] for k in ("npw", "nst", "nkb", "n1", "n2", "n3"))
     c = 16 if prec == 0 else 8
     nfft = n1 * n2 * n3
-    if stage == "k1_scatter_zinv":   # read psi (complex128), write sticks
-        return "hbm", nb * (16 * npw + c * nst * n3 + 4 * npw)
+    if stage == "k1_scatter_zinv":   # read psi (complex128), write sticks (+ FP32 psi copy)
+        return "hbm", nb * (16 * npw + c * nst * n3 + 4 * npw + (8 * npw if prec else 0))
     if stage == "k2_plane":          # read + write sticks, V once per launch
         return "hbm", nb * 2 * c * nst * n3 + (c // 2) * nfft
     if stage == "k3_zfwd_gather":    # read sticks, psi, |k+G|^2, write H psi
@@ -54,6 +54,35 @@ def algorithmic(stage, shape, prec, nb):
     if stage == "dscale":
         return "hbm", nb * nkb * c * 2
     raise KeyError(stage)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c2_hbm_traffic.json")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources; a stored counter measurement is used only while
+    the kernels are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2104_10502_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by the copy-kernel calibration), or None if absent
+    or taken on other kernel sources."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get("%s/%s" % (kernel, "mixed" if prec else "fp64"))
+    return None if k is None else k["bytes_per_launch"]
 
 
 def time_apply(q, torch, cell, prec, nb, steps, warmup):
@@ -208,6 +237,9 @@ def main():
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (the reference "
+                         "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -261,7 +293,8 @@ def main():
                       "kernels": f64["per"]},
         "kernels": mixed["per"],
         "roofline": {"kernel": mixed["best"], "bound": b["bound"], "achieved": b["achieved"],
-                     "peak": b["peak"], "unit": b["unit"], "frac": b["frac"], "traffic": None},
+                     "peak": b["peak"], "unit": b["unit"], "frac": b["frac"],
+                     "traffic": stored_traffic(mixed["best"], q.QEH_MIXED)},
     }
     if a.davidson:
         psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
@@ -280,6 +313,13 @@ def main():
                 eig_min=float(eig[0]), eig_max=float(eig[-1]))
             ctx.close()
         out["davidson"] = dav
+    if a.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if a.serve > 0:
         out["serve"] = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate,
                                    slots=a.serve_slots)

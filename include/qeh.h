@@ -207,7 +207,8 @@ qeh_status qeh_server_destroy(qeh_server *srv);
  * precision, plane path (0 fused in one kernel, 1 split through HBM)].
  * The plane path is chosen by LDS fit; the environment variable
  * QEH_FORCE_SPLIT_PLANE=1, read by qeh_ctx_plan / qeh_ctx_create, forces the
- * split path (a test hook). */
+ * split path (a test hook); QEH_PLANE_ROWS=n caps the rows the fused plane
+ * kernel expands at once (a tuning knob; fewer rows use less LDS). */
 qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);
 
 const char *qeh_status_str(qeh_status s);

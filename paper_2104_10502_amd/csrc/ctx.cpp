@@ -276,6 +276,16 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
     if (force && force[0] == '1') g->plane_path = 1;
     if (g->plane_path == 1) g->pg.rc = 1;   // unused by the split path
   }
+  // tuning knob: QEH_PLANE_ROWS=n caps the rows per chunk of the fused plane
+  // pass (fewer rows = less LDS per workgroup = more workgroups per CU)
+  if (g->plane_path == 0) {
+    const char *rows = std::getenv("QEH_PLANE_ROWS");
+    const int cap = rows ? std::atoi(rows) : 0;
+    if (cap > 0 && cap < g->pg.rc) {
+      g->pg.rc = cap;
+      g->pg.lds_bytes = plane_lds_bytes(prec, hm.ext, n1, n2, g->pg);
+    }
+  }
   g->pg.ext_div = make_fastdiv(hm.ext);
   g->pg.rc_div = make_fastdiv(g->pg.rc);
   g->pg.rlast_div = make_fastdiv(n2 % g->pg.rc ? n2 % g->pg.rc : g->pg.rc);
