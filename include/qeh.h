@@ -204,11 +204,16 @@ qeh_status qeh_server_stats(qeh_server *srv, double *out, int n);
 qeh_status qeh_server_destroy(qeh_server *srv);
 
 /* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
- * precision, plane path (0 fused in one kernel, 1 split through HBM)].
- * The plane path is chosen by LDS fit; the environment variable
- * QEH_FORCE_SPLIT_PLANE=1, read by qeh_ctx_plan / qeh_ctx_create, forces the
- * split path (a test hook); QEH_PLANE_ROWS=n caps the rows the fused plane
- * kernel expands at once (a tuning knob; fewer rows use less LDS). */
+ * precision, plane path (0 fused in one kernel, 1 split through HBM,
+ * 2 lane-pair register kernel)].
+ * The plane path is chosen by LDS fit and box shape: the lane-pair kernel
+ * serves the mixed form when N1 = N2 is one of its compiled sizes (even,
+ * 16..90).  Environment variables read by qeh_ctx_plan / qeh_ctx_create:
+ * QEH_FORCE_SPLIT_PLANE=1 forces the split path (a test hook);
+ * QEH_PLANE_KERNEL=generic keeps the fused kernel where the lane-pair one
+ * would run (a test and comparison hook); QEH_PAIR_PLANES=n sets the bands per
+ * lane-pair workgroup (default 2); QEH_PLANE_ROWS=n caps the rows the fused
+ * plane kernel expands at once (a tuning knob; fewer rows use less LDS). */
 qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);
 
 const char *qeh_status_str(qeh_status s);

@@ -286,6 +286,24 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
       g->pg.lds_bytes = plane_lds_bytes(prec, hm.ext, n1, n2, g->pg);
     }
   }
+  // lane-pair kernel (N1 = N2 with a compiled form, single precision): pb bands
+  // of one plane per workgroup, 2 by default (QEH_PAIR_PLANES=n overrides);
+  // QEH_PLANE_KERNEL=generic keeps the fused kernel (comparison and test hook)
+  g->pg.pb = 0;
+  g->pg.lds_pair = 0;
+  if (g->plane_path == 0 && pair_plane_supported(prec, n1, n2)) {
+    const char *kern = std::getenv("QEH_PLANE_KERNEL");
+    const bool generic = kern && std::strcmp(kern, "generic") == 0;
+    const char *pbs = std::getenv("QEH_PAIR_PLANES");
+    int pb = pbs ? std::atoi(pbs) : 2;
+    pb = std::max(1, std::min(8, pb));
+    while (pb > 1 && pair_plane_lds_bytes(prec, hm.ext, n2, pb) > (size_t)kLdsMax) --pb;
+    if (!generic && pair_plane_lds_bytes(prec, hm.ext, n2, pb) <= (size_t)kLdsMax) {
+      g->plane_path = 2;
+      g->pg.pb = pb;
+      g->pg.lds_pair = pair_plane_lds_bytes(prec, hm.ext, n2, pb);
+    }
+  }
   g->pg.ext_div = make_fastdiv(hm.ext);
   g->pg.rc_div = make_fastdiv(g->pg.rc);
   g->pg.rlast_div = make_fastdiv(n2 % g->pg.rc ? n2 % g->pg.rc : g->pg.rc);
@@ -480,7 +498,9 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   for (int s = 0; s < hm.nst; ++s) {
     for (int gg = hm.stick_off[s]; gg < hm.stick_off[s + 1]; ++gg)
       gmap[gg] = s * c->sg.ldz + fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3));
-    tidx[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, imod(hm.stick_k[s], n2));
+    const int ky = imod(hm.stick_k[s], n2);
+    tidx[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT +
+              (c->plane_path == 2 ? ky : fft_digit_pos(c->dy, ky));
   }
   for (int cc = 0; cc < hm.ext; ++cc) xin[fft_digit_pos(c->dx, imod(hm.hmin + cc, n1))] = cc;
   std::vector<int> colstart(hm.ext + 1, hm.nst);

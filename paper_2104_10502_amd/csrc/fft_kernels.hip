@@ -16,6 +16,7 @@
 // scatter / gather index tables, so no explicit reordering pass exists.
 #include "cplx.h"
 #include "fft_radix.h"
+#include "fft_reg.h"
 #include "qeh_internal.h"
 
 namespace qeh {
@@ -384,6 +385,122 @@ __global__ __launch_bounds__(kPT) void k2_plane(
   for (int s = tid; s < nst; s += kPT) plane[s] = T[tidx[s]];
 }
 
+// ---------------------------------------------------------------- K2, lane pairs
+// Plane pass with every line transform held in registers, for boxes with
+// N1 = N2 = N even and a compiled form of N.  Each line (a y column of the
+// x-extent tile, or a full x row) belongs to two adjacent lanes that hold one
+// half of it each (pair_inv / pair_fwd), so a transform costs one LDS load and
+// one LDS store per point, with compile-time indices and twiddles.
+// Rows: the x-extent column c = h - hmin sits at x position c instead of
+// h mod N.  The shift multiplies the inverse row transform by
+// exp(2 pi i hmin x / N) and the forward transform by its conjugate; V(r) is
+// real, so the two phases cancel and the values returned on the columns are
+// those of the unshifted transform.  Row positions c >= ext load from a zero
+// slot and store to a per-thread discard slot, which keeps every lane on one
+// path.  Column y positions are natural (tidx holds c*LD + (k mod N)).
+// One workgroup: pb bands of one z plane (they read the same V rows), with the
+// XCD-aware id remap of the fused kernel.
+constexpr int kRT = 256;
+
+template <typename C, int N>
+__global__ __launch_bounds__(kRT) void k2_plane_pair(
+    C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
+    const int *__restrict__ tidx, int nst, int n3, int ext, int pb, int nbk, int ngrp,
+    int per_xcd) {
+  using R = typename real_of<C>::type;
+  constexpr int LD = N | 1, M = N / 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *T = reinterpret_cast<C *>(smem_raw);
+  const int id = blockIdx.x;
+  const int logical = (id & 7) * per_xcd + (id >> 3);
+  if (logical >= ngrp * n3) return;
+  const int z = logical / ngrp;
+  const int g = logical - z * ngrp;
+  const int b0 = g * pb;
+  const int np = min(pb, nbk - b0);
+  const int tid = threadIdx.x;
+  const int tile = ext * LD;
+  const C *zslot = T + pb * tile;
+  C *dslot = T + pb * tile + 1 + tid;
+  const C zero = cmk<C>(0, 0);
+
+  for (int i = tid; i < np * tile; i += kRT) T[i] = zero;
+  if (tid == 0) T[pb * tile] = zero;
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    const C *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    C *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += kRT) Tp[tidx[s]] = plane[s];
+  }
+  __syncthreads();
+
+  // inverse y transforms of the np * ext columns
+  for (int j = tid; j < 2 * np * ext; j += kRT) {
+    const bool odd = j & 1;
+    C *col = T + (j >> 1) * LD;
+    C v[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) v[n] = col[2 * n + odd];
+    regfft::pair_inv<C, N>(v, odd);
+    C *out = col + (odd ? M : 0);
+#pragma unroll
+    for (int k = 0; k < M; ++k) out[k] = v[k];
+  }
+  __syncthreads();
+
+  // rows: x inverse, V(r)/N, x forward
+  for (int j = tid; j < 2 * np * N; j += kRT) {
+    const bool odd = j & 1;
+    const int r = j >> 1;
+    const int p = r / N;
+    const int y = r - p * N;
+    C *row = T + p * tile + y;
+    const int l = odd ? 1 : 0;
+    C v[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      const int c = 2 * n + l;
+      const C *a = c < ext ? row + c * LD : zslot;
+      v[n] = *a;
+    }
+    regfft::pair_inv<C, N>(v, odd);
+    const R *vr = vs + ((size_t)z * N + y) * N + l * M;
+#pragma unroll
+    for (int x = 0; x < M; ++x) v[x] = cscale(v[x], vr[x]);
+    regfft::pair_fwd<C, N>(v, odd);
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int c = 2 * m + l;
+      C *a = c < ext ? row + c * LD : dslot;
+      *a = v[m];
+    }
+  }
+  __syncthreads();
+
+  // forward y transforms
+  for (int j = tid; j < 2 * np * ext; j += kRT) {
+    const bool odd = j & 1;
+    C *col = T + (j >> 1) * LD;
+    const C *in = col + (odd ? M : 0);
+    C v[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) v[x] = in[x];
+    regfft::pair_fwd<C, N>(v, odd);
+#pragma unroll
+    for (int m = 0; m < M; ++m) col[2 * m + odd] = v[m];
+  }
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    C *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    const C *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += kRT) plane[s] = Tp[tidx[s]];
+  }
+}
+
+// Box sizes with a compiled lane-pair kernel (single precision).
+#define QEH_PAIR_SIZES(X) \
+  X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(90)
+
 // ---------------------------------------------------------------- K2, split
 // Planes whose column tile does not fit in LDS go through an HBM scratch
 // big[b][z][c][y] (one x-extent column of N2 values after another):
@@ -556,11 +673,49 @@ template <typename C> hipError_t k2_impl(const qeh_ctx *c, int nbk) {
   return hipGetLastError();
 }
 
+template <int N> hipError_t k2_pair_launch(const qeh_ctx *c, int nbk) {
+  const int pb = c->pg.pb;
+  const int ngrp = (nbk + pb - 1) / pb;
+  const int per_xcd = (ngrp * c->n3 + 7) / 8;
+  allow_lds(k2_plane_pair<float2, N>, c->pg.lds_pair);
+  hipLaunchKernelGGL((k2_plane_pair<float2, N>), dim3(8 * per_xcd), dim3(kRT), c->pg.lds_pair,
+                     c->stream, reinterpret_cast<float2 *>(c->d.sbuf),
+                     reinterpret_cast<const float *>(c->d.vs), c->d.tidx, c->nst, c->n3, c->ext,
+                     pb, nbk, ngrp, per_xcd);
+  return hipGetLastError();
+}
+
+hipError_t k2_pair_impl(const qeh_ctx *c, int nbk) {
+  switch (c->n1) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return k2_pair_launch<NN>(c, nbk);
+    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
   const size_t c = prec == QEH_FP64 ? 16 : 8;
   return c * ((size_t)ext * g.ldT + (size_t)g.rc * g.ldR + n1 + n2) + 4 * (size_t)n1;
+}
+
+bool pair_plane_supported(int prec, int n1, int n2) {
+  if (prec != QEH_MIXED || n1 != n2) return false;
+  switch (n1) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return true;
+    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+    default: return false;
+  }
+}
+
+size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb) {
+  const size_t c = prec == QEH_FP64 ? 16 : 8;
+  return c * ((size_t)pb * ext * (n2 | 1) + 1 + kRT);
 }
 
 size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
@@ -574,6 +729,7 @@ hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
 }
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {
+  if (c->plane_path == 2) return k2_pair_impl(c, nbk);
   if (c->plane_path != 0)
     return c->prec == QEH_FP64 ? k2_split_impl<double2>(c, nbk) : k2_split_impl<float2>(c, nbk);
   return c->prec == QEH_FP64 ? k2_impl<double2>(c, nbk) : k2_impl<float2>(c, nbk);

@@ -1,0 +1,161 @@
+// Whole 1D transforms held in one thread's registers, for lengths known at
+// compile time (natural order in and out).
+//
+// N = R * M with R the first radix from {8, 4, 2, 3, 5, 7}: the R sub-sequences
+// x[r + R m] are transformed recursively (length M), multiplied by the
+// twiddles W_N^{r k'}, and combined by R-point butterflies:
+//   X[k' + M s] = sum_r W_R^{r s} W_N^{r k'} Y_r[k'].
+// Every index is a compile-time constant after unrolling, so the arrays stay
+// in registers and the twiddles are immediate constants (tables evaluated by
+// constexpr trigonometry: Taylor series on the reduced angle).
+#pragma once
+
+#include "cplx.h"
+#include "fft_radix.h"
+
+namespace qeh {
+namespace regfft {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// sin / cos of 2 pi m / n for integers m, n (angle reduced to [-pi, pi]).
+constexpr double ce_sincos(long m, long n, bool want_sin) {
+  long r = m % n;
+  if (r < 0) r += n;
+  if (2 * r > n) r -= n;
+  const double x = 2.0 * kPi * (double)r / (double)n;
+  double term = want_sin ? x : 1.0;
+  double sum = term;
+  const int start = want_sin ? 1 : 0;
+  for (int i = 1; i < 30; ++i) {
+    const int a = 2 * i - 1 + start, b = 2 * i + start;
+    term *= -x * x / ((double)a * (double)b);
+    sum += term;
+  }
+  return sum;
+}
+
+template <int N> struct Table {
+  double re[N > 0 ? N : 1];
+  double im[N > 0 ? N : 1];
+};
+
+// exp(-2 pi i m / N)
+template <int N> constexpr Table<N> make_table() {
+  Table<N> t{};
+  for (int m = 0; m < N; ++m) {
+    t.re[m] = ce_sincos(m, N, false);
+    t.im[m] = -ce_sincos(m, N, true);
+  }
+  return t;
+}
+
+template <int N> struct Tw {
+  static constexpr Table<N> t = make_table<N>();
+};
+
+constexpr int first_radix(int n) {
+  return n % 8 == 0 ? 8 : n % 4 == 0 ? 4 : n % 2 == 0 ? 2 : n % 3 == 0 ? 3 : n % 5 == 0 ? 5 : 7;
+}
+
+template <typename C, int N, bool INV> struct Fft {
+  static __host__ __device__ __forceinline__ void run(C *v) {
+    constexpr int R = first_radix(N);
+    constexpr int M = N / R;
+    using Rl = typename real_of<C>::type;
+    if constexpr (M == 1) {
+      dftR<C, R, INV>(v);
+    } else {
+      C y[R][M];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) y[r][m] = v[r + R * m];
+        Fft<C, M, INV>::run(y[r]);
+      }
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        C u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e = (r * k) % N;
+          if (e == 0) {
+            u[r] = y[r][k];
+          } else {
+            const Rl wr = static_cast<Rl>(Tw<N>::t.re[e]);
+            const Rl wi = static_cast<Rl>(INV ? -Tw<N>::t.im[e] : Tw<N>::t.im[e]);
+            u[r] = cmul(y[r][k], cmk<C>(wr, wi));
+          }
+        }
+        dftR<C, R, INV>(u);
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[k + M * s] = u[s];
+      }
+    }
+  }
+};
+
+// ---------------------------------------------------------------- lane pairs
+// A line of N = 2M points held by two adjacent lanes (lane parity l), M points
+// each: the in-lane transforms of length M above plus one radix-2 stage across
+// the pair, whose partner values arrive through a DPP swap of adjacent lanes.
+// Both lanes of a pair must be active together.
+
+__device__ __forceinline__ float lane_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double lane_swap(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Lane 1 multiplies element k by W_N^{k} (conjugated for the inverse); the
+// product is formed on both lanes and selected, which keeps the code free of
+// divergent branches.
+template <typename C, int N, bool INV>
+__device__ __forceinline__ void pair_twiddle(C *v, bool odd) {
+  using Rl = typename real_of<C>::type;
+  constexpr int M = N / 2;
+#pragma unroll
+  for (int k = 1; k < M; ++k) {
+    const Rl wr = static_cast<Rl>(Tw<N>::t.re[k]);
+    const Rl wi = static_cast<Rl>(INV ? -Tw<N>::t.im[k] : Tw<N>::t.im[k]);
+    const C t = cmul(v[k], cmk<C>(wr, wi));
+    v[k] = odd ? t : v[k];
+  }
+}
+
+// Radix-2 across the pair: lane 0 keeps own + partner, lane 1 partner - own.
+template <typename C, int M>
+__device__ __forceinline__ void pair_butterfly(C *v, bool odd) {
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    const C o = v[k];
+    const C p = cmk<C>(lane_swap(o.x), lane_swap(o.y));
+    v[k].x = odd ? p.x - o.x : p.x + o.x;
+    v[k].y = odd ? p.y - o.y : p.y + o.y;
+  }
+}
+
+// Inverse (+i) transform of length N: on entry lane l holds x[2n + l], n < M;
+// on exit X[k + M l], k < M.
+template <typename C, int N>
+__device__ __forceinline__ void pair_inv(C *v, bool odd) {
+  Fft<C, N / 2, true>::run(v);
+  pair_twiddle<C, N, true>(v, odd);
+  pair_butterfly<C, N / 2>(v, odd);
+}
+
+// Forward (-i) transform of length N: on entry lane l holds f[x + M l];
+// on exit F[2m + l].
+template <typename C, int N>
+__device__ __forceinline__ void pair_fwd(C *v, bool odd) {
+  pair_butterfly<C, N / 2>(v, odd);
+  pair_twiddle<C, N, false>(v, odd);
+  Fft<C, N / 2, false>::run(v);
+}
+
+}  // namespace regfft
+}  // namespace qeh

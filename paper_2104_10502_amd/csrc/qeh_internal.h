@@ -48,6 +48,8 @@ struct PlaneGeom {
   int ldR;   // row stride of the row buffer (>= N1, odd)
   size_t lds_bytes;
   FastDiv ext_div, rc_div, rlast_div;   // ext, rc, rows of the last chunk
+  int pb;            // lane-pair kernel: planes (bands of one z) per workgroup
+  size_t lds_pair;   // lane-pair kernel: LDS bytes per workgroup
 };
 
 // Split plane path (planes too large for LDS): column groups of cg columns,
@@ -69,7 +71,8 @@ struct StickGeom {
 struct DevMaps {
   int *stick_off;    // [nst+1] first G of each stick
   int *gmap;         // [npw] s*ldz + digit-reversed z position
-  int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2)
+  int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2); the lane-pair
+                     // kernel takes natural y (pos_y = identity)
   int *xin;          // [N1] column c whose h sits at x-DIT input position p, or -1
   double *kin;       // [npw] |k+G|^2
   double *hdiag;     // [npw] diag(H)
@@ -95,7 +98,7 @@ struct qeh_ctx {
   int npw = 0, nst = 0, nkb = 0, nat = 0;
   int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
   int block = 0, prec = 0;
-  int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM
+  int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel
   int nsplit = 1, kchunk = 0;
   int nchunk = 0;
   qeh::FftDim dx{}, dy{}, dz{};
@@ -129,6 +132,10 @@ hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
                      double2 *hpsi, int ldh, int add_kinetic);
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g);
 size_t stick_lds_bytes(int prec, int n3, const StickGeom &g);
+// Lane-pair plane kernel: whether a compiled form exists for this precision and
+// box, and its LDS bytes for pb planes of ext columns.
+bool pair_plane_supported(int prec, int n1, int n2);
+size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 
 // ---- complex GEMM launchers (gemm_kernels.hip) ----------------------------
 // C[m][n] (+)= sum_k opA(A[m][k]) opB(B(k,n)), complex, MFMA.

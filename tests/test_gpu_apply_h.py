@@ -148,3 +148,67 @@ def test_apply_h_c2_bench_launch(prec):
     ref = oracle.apply_h(c, psi[idx])
     err = _rel_l2(got[idx], ref)
     assert err.max() < (1e-12 if prec == 0 else 1e-5), err
+
+
+def test_plane_kernel_choice_c1(monkeypatch):
+    # the mixed form of a cubic box with a compiled lane-pair size takes the
+    # lane-pair plane kernel; QEH_PLANE_KERNEL=generic keeps the fused one
+    c = cell("c1")
+    q = _qeh()
+    assert q.Context.from_cell(c, precision=1, block=4).info()["plane_path"] == 2
+    assert q.Context.from_cell(c, precision=0, block=4).info()["plane_path"] == 0
+    monkeypatch.setenv("QEH_PLANE_KERNEL", "generic")
+    assert q.Context.from_cell(c, precision=1, block=4).info()["plane_path"] == 0
+
+
+@pytest.mark.parametrize("kernel", ["pair", "generic"])
+def test_apply_h_c1_mixed_plane_kernels(kernel, monkeypatch):
+    if kernel == "generic":
+        monkeypatch.setenv("QEH_PLANE_KERNEL", "generic")
+    c = cell("c1")
+    psi = cellgen.make_psi0(c.npw, 16, seed=41)
+    got, ctx = run(c, psi, 1, 16)
+    assert ctx.info()["plane_path"] == (2 if kernel == "pair" else 0)
+    err = _rel_l2(got, oracle.apply_h(c, psi))
+    assert err.max() < 1e-5, err.max()
+
+
+@pytest.mark.parametrize("pb", [1, 3, 8])
+def test_apply_h_pair_planes_per_workgroup(pb, monkeypatch):
+    # bands per lane-pair workgroup 1, 3 and 8 on 7 bands in blocks of 5:
+    # ragged band groups in both launches
+    monkeypatch.setenv("QEH_PAIR_PLANES", str(pb))
+    c = cell("c1")
+    psi = cellgen.make_psi0(c.npw, 7, seed=42)
+    got, ctx = run(c, psi, 1, 5)
+    assert ctx.info()["plane_path"] == 2
+    err = _rel_l2(got, oracle.apply_h(c, psi))
+    assert err.max() < 1e-5, err.max()
+
+
+def test_apply_h_pair_small_box_general_k():
+    # N1 = N2 = 18 (in-lane length 9), non-cubic lattice, general k, s/p/d
+    # projectors, odd x-extent 7
+    c = cellgen.make_cell("t", lattice=np.diag([7.0, 7.0, 9.5]), frac=np.array(
+        [[0.1, 0.2, 0.3], [0.6, 0.5, 0.9]]), kpt=(0.11, -0.07, 0.23), ecutwfc=12.0,
+        fft=(18, 18, 28), proj="s2pd", dfixed=False, nbnd=8)
+    psi = cellgen.make_psi0(c.npw, 6, seed=43)
+    got, ctx = run(c, psi, 1, 4)
+    assert ctx.info()["plane_path"] == 2 and ctx.info()["ext"] == 7
+    err = _rel_l2(got, oracle.apply_h(c, psi))
+    assert err.max() < 1e-5, err.max()
+
+
+def test_pair_matches_generic_c2():
+    # the two mixed plane kernels agree on the full C2 shape to FP32 rounding
+    import os
+    c = cell("c2")
+    psi = cellgen.make_psi0(c.npw, 4, seed=44)
+    a, ca = run(c, psi, 1, 4)
+    os.environ["QEH_PLANE_KERNEL"] = "generic"
+    try:
+        b, cb = run(c, psi, 1, 4)
+    finally:
+        del os.environ["QEH_PLANE_KERNEL"]
+    assert ca.info()["plane_path"] == 2 and cb.info()["plane_path"] == 0
+    assert _rel_l2(a, b).max() < 2e-6
