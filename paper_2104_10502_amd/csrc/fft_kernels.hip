@@ -402,8 +402,11 @@ __global__ __launch_bounds__(kPT) void k2_plane(
 // XCD-aware id remap of the fused kernel.
 constexpr int kRT = 256;
 
+// Register budget: three waves per SIMD (<= 168 VGPRs) keeps three 2-band
+// workgroups resident per CU at N = 72 without spills, measured faster there
+// than two waves per SIMD; N = 90 needs the two-wave budget to avoid spills.
 template <typename C, int N>
-__global__ __launch_bounds__(kRT) void k2_plane_pair(
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 : 2))) void k2_plane_pair(
     C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
     const int *__restrict__ tidx, int nst, int n3, int ext, int pb, int nbk, int ngrp,
     int per_xcd) {

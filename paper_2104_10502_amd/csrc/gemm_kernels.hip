@@ -256,9 +256,21 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP *__restrict
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total;
        t += (long)gridDim.x * blockDim.x) {
     const int m = (int)(t / N), n = (int)(t % N);
+    const TP *pp = part + (long)m * ldp + n;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < nsplit; ++s) {
-      const TP v = part[(long)s * stride + (long)m * ldp + n];
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {   // split order kept; 8 loads in flight
+      TP v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(long)(s + u) * stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sr += static_cast<double>(v[u].x);
+        si += static_cast<double>(v[u].y);
+      }
+    }
+    for (; s < nsplit; ++s) {
+      const TP v = pp[(long)s * stride];
       sr += static_cast<double>(v.x);
       si += static_cast<double>(v.y);
     }
@@ -287,9 +299,23 @@ __global__ __launch_bounds__(256) void dscale_kernel(
   const int t = threadIdx.x;
   const int j = p0 + t;
   if (j < p1) {
+    // partials summed in split order; loads issued eight at a time so that
+    // several are in flight per thread
+    const TP *pp = part + (long)b * nkb + j;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < nsplit; ++s) {
-      const TP v = part[(long)s * split_stride + (long)b * nkb + j];
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {
+      TP v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(long)(s + u) * split_stride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        sr += static_cast<double>(v[u].x);
+        si += static_cast<double>(v[u].y);
+      }
+    }
+    for (; s < nsplit; ++s) {
+      const TP v = pp[(long)s * split_stride];
       sr += static_cast<double>(v.x);
       si += static_cast<double>(v.y);
     }
