@@ -33,18 +33,36 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_TFLOPS = 157.3
 MFMA_F64_TFLOPS = 78.6
+# vector ALU peaks (256 CUs x 4 SIMDs x 16 lanes x FMA at 2.4 GHz = 78.6 TFLOP/s
+# per instruction stream; the published FP32 figure counts packed FP32, 2x)
+VALU_F32_TFLOPS = 157.3
+VALU_F64_TFLOPS = 78.6
 METRIC = "H|psi> band-applies/sec (FFT pts*bands/s) FP32 vs FP64; serve p50/p99 latency"
 
 
+def fft_flops(n):
+    """Conventional flop count of a complex 1D transform of length n."""
+    return 5.0 * n * np.log2(n)
+
+
+def plane_flops(shape):
+    """Flops of the pruned plane pass per band and z plane: inverse and forward
+    transforms of the N2 x rows and the x-extent y columns, and the real V(r)
+    multiply (2 flops per point)."""
+    n1, n2, ext = shape["n1"], shape["n2"], shape["ext"]
+    return 2.0 * (n2 * fft_flops(n1) + ext * fft_flops(n2)) + 2.0 * n1 * n2
+
+
 def algorithmic(stage, shape, prec, nb):
-    """Algorithmic bytes (FFT stages) or flops (GEMM stages) of one launch of nb bands."""
+    """Algorithmic bytes (stick stages), flops (plane pass, GEMM stages) of one
+    launch of nb bands, with the resource that bounds it."""
     npw, nst, nkb, n1, n2, n3 = (shape[k] for k in ("npw", "nst", "nkb", "n1", "n2", "n3"))
     c = 16 if prec == 0 else 8
     nfft = n1 * n2 * n3
     if stage == "k1_scatter_zinv":   # read psi (complex128), write sticks (+ FP32 psi copy)
         return "hbm", nb * (16 * npw + c * nst * n3 + 4 * npw + (8 * npw if prec else 0))
-    if stage == "k2_plane":          # read + write sticks, V once per launch
-        return "hbm", nb * 2 * c * nst * n3 + (c // 2) * nfft
+    if stage == "k2_plane":          # transform flops; its bytes: plane_bytes()
+        return "alu", nb * n3 * plane_flops(shape)
     if stage == "k3_zfwd_gather":    # read sticks, psi, |k+G|^2, write H psi
         return "hbm", nb * (c * nst * n3 + 16 * npw + 16 * npw + 4 * npw) + 8 * npw
     if stage == "calbec_gemm":
@@ -54,6 +72,12 @@ def algorithmic(stage, shape, prec, nb):
     if stage == "dscale":
         return "hbm", nb * nkb * c * 2
     raise KeyError(stage)
+
+
+def plane_bytes(shape, prec, nb):
+    """K2 algorithmic HBM bytes: read + write the sticks, V once per launch."""
+    c = 16 if prec == 0 else 8
+    return nb * 2 * c * shape["nst"] * shape["n3"] + (c // 2) * shape["n1"] * shape["n2"] * shape["n3"]
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c2_hbm_traffic.json")
@@ -117,11 +141,17 @@ def roofline_for(stages, shape, prec, nb):
         if bound == "hbm":
             achieved = amount / avg_s / 1e9
             peak, unit = HBM_PEAK_GBS, "GB/s"
+        elif bound == "alu":
+            achieved = amount / avg_s / 1e12
+            peak, unit = (VALU_F64_TFLOPS if prec == 0 else VALU_F32_TFLOPS), "TFLOP/s"
         else:
             achieved = amount / avg_s / 1e12
             peak, unit = (MFMA_F64_TFLOPS if prec == 0 else MFMA_F32_TFLOPS), "TFLOP/s"
         per[name] = dict(avg_us=avg_s * 1e6, launches=n, bound=bound, achieved=achieved,
                          peak=peak, unit=unit, frac=achieved / peak)
+        if name == "k2_plane":   # its HBM side, for the ridge between the two bounds
+            gbs = plane_bytes(shape, prec, nb) / avg_s / 1e9
+            per[name].update(hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
         if best is None or ms > stages[best][0]:
             best = name
     return best, per

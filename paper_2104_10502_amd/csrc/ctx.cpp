@@ -321,12 +321,12 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
     }
   }
   // split-K of beta^H psi: enough workgroups to fill the chip (~4 per CU),
-  // fixed chunks of >= 256 plane waves.  Tiles: 128 x 64 for blocks > 64 bands
-  // in the mixed form, else 64 x 64.
+  // fixed chunks of >= 256 plane waves, 64 x 64 tiles (measured faster than
+  // 128 x 64 at 128 bands: four waves per SIMD instead of two).
   g->nsplit = 1;
   g->kchunk = c->npw;
   if (g->nkb > 0) {
-    const int bm = (prec == QEH_MIXED && c->block > 64) ? 128 : 64;
+    const int bm = 64;
     const int tiles = ((c->block + bm - 1) / bm) * ((g->nkb + 63) / 64);
     int ns = std::max(1, (1024 + tiles - 1) / tiles);
     ns = std::min(ns, std::max(1, c->npw / 256));
@@ -690,7 +690,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     g1.A = use32 ? static_cast<const void *>(c->d.psi32) : static_cast<const void *>(psi);
     g1.lda = use32 ? c->npw : ldpsi;
     g1.ta = use32 ? T_F2 : T_D2;
-    g1.tile = 1;
+    g1.tile = 0;
     g1.B = c->d.beta;
     g1.ldb = c->npw;
     g1.tb = f64 ? T_D2 : T_F2;

@@ -7,8 +7,15 @@
 // solver, which the paper runs through GPU BLAS (section "Evolution of the
 // GPU-enabled version").
 //
-// A complex product is four real MFMA products on planar (re, im) tiles:
-//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// FP32: a complex product is three real MFMA products on planar (re, im)
+// tiles (Gauss's three-multiplication form):
+//   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + Ai)(Br + Bi),
+//   Cr = P1 - P2,  Ci = P3 - P1 - P2.
+// The operand sums are formed in registers after the LDS reads.  The form is
+// normwise stable; its rounding error is a small constant multiple of that of
+// the four-product form.  FP64 keeps four products,
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br,
+// which measured faster there (two accumulators instead of three).
 // 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
 // (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
 // split into fixed chunks whose partial results are summed in double by a
@@ -64,7 +71,7 @@ template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, 
 __global__ __launch_bounds__(kGT) void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
     long ldc, int M, int N, int K, int conjA, int conjB, int accumulate, int kchunk,
-    long split_stride) {
+    long split_stride, int tiles_m, int tiles_n, int ntiles, int per_xcd) {
   using ACC = typename acc_of<R>::type;
   constexpr int BKP = BK + 1;
   constexpr int TM = BM / 32;
@@ -80,22 +87,34 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
   const int wave = tid >> 6;
   const int wm0 = (wave >> 1) * (BM / 2);
   const int wn0 = (wave & 1) * (BN / 2);
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
-  const int kz = blockIdx.z;
+  // Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2);
+  // the remap gives each XCD a contiguous run of (m tile fastest, n tile,
+  // K slice), so tiles that read the same operand rows run on one XCD
+  // back to back.
+  const int id = blockIdx.x;
+  const int logical = (id & 7) * per_xcd + (id >> 3);
+  if (logical >= ntiles) return;
+  const int mt = logical % tiles_m;
+  const int nt = (logical / tiles_m) % tiles_n;
+  const int kz = logical / (tiles_m * tiles_n);
+  const int m0 = mt * BM;
+  const int n0 = nt * BN;
   const int kbeg = kz * kchunk;
   const int kend = min(K, kbeg + kchunk);
   TC *Cz = C + (long)kz * split_stride;
   const R sa = conjA ? R(-1) : R(1);
   const R sb = conjB ? R(-1) : R(1);
 
-  ACC acc_r[TM][TN], acc_i[TM][TN];
+  // Gauss form: p1, p2, p3 as above; four-product form: p1 = Cr, p2 = Ci
+  constexpr bool kGauss = sizeof(R) == 4;
+  ACC p1[TM][TN], p2[TM][TN], p3[kGauss ? TM : 1][kGauss ? TN : 1];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      acc_r[i][j] = ACC{0, 0, 0, 0};
-      acc_i[i][j] = ACC{0, 0, 0, 0};
+      p1[i][j] = ACC{0, 0, 0, 0};
+      p2[i][j] = ACC{0, 0, 0, 0};
+      if constexpr (kGauss) p3[i][j] = ACC{0, 0, 0, 0};
     }
 
   TA ra[NA];
@@ -160,28 +179,35 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
     if (more) gload(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      R ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
+      R ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
         const int off = (wm0 + i * 16 + lr) * BKP + kk + lk;
         ar[i] = As[buf][0][off];
         ai[i] = As[buf][1][off];
-        nai[i] = -ai[i];
+        as[i] = kGauss ? ar[i] + ai[i] : R(0);
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int off = (wn0 + j * 16 + lr) * BKP + kk + lk;
         br[j] = Bs[buf][0][off];
         bi[j] = Bs[buf][1][off];
+        bs[j] = kGauss ? br[j] + bi[j] : R(0);
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          mfma(ar[i], br[j], acc_r[i][j]);
-          mfma(nai[i], bi[j], acc_r[i][j]);
-          mfma(ar[i], bi[j], acc_i[i][j]);
-          mfma(ai[i], br[j], acc_i[i][j]);
+          if constexpr (kGauss) {
+            mfma(ar[i], br[j], p1[i][j]);
+            mfma(ai[i], bi[j], p2[i][j]);
+            mfma(as[i], bs[j], p3[i][j]);
+          } else {
+            mfma(ar[i], br[j], p1[i][j]);
+            mfma(-ai[i], bi[j], p1[i][j]);
+            mfma(ar[i], bi[j], p2[i][j]);
+            mfma(ai[i], br[j], p2[i][j]);
+          }
         }
     }
     if (more) sstore(buf ^ 1);
@@ -204,16 +230,24 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
         if (gm < M && gn < N) {
           TC *p = Cz + (long)gm * ldc + gn;
           using RC = typename real_of<TC>::type;
+          R cr, ci;
+          if constexpr (kGauss) {
+            cr = p1[i][j][r] - p2[i][j][r];
+            ci = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+          } else {
+            cr = p1[i][j][r];
+            ci = p2[i][j][r];
+          }
           if (accumulate) {
             TC v = *p;
             // the add happens in the result's precision
-            v.x = v.x + static_cast<RC>(acc_r[i][j][r]);
-            v.y = v.y + static_cast<RC>(acc_i[i][j][r]);
+            v.x = v.x + static_cast<RC>(cr);
+            v.y = v.y + static_cast<RC>(ci);
             *p = v;
           } else {
             TC v;
-            v.x = static_cast<RC>(acc_r[i][j][r]);
-            v.y = static_cast<RC>(acc_i[i][j][r]);
+            v.x = static_cast<RC>(cr);
+            v.y = static_cast<RC>(ci);
             *p = v;
           }
         }
@@ -222,12 +256,16 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
 
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
 hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, g.nsplit);
+  const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  const long total = (long)tm * tn * g.nsplit;
+  if (total > (1L << 30)) return hipErrorInvalidValue;
+  const int per_xcd = (int)((total + 7) / 8);
   const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
-  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK>), grid, dim3(kGT), 0, s,
-                     reinterpret_cast<const TA *>(g.A), g.lda, reinterpret_cast<const TB *>(g.B),
-                     g.ldb, reinterpret_cast<TC *>(g.C), g.ldc, g.M, g.N, g.K, g.conjA, g.conjB,
-                     g.accumulate, kchunk, g.split_stride);
+  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK>), dim3(8 * per_xcd),
+                     dim3(kGT), 0, s, reinterpret_cast<const TA *>(g.A), g.lda,
+                     reinterpret_cast<const TB *>(g.B), g.ldb, reinterpret_cast<TC *>(g.C), g.ldc,
+                     g.M, g.N, g.K, g.conjA, g.conjB, g.accumulate, kchunk, g.split_stride, tm, tn,
+                     (int)total, per_xcd);
   return hipGetLastError();
 }
 
