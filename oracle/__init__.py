@@ -20,6 +20,9 @@ exascale):
 * ``davidson``: the Davidson iterative diagonalisation (same section) with the
   Rayleigh-Ritz step solved as a Hermitian generalized eigenproblem, as the
   paper's dense-solver library does.
+* ``density``: the charge density generation of the same list of ported
+  kernels, rho(r) = (1/Omega) sum_i f_i |psi_i(r)|^2 on the FFT grid;
+  ``density_direct`` sums the plane waves point by point (tiny cells).
 
 The paper prints no formula for any of these; the forms are the standard
 plane-wave pseudopotential ones.  Every reading taken where the paper is
@@ -33,6 +36,8 @@ from .dft import dft_matrix, dft_axis, inv3, fwd3
 from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, vloc_coeffs,
                           hdiag)
 from .davidson import davidson, rayleigh_ritz
+from .density import cell_volume, density, density_direct, psi_real_space
 
 __all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
-           "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz"]
+           "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
+           "cell_volume", "density", "density_direct", "psi_real_space"]
