@@ -105,6 +105,32 @@ qeh_status qeh_apply_h(qeh_ctx *ctx, int nb, const double *psi, int ldpsi,
 qeh_status qeh_apply_h_part(qeh_ctx *ctx, int part, int nb, const double *psi,
                             int ldpsi, double *hpsi, int ldh);
 
+/* Charge density of a set of bands: the charge density generation listed
+ * among the GPU-ported kernels (section "Evolution of the GPU-enabled
+ * version"), the step that follows the diagonalisation in the
+ * self-consistency cycle.
+ *   rho[(z * N2 + y) * N1 + x] = (1 / Omega) sum_b occ[b] |psi_b(r)|^2,
+ *   psi_b(r) = sum_G psi_b(G) exp(i (k + G) . r),  r = x/N1 a1 + y/N2 a2 + z/N3 a3,
+ * with Omega = |det(lattice)|.  For bands normalised to sum_G |psi(G)|^2 = 1,
+ * (Omega / N) sum_r rho = sum_b occ[b].
+ *   psi  : device, nb rows of npw complex values (row stride ldpsi >= npw),
+ *          same layout as qeh_apply_h;
+ *   occ  : host, nb finite weights (any sign);
+ *   rho  : device, N1 N2 N3 doubles, overwritten (zero when nb = 0);
+ *   work : device workspace of qeh_density_plan bytes, 256-byte aligned,
+ *          owned by the caller.
+ * Bands go through in blocks of the context's block size: K1 (sticks and
+ * inverse z), inverse y columns into the workspace, then inverse x rows with
+ * the occupation-weighted |psi|^2 summed in double in a fixed order (the
+ * result does not depend on timing).  Precision: the context's (the mixed
+ * form transforms in FP32 and sums in FP64).  Blocking: returns after the
+ * device work of the call has finished.  Errors: QEH_ERR_INVALID for null
+ * pointers, ldpsi < npw, a short or misaligned workspace, a non-finite
+ * occupation, or a box whose rows exceed the row kernel (N1 > 2048). */
+qeh_status qeh_density_plan(const qeh_ctx *ctx, size_t *work_bytes);
+qeh_status qeh_density(qeh_ctx *ctx, int nb, const double *psi, int ldpsi,
+                       const double *occ, double *rho, void *work, size_t work_bytes);
+
 /* Davidson options: nvecx = maximum basis size (>= 2 nb; 0 = 2 nb),
  * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
  * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single

@@ -76,6 +76,9 @@ _SIGS = {
     "qeh_davidson_plan": ([_vp, ctypes.c_int, ctypes.POINTER(DavOpts), _sz_p], ctypes.c_int),
     "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
                       _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
+    "qeh_density_plan": ([_vp, _sz_p], ctypes.c_int),
+    "qeh_density": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, _vp, _vp, ctypes.c_size_t],
+                    ctypes.c_int),
     "qeh_ctx_profile": ([_vp, ctypes.c_int], ctypes.c_int),
     "qeh_ctx_stage_times": ([_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_long), ctypes.c_int],
                             ctypes.c_int),
@@ -298,6 +301,33 @@ class Context:
             st = _lib.qeh_apply_h_part(self._h, int(part), nb, _vp(psi.data_ptr()), ld_in,
                                        _vp(out.data_ptr()), ld_out)
         _check(st, "qeh_apply_h")
+        return out
+
+    # ---------------------------------------------------------------- density
+    def density_plan(self):
+        n = ctypes.c_size_t()
+        _check(_lib.qeh_density_plan(self._h, ctypes.byref(n)), "qeh_density_plan")
+        return int(n.value)
+
+    def density(self, psi, occ, out=None, work=None):
+        """rho(r) = (1/Omega) sum_b occ[b] |psi_b(r)|^2 as a (N3, N2, N1) float64 CUDA tensor."""
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        occ = np.ascontiguousarray(np.asarray(occ, dtype=np.float64).reshape(-1))
+        if occ.shape[0] != nb:
+            raise ValueError("one occupation per band")
+        shape = (self.info()["n3"], self.info()["n2"], self.info()["n1"])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device=psi.device)
+        if tuple(out.shape) != shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of shape %s" % (shape,))
+        need = self.density_plan()
+        if work is None or work.numel() < need:
+            work = torch.empty(max(need, 256), dtype=torch.uint8, device=psi.device)
+        _check(_lib.qeh_density(self._h, nb, _vp(psi.data_ptr()), psi.stride(0),
+                                occ.ctypes.data_as(_c_dbl_p), _vp(out.data_ptr()),
+                                _vp(work.data_ptr()), int(work.numel())), "qeh_density")
         return out
 
     # ---------------------------------------------------------------- Davidson

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <vector>
 
@@ -200,9 +201,9 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 
 // Arena layout, shared by plan and create.
 struct Layout {
-  size_t off_stick_off, off_gmap, off_tidx, off_xin, off_kin, off_hdiag, off_vs, off_tw,
-      off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part, off_ps,
-      off_big, off_colstart, off_psi32;
+  size_t off_stick_off, off_gmap, off_tidx, off_tidx_dit, off_xin, off_kin, off_hdiag, off_vs,
+      off_tw, off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part,
+      off_ps, off_big, off_colstart, off_psi32;
   size_t total;
 };
 
@@ -346,6 +347,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   L.off_stick_off = bump(&cur, 4 * (hm.nst + 1));
   L.off_gmap = bump(&cur, 4 * (size_t)c->npw);
   L.off_tidx = bump(&cur, 4 * (size_t)hm.nst);
+  L.off_tidx_dit = bump(&cur, 4 * (size_t)hm.nst);
   L.off_xin = bump(&cur, 4 * (size_t)c->fft[0]);
   L.off_kin = bump(&cur, 8 * (size_t)c->npw);
   L.off_hdiag = bump(&cur, 8 * (size_t)c->npw);
@@ -472,6 +474,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.stick_off = reinterpret_cast<int *>(A + L.off_stick_off);
   c->d.gmap = reinterpret_cast<int *>(A + L.off_gmap);
   c->d.tidx = reinterpret_cast<int *>(A + L.off_tidx);
+  c->d.tidx_dit = reinterpret_cast<int *>(A + L.off_tidx_dit);
   c->d.xin = reinterpret_cast<int *>(A + L.off_xin);
   c->d.kin = reinterpret_cast<double *>(A + L.off_kin);
   c->d.hdiag = reinterpret_cast<double *>(A + L.off_hdiag);
@@ -494,13 +497,13 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   const size_t nfft = (size_t)n1 * n2 * n3;
   const bool f64 = c->prec == QEH_FP64;
   // ---- host-side maps
-  std::vector<int> gmap(npw), tidx(hm.nst), xin(n1, -1);
+  std::vector<int> gmap(npw), tidx(hm.nst), tidx_dit(hm.nst), xin(n1, -1);
   for (int s = 0; s < hm.nst; ++s) {
     for (int gg = hm.stick_off[s]; gg < hm.stick_off[s + 1]; ++gg)
       gmap[gg] = s * c->sg.ldz + fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3));
     const int ky = imod(hm.stick_k[s], n2);
-    tidx[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT +
-              (c->plane_path == 2 ? ky : fft_digit_pos(c->dy, ky));
+    tidx_dit[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, ky);
+    tidx[s] = c->plane_path == 2 ? (hm.stick_h[s] - hm.hmin) * c->pg.ldT + ky : tidx_dit[s];
   }
   for (int cc = 0; cc < hm.ext; ++cc) xin[fft_digit_pos(c->dx, imod(hm.hmin + cc, n1))] = cc;
   std::vector<int> colstart(hm.ext + 1, hm.nst);
@@ -508,6 +511,11 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   for (int cc = hm.ext - 1; cc >= 0; --cc) colstart[cc] = std::min(colstart[cc], colstart[cc + 1]);
   double b[9];
   reciprocal(cell->lattice, b);
+  {
+    const double *a = cell->lattice;
+    c->omega = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                         a[2] * (a[3] * a[7] - a[4] * a[6]));
+  }
   std::vector<double> kin(npw), hdiag(npw);
   double vsum = 0.0;
   for (size_t i = 0; i < nfft; ++i) vsum += cell->vloc[i];
@@ -583,6 +591,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   up(c->d.stick_off, hm.stick_off.data(), 4 * hm.stick_off.size());
   up(c->d.gmap, gmap.data(), 4 * gmap.size());
   up(c->d.tidx, tidx.data(), 4 * tidx.size());
+  up(c->d.tidx_dit, tidx_dit.data(), 4 * tidx_dit.size());
   up(c->d.xin, xin.data(), 4 * xin.size());
   up(c->d.colstart, colstart.data(), 4 * colstart.size());
   up(c->d.kin, kin.data(), 8 * kin.size());
@@ -768,6 +777,71 @@ qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldp
   return QEH_OK;
 }
 
+// ---- charge density (charge density generation among the ported kernels,
+// section "Evolution of the GPU-enabled version")
+struct DensityWork {
+  size_t big, partial, occ, total;
+};
+
+DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
+  DensityWork w{};
+  size_t cur = 0;
+  const size_t cs = c->prec == QEH_FP64 ? 16 : 8;
+  const size_t nfft = (size_t)c->n1 * c->n2 * c->n3;
+  const int nsub = (c->block + dg.bsub - 1) / dg.bsub;
+  w.big = bump(&cur, cs * (size_t)c->block * c->n3 * c->ext * c->n2);
+  w.partial = bump(&cur, 8 * (size_t)nsub * nfft);
+  w.occ = bump(&cur, 8 * (size_t)c->block);
+  w.total = cur;
+  return w;
+}
+
+qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const double *occ,
+                        double *rho, void *work, size_t work_bytes) {
+  if (!c) return invalid("ctx is null");
+  if (nb < 0) return invalid("nb < 0");
+  if (!rho) return invalid("rho is null");
+  if (nb > 0 && (!psi || !occ)) return invalid("psi / occ null");
+  if (ldpsi < c->npw) return invalid("leading dimension < npw");
+  DensityGeom dg{};
+  if (!density_geometry(c, &dg)) return invalid("box too large for the density row kernel");
+  const DensityWork w = density_work(c, dg);
+  if (!work || work_bytes < w.total) return invalid("density work buffer too small");
+  if ((reinterpret_cast<uintptr_t>(work) % kAlign) != 0)
+    return invalid("density work buffer not 256-byte aligned");
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(occ[b])) return invalid("non-finite occupation");
+  char *W = static_cast<char *>(work);
+  double *occ_d = reinterpret_cast<double *>(W + w.occ);
+  double *partial = reinterpret_cast<double *>(W + w.partial);
+  const long npts = (long)c->n1 * c->n2 * c->n3;
+  const double scale = 1.0 / c->omega;
+  hipError_t e;
+  if (nb == 0) {
+    // no bands: rho = 0 (a kernel, not a memset)
+    e = launch_density_reduce(partial, 0, npts, scale, rho, 0, c->stream);
+    return e == hipSuccess ? QEH_OK : hip_fail(e, "density reduce launch");
+  }
+  const double2 *p = reinterpret_cast<const double2 *>(psi);
+  for (int b0 = 0; b0 < nb; b0 += c->block) {
+    const int nbk = std::min(c->block, nb - b0);
+    // the previous block's kernels read occ_d; the copy below is ordered after
+    // them on the same stream
+    e = hipMemcpyAsync(occ_d, occ + b0, 8 * (size_t)nbk, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "occupation upload");
+    e = launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
+    if (e != hipSuccess) return hip_fail(e, "K1 launch");
+    e = launch_density_block(c, dg, nbk, W + w.big, occ_d, partial);
+    if (e != hipSuccess) return hip_fail(e, "density launch");
+    const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
+    e = launch_density_reduce(partial, nsub, npts, scale, rho, b0 > 0 ? 1 : 0, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "density reduce launch");
+  }
+  // occ is a caller's host array: the copies above must be complete on return
+  e = hipStreamSynchronize(c->stream);
+  return e == hipSuccess ? QEH_OK : hip_fail(e, "density sync");
+}
+
 }  // namespace qeh
 
 extern "C" {
@@ -781,6 +855,19 @@ qeh_status qeh_apply_h_part(qeh_ctx *c, int part, int nb, const double *psi, int
                             double *hpsi, int ldh) {
   if (part != 0 && part != 1) return invalid("part must be 0 (kinetic+local) or 1 (nonlocal)");
   return apply_h_impl(c, part, nb, psi, ldpsi, hpsi, ldh);
+}
+
+qeh_status qeh_density_plan(const qeh_ctx *c, size_t *work_bytes) {
+  if (!c || !work_bytes) return invalid("null argument");
+  DensityGeom dg{};
+  if (!density_geometry(c, &dg)) return invalid("box too large for the density row kernel");
+  *work_bytes = density_work(c, dg).total;
+  return QEH_OK;
+}
+
+qeh_status qeh_density(qeh_ctx *c, int nb, const double *psi, int ldpsi, const double *occ,
+                       double *rho, void *work, size_t work_bytes) {
+  return density_impl(c, nb, psi, ldpsi, occ, rho, work, work_bytes);
 }
 
 qeh_status qeh_ctx_profile(qeh_ctx *c, int enable) {

@@ -14,6 +14,8 @@
 // yields natural order; forward transforms use decimation in frequency,
 // natural in and digit-reversed out.  The permutations are folded into the
 // scatter / gather index tables, so no explicit reordering pass exists.
+#include <algorithm>
+
 #include "cplx.h"
 #include "fft_radix.h"
 #include "fft_reg.h"
@@ -500,6 +502,98 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 
   }
 }
 
+// ---------------------------------------------------------------- density
+// Charge density generation: rho(r) = (1/Omega) sum_b occ_b |psi_b(r)|^2.
+// The bands reach real space along z and y through K1 and k2a (big holds the
+// inverse-y columns of every plane); this kernel takes a group of rows of one
+// z plane for a subgroup of bands: rows from big -> inverse x transforms ->
+// sum over the subgroup's bands of occ_b |psi_b|^2, accumulated in double in
+// band order, written as partial[sub][z][y][x].  density_reduce sums the
+// subgroups in order, so every point has one fixed summation order.
+constexpr int kDensityPPT = 8;   // grid points per thread of a row group
+
+template <typename C>
+__global__ __launch_bounds__(kNT) void k2d_rows_density(
+    const C *__restrict__ big, const double *__restrict__ occ, double *__restrict__ partial,
+    const int *__restrict__ xin_g, const C *__restrict__ twx_g, FftDim dx, int n2, int n3,
+    int ext, int rg, int ldR, int ngroups, int nbk, int bsub, FastDiv rgd, FastDiv rglast) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n1 = dx.n;
+  C *RB = reinterpret_cast<C *>(smem_raw);
+  C *twx = RB + rg * ldR;
+  int *xin = reinterpret_cast<int *>(twx + n1);
+  const int g = blockIdx.x % ngroups;
+  const int z = (blockIdx.x / ngroups) % n3;
+  const int sub = blockIdx.x / (ngroups * n3);
+  const int y0 = g * rg;
+  const int nr = min(rg, n2 - y0);
+  const int b0 = sub * bsub;
+  const int b1 = min(nbk, b0 + bsub);
+  const int tid = threadIdx.x;
+  const int npt = nr * n1;
+  const C zero = cmk<C>(0, 0);
+  for (int i = tid; i < n1; i += kNT) {
+    twx[i] = twx_g[i];
+    xin[i] = xin_g[i];
+  }
+  __syncthreads();
+  // per-thread points: line buffer slot of each input (DIT position p of
+  // row r) and of each output (natural x of row r); fixed for every band
+  int lds_in[kDensityPPT], src[kDensityPPT], lds_out[kDensityPPT];
+#pragma unroll
+  for (int k = 0; k < kDensityPPT; ++k) {
+    const int i = tid + k * kNT;
+    lds_in[k] = -1;
+    src[k] = -1;
+    lds_out[k] = -1;
+    if (i < npt) {
+      const int p = i / nr, r = i - (i / nr) * nr;   // r fastest: y-contiguous reads
+      const int c = xin[p];
+      lds_in[k] = r * ldR + p;
+      src[k] = c >= 0 ? c * n2 + y0 + r : -1;
+      const int ro = i / n1, x = i - (i / n1) * n1;
+      lds_out[k] = ro * ldR + x;
+    }
+  }
+  double acc[kDensityPPT];
+#pragma unroll
+  for (int k = 0; k < kDensityPPT; ++k) acc[k] = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    const C *col = big + ((size_t)b * n3 + z) * ext * n2;
+#pragma unroll
+    for (int k = 0; k < kDensityPPT; ++k)
+      if (lds_in[k] >= 0) RB[lds_in[k]] = src[k] >= 0 ? col[src[k]] : zero;
+    __syncthreads();
+    fft_inv_dit<C>(RB, nr == rg ? rgd : rglast, ldR, dx, twx, tid, kNT);
+    const double f = occ[b];
+#pragma unroll
+    for (int k = 0; k < kDensityPPT; ++k)
+      if (lds_out[k] >= 0) {
+        const C v = RB[lds_out[k]];
+        const double re = static_cast<double>(v.x), im = static_cast<double>(v.y);
+        acc[k] += f * (re * re + im * im);
+      }
+    __syncthreads();
+  }
+  double *out = partial + ((size_t)sub * n3 + z) * n2 * n1 + (size_t)y0 * n1;
+#pragma unroll
+  for (int k = 0; k < kDensityPPT; ++k) {
+    const int i = tid + k * kNT;
+    if (i < npt) out[i] = acc[k];
+  }
+}
+
+// rho[i] = (accumulate ? rho[i] : 0) + scale * sum_sub partial[sub][i], sub in order.
+__global__ __launch_bounds__(256) void density_reduce(const double *__restrict__ partial,
+                                                      int nsub, long npts, double scale,
+                                                      double *__restrict__ rho, int accumulate) {
+  for (long i = blockIdx.x * 256L + threadIdx.x; i < npts; i += (long)gridDim.x * 256) {
+    double t = 0.0;
+    for (int s = 0; s < nsub; ++s) t += partial[(size_t)s * npts + i];
+    rho[i] = (accumulate ? rho[i] : 0.0) + scale * t;
+  }
+}
+
 // Box sizes with a compiled lane-pair kernel (single precision).
 #define QEH_PAIR_SIZES(X) \
   X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(90)
@@ -698,11 +792,64 @@ hipError_t k2_pair_impl(const qeh_ctx *c, int nbk) {
   }
 }
 
+template <typename C>
+hipError_t density_block_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big_v,
+                              const double *occ_d, double *partial) {
+  using R = typename real_of<C>::type;
+  (void)sizeof(R);
+  const C *tw = reinterpret_cast<const C *>(c->d.tw);
+  const SplitGeom &g = c->spg;
+  C *big = reinterpret_cast<C *>(big_v);
+  const int ncg = (c->ext + g.cg - 1) / g.cg;
+  const unsigned planes = (unsigned)nbk * c->n3;
+  allow_lds(k2a_columns_inv<C>, g.lds_col);
+  hipLaunchKernelGGL(k2a_columns_inv<C>, dim3(planes * ncg), dim3(kNT), g.lds_col, c->stream,
+                     reinterpret_cast<const C *>(c->d.sbuf), big, c->d.tidx_dit, c->d.colstart,
+                     tw + c->tw_off[1], c->dy, c->nst, c->n3, c->ext, c->pg.ldT, g.cg, ncg,
+                     g.cg_div, g.cglast_div);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
+  allow_lds(k2d_rows_density<C>, dg.lds);
+  hipLaunchKernelGGL(k2d_rows_density<C>, dim3((unsigned)nsub * c->n3 * dg.ngroups), dim3(kNT),
+                     dg.lds, c->stream, big, occ_d, partial, c->d.xin, tw + c->tw_off[0], c->dx,
+                     c->n2, c->n3, c->ext, dg.rg, c->pg.ldR, dg.ngroups, nbk, dg.bsub, dg.rg_div,
+                     dg.rglast_div);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
   const size_t c = prec == QEH_FP64 ? 16 : 8;
   return c * ((size_t)ext * g.ldT + (size_t)g.rc * g.ldR + n1 + n2) + 4 * (size_t)n1;
+}
+
+bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
+  const int n1 = c->n1, n2 = c->n2;
+  const size_t cs = c->prec == QEH_FP64 ? 16 : 8;
+  dg->bsub = 16;
+  dg->rg = std::max(1, std::min(n2, kDensityPPT * kNT / n1));
+  if ((size_t)dg->rg * n1 > (size_t)kDensityPPT * kNT) return false;
+  dg->ngroups = (n2 + dg->rg - 1) / dg->rg;
+  dg->rg_div = make_fastdiv(dg->rg);
+  dg->rglast_div = make_fastdiv(n2 - (dg->ngroups - 1) * dg->rg);
+  dg->lds = cs * ((size_t)dg->rg * c->pg.ldR + n1) + 4 * (size_t)n1;
+  return dg->lds <= (size_t)kLdsMax && c->spg.lds_col <= (size_t)kLdsMax;
+}
+
+hipError_t launch_density_block(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big,
+                                 const double *occ_d, double *partial) {
+  return c->prec == QEH_FP64 ? density_block_impl<double2>(c, dg, nbk, big, occ_d, partial)
+                             : density_block_impl<float2>(c, dg, nbk, big, occ_d, partial);
+}
+
+hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
+                                 double *rho, int accumulate, hipStream_t s) {
+  const int blocks = (int)std::min<long>((npts + 255) / 256, 8192);
+  hipLaunchKernelGGL(density_reduce, dim3(blocks), dim3(256), 0, s, partial, nsub, npts, scale,
+                     rho, accumulate);
+  return hipGetLastError();
 }
 
 bool pair_plane_supported(int prec, int n1, int n2) {

@@ -73,6 +73,7 @@ struct DevMaps {
   int *gmap;         // [npw] s*ldz + digit-reversed z position
   int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2); the lane-pair
                      // kernel takes natural y (pos_y = identity)
+  int *tidx_dit;     // [nst] the same with pos_y the y-DIT input position (always)
   int *xin;          // [N1] column c whose h sits at x-DIT input position p, or -1
   double *kin;       // [npw] |k+G|^2
   double *hdiag;     // [npw] diag(H)
@@ -111,6 +112,7 @@ struct qeh_ctx {
   char *arena = nullptr;
   size_t arena_bytes = 0;
   double vmean = 0.0;
+  double omega = 0.0;   // cell volume
   // profiling
   bool prof = false;
   double stage_ms[QEH_NSTAGES] = {0};
@@ -136,6 +138,20 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g);
 // box, and its LDS bytes for pb planes of ext columns.
 bool pair_plane_supported(int prec, int n1, int n2);
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
+
+// Charge density: row groups of rg rows, subgroups of bsub bands.
+struct DensityGeom {
+  int rg, ngroups, bsub;
+  size_t lds;
+  FastDiv rg_div, rglast_div;
+};
+bool density_geometry(const qeh_ctx *c, DensityGeom *dg);
+// One block of nbk bands whose sticks K1 has written: inverse y columns into
+// big, then partial[sub][z][y][x] = sum over subgroup sub of occ_b |psi_b|^2.
+hipError_t launch_density_block(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big,
+                                const double *occ_d, double *partial);
+hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
+                                 double *rho, int accumulate, hipStream_t s);
 
 // ---- complex GEMM launchers (gemm_kernels.hip) ----------------------------
 // C[m][n] (+)= sum_k opA(A[m][k]) opB(B(k,n)), complex, MFMA.
