@@ -11,10 +11,12 @@ projector GEMMs, FP64 psi / kinetic); the plain FP64 form is reported beside
 it.  Per-kernel device times come from HIP events recorded on the context
 stream during the timed steps; ``roofline`` reports the dominant kernel.
 ``cpu_baseline`` times the FP64 oracle's H|psi> on a bounded band sample on
-the host cores.  Davidson time-to-solution is reported when --davidson is set.
+the host cores.  The charge density of the same 128 bands (both forms) is
+timed beside it (``density``).  Davidson time-to-solution is reported when
+--davidson is set.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--davidson] [--serve SECONDS]
-                      [--no-cpu]
+                      [--no-cpu] [--no-density]
 """
 
 from __future__ import annotations
@@ -71,7 +73,18 @@ def algorithmic(stage, shape, prec, nb):
         return "mfma", 8.0 * nb * nkb * npw
     if stage == "dscale":
         return "hbm", nb * nkb * c * 2
+    ext = shape["ext"]
+    nsub = -(-nb // DENSITY_BSUB)
+    if stage == "density_columns":   # read sticks, write inverse-y columns
+        return "hbm", nb * c * (nst * n3 + ext * n2 * n3)
+    if stage == "density_rows":      # read the columns, write the subgroup partial planes
+        return "hbm", nb * c * ext * n2 * n3 + 8 * nsub * nfft
+    if stage == "density_reduce":    # read the partial planes, write rho
+        return "hbm", 8 * nsub * nfft + 8 * nfft
     raise KeyError(stage)
+
+
+DENSITY_BSUB = 16   # bands per density subgroup (library constant)
 
 
 def plane_bytes(shape, prec, nb):
@@ -128,6 +141,32 @@ def time_apply(q, torch, cell, prec, nb, steps, warmup):
     shape = ctx.info()
     ctx.close()
     return dt, stages, shape
+
+
+def time_density(q, torch, cell, prec, nb, steps, warmup):
+    """Charge density of nb bands (occupation 2 each): seconds for `steps`
+    calls, per-stage device times, context shape."""
+    ctx = q.Context.from_cell(cell, precision=prec, block=nb)
+    psi = torch.from_numpy(__import__("cellgen").make_psi0(cell.npw, nb, seed=10502)).cuda()
+    occ = np.full(nb, 2.0)
+    info = ctx.info()
+    rho = torch.empty((info["n3"], info["n2"], info["n1"]), dtype=torch.float64, device="cuda")
+    work = torch.empty(ctx.density_plan(), dtype=torch.uint8, device="cuda")
+    for _ in range(warmup):
+        ctx.density(psi, occ, out=rho, work=work)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.density(psi, occ, out=rho, work=work)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = ctx.stage_times()
+    ctx.profile(False)
+    n = np.prod(cell.fft)
+    integral = float(rho.sum()) * abs(np.linalg.det(cell.lattice)) / n
+    ctx.close()
+    return dt, stages, info, integral
 
 
 def roofline_for(stages, shape, prec, nb):
@@ -263,6 +302,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--davidson", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the charge density leg (128 bands, both forms)")
     ap.add_argument("--serve", type=float, default=0.0,
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -326,6 +367,21 @@ def main():
                      "peak": b["peak"], "unit": b["unit"], "frac": b["frac"],
                      "traffic": stored_traffic(mixed["best"], q.QEH_MIXED)},
     }
+    if not a.no_density:
+        dens = {}
+        for prec in (q.QEH_MIXED, q.QEH_FP64):
+            dt, stages, shape, integral = time_density(q, torch, cell, prec, nb, a.steps,
+                                                       a.warmup)
+            _, per = roofline_for(stages, shape, prec, nb)
+            dens["mixed" if prec else "fp64"] = dict(
+                ms_per_call=dt / a.steps * 1e3, band_densities_per_s=nb * a.steps / dt,
+                integral=integral, occupation_sum=2.0 * nb, kernels=per)
+            print("# density %s: %.3f ms/call; kernels: %s" % (
+                "mixed" if prec else "fp64", dt / a.steps * 1e3,
+                ", ".join("%s %.1f us (%.2f of %s peak)" % (k, v["avg_us"], v["frac"],
+                                                            v["bound"])
+                          for k, v in per.items())), file=sys.stderr, flush=True)
+        out["density"] = dens
     if a.davidson:
         psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
         dav = {}

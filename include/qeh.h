@@ -168,12 +168,14 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
                         double *eig, const qeh_dav_opts *opts, void *work,
                         size_t work_bytes, qeh_dav_info *info);
 
-/* Per-stage device timing of H application (HIP events on the context
- * stream).  Stages: 0 scatter+z-FFT, 1 plane pass, 2 z-FFT+gather+kinetic,
- * 3 beta^H psi, 4 D scaling, 5 beta ps accumulate.  enable=1 starts
- * recording (and clears totals); qeh_ctx_stage_times synchronises the
+/* Per-stage device timing of H application and of the charge density (HIP
+ * events on the context stream).  Stages: 0 scatter+z-FFT, 1 plane pass,
+ * 2 z-FFT+gather+kinetic, 3 beta^H psi, 4 D scaling, 5 beta ps accumulate,
+ * 6 density inverse y columns, 7 density inverse x rows + |psi|^2 sums,
+ * 8 density subgroup reduce (qeh_density's K1 counts as stage 0).  enable=1
+ * starts recording (and clears totals); qeh_ctx_stage_times synchronises the
  * stream and returns total milliseconds and launch counts per stage. */
-#define QEH_NSTAGES 6
+#define QEH_NSTAGES 9
 qeh_status qeh_ctx_profile(qeh_ctx *ctx, int enable);
 qeh_status qeh_ctx_stage_times(qeh_ctx *ctx, double *ms, long *launches, int nstages);
 

@@ -28,9 +28,9 @@ QEH_ERR_DEVICE = -7
 QEH_ERR_BUSY = -8
 QEH_FP64 = 0
 QEH_MIXED = 1
-NSTAGES = 6
+NSTAGES = 9
 STAGE_NAMES = ["k1_scatter_zinv", "k2_plane", "k3_zfwd_gather", "calbec_gemm", "dscale",
-               "addnl_gemm"]
+               "addnl_gemm", "density_columns", "density_rows", "density_reduce"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libqeh.so is not built: run `python -m paper_2104_10502_amd.build` "

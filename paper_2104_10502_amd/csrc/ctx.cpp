@@ -829,12 +829,26 @@ qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const 
     // them on the same stream
     e = hipMemcpyAsync(occ_d, occ + b0, 8 * (size_t)nbk, hipMemcpyHostToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(e, "occupation upload");
-    e = launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
+    {
+      StageGuard g(c, 0);
+      e = launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
+    }
     if (e != hipSuccess) return hip_fail(e, "K1 launch");
-    e = launch_density_block(c, dg, nbk, W + w.big, occ_d, partial);
-    if (e != hipSuccess) return hip_fail(e, "density launch");
+    {
+      StageGuard g(c, 6);
+      e = launch_density_columns(c, nbk, W + w.big);
+    }
+    if (e != hipSuccess) return hip_fail(e, "density columns launch");
+    {
+      StageGuard g(c, 7);
+      e = launch_density_rows(c, dg, nbk, W + w.big, occ_d, partial);
+    }
+    if (e != hipSuccess) return hip_fail(e, "density rows launch");
     const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
-    e = launch_density_reduce(partial, nsub, npts, scale, rho, b0 > 0 ? 1 : 0, c->stream);
+    {
+      StageGuard g(c, 8);
+      e = launch_density_reduce(partial, nsub, npts, scale, rho, b0 > 0 ? 1 : 0, c->stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "density reduce launch");
   }
   // occ is a caller's host array: the copies above must be complete on return

@@ -792,11 +792,7 @@ hipError_t k2_pair_impl(const qeh_ctx *c, int nbk) {
   }
 }
 
-template <typename C>
-hipError_t density_block_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big_v,
-                              const double *occ_d, double *partial) {
-  using R = typename real_of<C>::type;
-  (void)sizeof(R);
+template <typename C> hipError_t density_columns_impl(const qeh_ctx *c, int nbk, void *big_v) {
   const C *tw = reinterpret_cast<const C *>(c->d.tw);
   const SplitGeom &g = c->spg;
   C *big = reinterpret_cast<C *>(big_v);
@@ -807,14 +803,19 @@ hipError_t density_block_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, 
                      reinterpret_cast<const C *>(c->d.sbuf), big, c->d.tidx_dit, c->d.colstart,
                      tw + c->tw_off[1], c->dy, c->nst, c->n3, c->ext, c->pg.ldT, g.cg, ncg,
                      g.cg_div, g.cglast_div);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <typename C>
+hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
+                             const double *occ_d, double *partial) {
+  const C *tw = reinterpret_cast<const C *>(c->d.tw);
   const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
   allow_lds(k2d_rows_density<C>, dg.lds);
   hipLaunchKernelGGL(k2d_rows_density<C>, dim3((unsigned)nsub * c->n3 * dg.ngroups), dim3(kNT),
-                     dg.lds, c->stream, big, occ_d, partial, c->d.xin, tw + c->tw_off[0], c->dx,
-                     c->n2, c->n3, c->ext, dg.rg, c->pg.ldR, dg.ngroups, nbk, dg.bsub, dg.rg_div,
-                     dg.rglast_div);
+                     dg.lds, c->stream, reinterpret_cast<const C *>(big), occ_d, partial,
+                     c->d.xin, tw + c->tw_off[0], c->dx, c->n2, c->n3, c->ext, dg.rg,
+                     c->pg.ldR, dg.ngroups, nbk, dg.bsub, dg.rg_div, dg.rglast_div);
   return hipGetLastError();
 }
 
@@ -838,10 +839,15 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
   return dg->lds <= (size_t)kLdsMax && c->spg.lds_col <= (size_t)kLdsMax;
 }
 
-hipError_t launch_density_block(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big,
-                                 const double *occ_d, double *partial) {
-  return c->prec == QEH_FP64 ? density_block_impl<double2>(c, dg, nbk, big, occ_d, partial)
-                             : density_block_impl<float2>(c, dg, nbk, big, occ_d, partial);
+hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big) {
+  return c->prec == QEH_FP64 ? density_columns_impl<double2>(c, nbk, big)
+                             : density_columns_impl<float2>(c, nbk, big);
+}
+
+hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
+                               const double *occ_d, double *partial) {
+  return c->prec == QEH_FP64 ? density_rows_impl<double2>(c, dg, nbk, big, occ_d, partial)
+                             : density_rows_impl<float2>(c, dg, nbk, big, occ_d, partial);
 }
 
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,

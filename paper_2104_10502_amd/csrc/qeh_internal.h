@@ -148,8 +148,9 @@ struct DensityGeom {
 bool density_geometry(const qeh_ctx *c, DensityGeom *dg);
 // One block of nbk bands whose sticks K1 has written: inverse y columns into
 // big, then partial[sub][z][y][x] = sum over subgroup sub of occ_b |psi_b|^2.
-hipError_t launch_density_block(const qeh_ctx *c, const DensityGeom &dg, int nbk, void *big,
-                                const double *occ_d, double *partial);
+hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big);
+hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
+                               const double *occ_d, double *partial);
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
                                  double *rho, int accumulate, hipStream_t s);
 
