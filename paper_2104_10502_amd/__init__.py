@@ -368,9 +368,10 @@ class Context:
         return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(NSTAGES)}
 
     def info(self):
-        out = (ctypes.c_long * 10)()
-        _check(_lib.qeh_ctx_info(self._h, out, 10), "qeh_ctx_info")
-        keys = ["npw", "nst", "nkb", "n1", "n2", "n3", "ext", "block", "precision", "plane_path"]
+        out = (ctypes.c_long * 11)()
+        _check(_lib.qeh_ctx_info(self._h, out, 11), "qeh_ctx_info")
+        keys = ["npw", "nst", "nkb", "n1", "n2", "n3", "ext", "block", "precision", "plane_path",
+                "stick_path"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -214,7 +214,7 @@ size_t bump(size_t *cur, size_t bytes) {
 }
 
 struct Geometry {
-  int nkb, nd, nchunk, nsplit, kchunk, plane_path;
+  int nkb, nd, nchunk, nsplit, kchunk, plane_path, zpair;
   FftDim dx, dy, dz;
   PlaneGeom pg;
   SplitGeom spg;
@@ -304,6 +304,13 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
       g->pg.pb = pb;
       g->pg.lds_pair = pair_plane_lds_bytes(prec, hm.ext, n2, pb);
     }
+  }
+  // lane-pair K1 / K3 (single precision, N3 with a compiled form);
+  // QEH_STICK_KERNEL=generic keeps the LDS-pass kernels (test hook)
+  g->zpair = 0;
+  if (pair_z_supported(prec, n3) && pair_z_lds_bytes(n3) <= (size_t)kLdsMax) {
+    const char *kern = std::getenv("QEH_STICK_KERNEL");
+    if (!(kern && std::strcmp(kern, "generic") == 0)) g->zpair = 1;
   }
   g->pg.ext_div = make_fastdiv(hm.ext);
   g->pg.rc_div = make_fastdiv(g->pg.rc);
@@ -458,6 +465,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->block = cell->block;
   c->prec = cell->precision;
   c->plane_path = g.plane_path;
+  c->zpair = g.zpair;
   c->nsplit = g.nsplit;
   c->kchunk = g.kchunk;
   c->nchunk = g.nchunk;
@@ -500,7 +508,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   std::vector<int> gmap(npw), tidx(hm.nst), tidx_dit(hm.nst), xin(n1, -1);
   for (int s = 0; s < hm.nst; ++s) {
     for (int gg = hm.stick_off[s]; gg < hm.stick_off[s + 1]; ++gg)
-      gmap[gg] = s * c->sg.ldz + fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3));
+      gmap[gg] = s * c->sg.ldz + (c->zpair ? imod(cell->miller[3 * gg + 2], n3)
+                                           : fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3)));
     const int ky = imod(hm.stick_k[s], n2);
     tidx_dit[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, ky);
     tidx[s] = c->plane_path == 2 ? (hm.stick_h[s] - hm.hmin) * c->pg.ldT + ky : tidx_dit[s];
@@ -918,9 +927,9 @@ qeh_status qeh_ctx_stage_times(qeh_ctx *c, double *ms, long *launches, int nstag
 
 qeh_status qeh_ctx_info(const qeh_ctx *c, long *out, int n) {
   if (!c || !out) return invalid("null argument");
-  const long v[10] = {c->npw, c->nst, c->nkb, c->n1, c->n2, c->n3, c->ext, c->block, c->prec,
-                      c->plane_path};
-  for (int i = 0; i < n && i < 10; ++i) out[i] = v[i];
+  const long v[11] = {c->npw, c->nst, c->nkb, c->n1, c->n2, c->n3, c->ext, c->block, c->prec,
+                      c->plane_path, c->zpair};
+  for (int i = 0; i < n && i < 11; ++i) out[i] = v[i];
   return QEH_OK;
 }
 

@@ -598,6 +598,101 @@ __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__
 #define QEH_PAIR_SIZES(X) \
   X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(90)
 
+// ---------------------------------------------------------------- K1 / K3, lane pairs
+// Mixed form with N3 = N even and a compiled form of N: the z transforms held
+// in registers by lane pairs (pair_inv / pair_fwd).  The sphere runs of S
+// consecutive sticks are staged through LDS at natural z positions (gmap holds
+// s*ldz + (l mod N3) for this path) so that the psi reads and H psi writes stay
+// coalesced; each pair then loads its z line from LDS once.  K1 writes the
+// transformed line straight to the plane-major stick buffer: the lanes of a
+// wave hold consecutive sticks, so every store covers two runs of consecutive
+// sticks.  K3 reads the same way, transforms forward, and stages the result
+// for the sphere gather.
+constexpr int kPairSticks = 64;   // 37 KB of LDS at N = 72: four workgroups per CU
+
+template <int N>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 : 2))) void
+k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
+        const int *__restrict__ stick_off, const int *__restrict__ gmap, int nst,
+        float2 *__restrict__ psi32, int npw) {
+  constexpr int LD = N | 1, M = N / 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2 *tile = reinterpret_cast<float2 *>(smem_raw);
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int s0 = blockIdx.x * kPairSticks;
+  const int ns = min(kPairSticks, nst - s0);
+  const float2 zero = make_float2(0.f, 0.f);
+  for (int i = tid; i < ns * LD; i += kNT) tile[i] = zero;
+  __syncthreads();
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  const double2 *pb = psi + (size_t)b * ldpsi;
+  const int base = s0 * LD;
+  float2 *p32 = psi32 + (size_t)b * npw;
+  for (int g = g0 + tid; g < g1; g += kNT) {
+    const double2 v = pb[g];
+    const float2 f = make_float2((float)v.x, (float)v.y);
+    tile[gmap[g] - base] = f;
+    p32[g] = f;
+  }
+  __syncthreads();
+  float2 *out = sbuf + (size_t)b * N * nst + s0;
+  for (int j = tid; j < 2 * ns; j += kNT) {
+    const bool odd = j & 1;
+    const int st = j >> 1;
+    const float2 *line = tile + st * LD;
+    float2 v[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) v[n] = line[2 * n + odd];
+    regfft::pair_inv<float2, N>(v, odd);
+    float2 *o = out + (size_t)(odd ? M : 0) * nst + st;
+#pragma unroll
+    for (int k = 0; k < M; ++k) o[(size_t)k * nst] = v[k];
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 : 2))) void
+k3_pair(const float2 *__restrict__ sbuf, const double2 *__restrict__ psi, int ldpsi,
+        double2 *__restrict__ hpsi, int ldh, const double *__restrict__ kin,
+        const int *__restrict__ stick_off, const int *__restrict__ gmap, int nst, int add_kin) {
+  constexpr int LD = N | 1, M = N / 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2 *tile = reinterpret_cast<float2 *>(smem_raw);
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int s0 = blockIdx.x * kPairSticks;
+  const int ns = min(kPairSticks, nst - s0);
+  const float2 *in = sbuf + (size_t)b * N * nst + s0;
+  for (int j = tid; j < 2 * ns; j += kNT) {
+    const bool odd = j & 1;
+    const int st = j >> 1;
+    const float2 *ip = in + (size_t)(odd ? M : 0) * nst + st;
+    float2 v[M];
+#pragma unroll
+    for (int x = 0; x < M; ++x) v[x] = ip[(size_t)x * nst];
+    regfft::pair_fwd<float2, N>(v, odd);
+    float2 *line = tile + st * LD;
+#pragma unroll
+    for (int m = 0; m < M; ++m) line[2 * m + odd] = v[m];
+  }
+  __syncthreads();
+  const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
+  const int base = s0 * LD;
+  const double2 *pb = psi + (size_t)b * ldpsi;
+  double2 *hb = hpsi + (size_t)b * ldh;
+  for (int g = g0 + tid; g < g1; g += kNT) {
+    double2 r = ccast<double2>(tile[gmap[g] - base]);
+    if (add_kin) {
+      const double2 p = pb[g];
+      const double k = kin[g];
+      r.x += k * p.x;
+      r.y += k * p.y;
+    }
+    hb[g] = r;
+  }
+}
+
 // ---------------------------------------------------------------- K2, split
 // Planes whose column tile does not fit in LDS go through an HBM scratch
 // big[b][z][c][y] (one x-extent column of N2 values after another):
@@ -819,6 +914,47 @@ hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, c
   return hipGetLastError();
 }
 
+template <int N> hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  const size_t lds = 8 * (size_t)kPairSticks * (N | 1);
+  allow_lds(k1_pair<N>, lds);
+  hipLaunchKernelGGL(k1_pair<N>, dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk), dim3(kNT),
+                     lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
+                     c->d.stick_off, c->d.gmap, c->nst, c->d.psi32, c->npw);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t k3_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
+                          double2 *hpsi, int ldh, int add_kin) {
+  const size_t lds = 8 * (size_t)kPairSticks * (N | 1);
+  allow_lds(k3_pair<N>, lds);
+  hipLaunchKernelGGL(k3_pair<N>, dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk), dim3(kNT),
+                     lds, c->stream, reinterpret_cast<const float2 *>(c->d.sbuf), psi, ldpsi,
+                     hpsi, ldh, c->d.kin, c->d.stick_off, c->d.gmap, c->nst, add_kin);
+  return hipGetLastError();
+}
+
+hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  switch (c->n3) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return k1_pair_launch<NN>(c, nbk, psi, ldpsi);
+    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t k3_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, double2 *hpsi,
+                        int ldh, int add_kin) {
+  switch (c->n3) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return k3_pair_launch<NN>(c, nbk, psi, ldpsi, hpsi, ldh, add_kin);
+    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
@@ -858,6 +994,10 @@ hipError_t launch_density_reduce(const double *partial, int nsub, long npts, dou
   return hipGetLastError();
 }
 
+bool pair_z_supported(int prec, int n3) { return pair_plane_supported(prec, n3, n3); }
+
+size_t pair_z_lds_bytes(int n3) { return 8 * (size_t)kPairSticks * (n3 | 1); }
+
 bool pair_plane_supported(int prec, int n1, int n2) {
   if (prec != QEH_MIXED || n1 != n2) return false;
   switch (n1) {
@@ -880,6 +1020,7 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
 }
 
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  if (c->zpair) return k1_pair_impl(c, nbk, psi, ldpsi);
   return c->prec == QEH_FP64 ? k1_impl<double2>(c, nbk, psi, ldpsi)
                              : k1_impl<float2>(c, nbk, psi, ldpsi);
 }
@@ -893,6 +1034,7 @@ hipError_t launch_k2(const qeh_ctx *c, int nbk) {
 
 hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, double2 *hpsi,
                      int ldh, int add_kinetic) {
+  if (c->zpair) return k3_pair_impl(c, nbk, psi, ldpsi, hpsi, ldh, add_kinetic);
   return c->prec == QEH_FP64 ? k3_impl<double2>(c, nbk, psi, ldpsi, hpsi, ldh, add_kinetic)
                              : k3_impl<float2>(c, nbk, psi, ldpsi, hpsi, ldh, add_kinetic);
 }

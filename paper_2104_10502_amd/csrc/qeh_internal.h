@@ -70,7 +70,8 @@ struct StickGeom {
 // Device arrays of one context, all inside the caller's arena.
 struct DevMaps {
   int *stick_off;    // [nst+1] first G of each stick
-  int *gmap;         // [npw] s*ldz + digit-reversed z position
+  int *gmap;         // [npw] s*ldz + digit-reversed z position (natural z for the
+                     // lane-pair K1 / K3, whose ldz is N3 | 1 as well)
   int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2); the lane-pair
                      // kernel takes natural y (pos_y = identity)
   int *tidx_dit;     // [nst] the same with pos_y the y-DIT input position (always)
@@ -100,6 +101,7 @@ struct qeh_ctx {
   int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
   int block = 0, prec = 0;
   int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel
+  int zpair = 0;        // 1: lane-pair K1 / K3 (gmap at natural z)
   int nsplit = 1, kchunk = 0;
   int nchunk = 0;
   qeh::FftDim dx{}, dy{}, dz{};
@@ -137,6 +139,8 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g);
 // Lane-pair plane kernel: whether a compiled form exists for this precision and
 // box, and its LDS bytes for pb planes of ext columns.
 bool pair_plane_supported(int prec, int n1, int n2);
+bool pair_z_supported(int prec, int n3);
+size_t pair_z_lds_bytes(int n3);
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 
 // Charge density: row groups of rg rows, subgroups of bsub bands.

@@ -212,3 +212,44 @@ def test_pair_matches_generic_c2():
         del os.environ["QEH_PLANE_KERNEL"]
     assert ca.info()["plane_path"] == 2 and cb.info()["plane_path"] == 0
     assert _rel_l2(a, b).max() < 2e-6
+
+
+@pytest.mark.parametrize("kernel", ["pair", "generic"])
+def test_apply_h_c1_mixed_stick_kernels(kernel, monkeypatch):
+    # the lane-pair z transforms (K1 / K3) and the LDS-pass ones
+    if kernel == "generic":
+        monkeypatch.setenv("QEH_STICK_KERNEL", "generic")
+    c = cell("c1")
+    psi = cellgen.make_psi0(c.npw, 16, seed=45)
+    got, ctx = run(c, psi, 1, 16)
+    assert ctx.info()["stick_path"] == (1 if kernel == "pair" else 0)
+    err = _rel_l2(got, oracle.apply_h(c, psi))
+    assert err.max() < 1e-5, err.max()
+
+
+def test_stick_path_choice():
+    q = _qeh()
+    c1 = cell("c1")
+    assert q.Context.from_cell(c1, precision=1, block=4).info()["stick_path"] == 1
+    assert q.Context.from_cell(c1, precision=0, block=4).info()["stick_path"] == 0
+    # N3 = 30 has a compiled size, 21 x 25 planes do not: pair sticks with
+    # generic planes (and the reverse on the radix-7 box 21 x 25 x 28), both
+    # checked against the oracle
+    for fft, sticks in (((21, 25, 30), 1), ((21, 25, 28), 0)):
+        t = cellgen.make_cell("t", lattice=np.diag([7.0, 8.0, 9.5]), frac=np.array(
+            [[0.1, 0.2, 0.3], [0.6, 0.5, 0.9]]), kpt=(0.11, -0.07, 0.23), ecutwfc=12.0,
+            fft=fft, proj="s2pd", dfixed=False, nbnd=6)
+        psi = cellgen.make_psi0(t.npw, 6, seed=47)
+        got, ctx = run(t, psi, 1, 4)
+        assert ctx.info()["stick_path"] == sticks and ctx.info()["plane_path"] == 0
+        assert _rel_l2(got, oracle.apply_h(t, psi)).max() < 1e-5
+
+
+def test_pair_sticks_match_generic_c2(monkeypatch):
+    c = cell("c2")
+    psi = cellgen.make_psi0(c.npw, 4, seed=46)
+    a, ca = run(c, psi, 1, 4)
+    monkeypatch.setenv("QEH_STICK_KERNEL", "generic")
+    b, cb = run(c, psi, 1, 4)
+    assert ca.info()["stick_path"] == 1 and cb.info()["stick_path"] == 0
+    assert _rel_l2(a, b).max() < 2e-6
