@@ -12,8 +12,9 @@ it.  Per-kernel device times come from HIP events recorded on the context
 stream during the timed steps; ``roofline`` reports the dominant kernel.
 ``cpu_baseline`` times the FP64 oracle's H|psi> on a bounded band sample on
 the host cores.  The charge density of the same 128 bands (both forms) is
-timed beside it (``density``).  Davidson time-to-solution is reported when
---davidson is set.
+timed beside it (``density``), and a 5 s replay of the served request trace
+(Poisson arrivals at 20 req/s) reports p50/p99 latency (``serve``; --serve 0
+skips it).  Davidson time-to-solution is reported when --davidson is set.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--davidson] [--serve SECONDS]
                       [--no-cpu] [--no-density]
@@ -262,12 +263,17 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
             lag = max(lag, -delay)
         tickets.append(srv.submit(cells, psis, cells[0].nbnd, precision=q.QEH_MIXED))
     res = {}
+    t_note = time.perf_counter()
     while len(res) < len(tickets):
         for t in tickets:
             if t not in res:
                 o = srv.poll(t)
                 if o is not None:
                     res[t] = o
+        if time.perf_counter() - t_note > 20.0:
+            t_note = time.perf_counter()
+            print("# serve: %d of %d requests done" % (len(res), len(tickets)), file=sys.stderr,
+                  flush=True)
         time.sleep(0.005)
     st = srv.stats()
     srv.close()
@@ -295,6 +301,34 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
                 generation_s=t_gen)
 
 
+def serve_child_main(a):
+    """Served-trace leg (child process): trace on the host, wait for the
+    parent's go, replay, print one JSON line."""
+    served = make_trace(a.serve, a.serve_rate)
+    print("# serve: trace of %d requests ready" % len(served[0]), file=sys.stderr, flush=True)
+    print("ready", flush=True)
+    if sys.stdin.readline().strip() != "go":
+        return
+    import paper_2104_10502_amd as q
+    res = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate, slots=a.serve_slots)
+    print(json.dumps(res), flush=True)
+
+
+def run_serve_child(child, timeout_s=300.0):
+    """Release the served-trace child and collect its result (or its failure)."""
+    import subprocess
+    try:
+        out, _ = child.communicate("go\n", timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        child.kill()
+        child.communicate()
+        return {"error": "served-trace leg exceeded %.0f s" % timeout_s}
+    lines = [ln for ln in (out or "").splitlines() if ln.startswith("{")]
+    if child.returncode != 0 or not lines:
+        return {"error": "served-trace leg ended with status %s" % child.returncode}
+    return json.loads(lines[-1])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,9 +338,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the charge density leg (128 bands, both forms)")
-    ap.add_argument("--serve", type=float, default=0.0,
+    ap.add_argument("--serve", type=float, default=5.0,
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (the reference "
@@ -316,12 +351,29 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.serve_child:
+        serve_child_main(a)
+        return
+    # The served-trace leg runs in a child process, started here before this
+    # process touches the GPU: it builds the trace on the host, then waits for
+    # the parent's go (after the timed H|psi> and density work) before it
+    # initialises its own device context.  A failure there cannot take down this
+    # benchmark line.
+    child = None
     if a.serve > 0:
+        import subprocess
+        env = dict(os.environ)
         # one hardware queue per few job streams, so that a long dense eigensolve
         # on one stream does not hold up the jobs sharing its queue (HIP reads
         # this at initialisation; <= 32)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
-    served = make_trace(a.serve, a.serve_rate) if a.serve > 0 else None
+        env.setdefault("GPU_MAX_HW_QUEUES", "16")
+        child = subprocess.Popen(
+            [sys.executable, os.path.abspath(__file__), "--serve-child", "--serve", str(a.serve),
+             "--serve-rate", str(a.serve_rate), "--serve-slots", str(a.serve_slots)],
+            stdin=subprocess.PIPE, stdout=subprocess.PIPE, env=env, text=True)
+        # host-side trace generation uses all cores: let it finish before the
+        # timed device work starts
+        child.stdout.readline()
     import torch
     import cellgen
     import paper_2104_10502_amd as q
@@ -406,9 +458,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if a.serve > 0:
-        out["serve"] = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate,
-                                   slots=a.serve_slots)
+    if child is not None:
+        out["serve"] = run_serve_child(child)
         print("# serve: %s" % json.dumps(out["serve"]), file=sys.stderr, flush=True)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cell)

@@ -35,6 +35,11 @@ STAGE_NAMES = ["k1_scatter_zinv", "k2_plane", "k3_zfwd_gather", "calbec_gemm", "
 if not os.path.exists(LIB_PATH):
     raise ImportError("libqeh.so is not built: run `python -m paper_2104_10502_amd.build` "
                       "(or __graft_entry__.build()) first; there is no non-GPU fallback")
+# PyTorch's HIP runtime is loaded before the library, so that the library binds
+# to the same runtime instance whichever module a process imports first (two
+# runtimes in one process do not share devices).
+import torch as _torch_runtime  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)

@@ -789,7 +789,7 @@ qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldp
 // ---- charge density (charge density generation among the ported kernels,
 // section "Evolution of the GPU-enabled version")
 struct DensityWork {
-  size_t big, partial, occ, total;
+  size_t big, partial, occ, zcol, total;
 };
 
 DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
@@ -801,6 +801,7 @@ DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
   w.big = bump(&cur, cs * (size_t)c->block * c->n3 * c->ext * c->n2);
   w.partial = bump(&cur, 8 * (size_t)nsub * nfft);
   w.occ = bump(&cur, 8 * (size_t)c->block);
+  w.zcol = bump(&cur, 8 * (size_t)c->n2);
   w.total = cur;
   return w;
 }
@@ -832,6 +833,9 @@ qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const 
     return e == hipSuccess ? QEH_OK : hip_fail(e, "density reduce launch");
   }
   const double2 *p = reinterpret_cast<const double2 *>(psi);
+  // the zero column of the lane-pair rows (a kernel, not a memset)
+  e = launch_fill_int(reinterpret_cast<int *>(W + w.zcol), 2 * c->n2, 0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "density zero column");
   for (int b0 = 0; b0 < nb; b0 += c->block) {
     const int nbk = std::min(c->block, nb - b0);
     // the previous block's kernels read occ_d; the copy below is ordered after
@@ -850,7 +854,7 @@ qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const 
     if (e != hipSuccess) return hip_fail(e, "density columns launch");
     {
       StageGuard g(c, 7);
-      e = launch_density_rows(c, dg, nbk, W + w.big, occ_d, partial);
+      e = launch_density_rows(c, dg, nbk, W + w.big, occ_d, partial, W + w.zcol);
     }
     if (e != hipSuccess) return hip_fail(e, "density rows launch");
     const int nsub = (nbk + dg.bsub - 1) / dg.bsub;

@@ -15,6 +15,8 @@
 // natural in and digit-reversed out.  The permutations are folded into the
 // scatter / gather index tables, so no explicit reordering pass exists.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "cplx.h"
 #include "fft_radix.h"
@@ -583,6 +585,52 @@ __global__ __launch_bounds__(kNT) void k2d_rows_density(
   }
 }
 
+// Density rows on lane pairs (mixed form, N1 = N a compiled size): one
+// workgroup = one z plane x one subgroup of bands; the pair (y, l) loads row y
+// of each band from big with the x-extent column c at x position c (the shift
+// multiplies psi by a unit-modulus phase, which |psi|^2 does not see),
+// transforms it in registers and keeps its N/2 points' occ_b |psi_b|^2 sums in
+// double registers across the subgroup, in band order.
+template <int N>
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(2))) void k2d_rows_pair(
+    const float2 *__restrict__ big, const double *__restrict__ occ, double *__restrict__ partial,
+    const float2 *__restrict__ zcol, int n2, int n3, int ext, int nbk, int bsub) {
+  constexpr int M = N / 2;
+  const int z = blockIdx.x % n3;
+  const int sub = blockIdx.x / n3;
+  const int b0 = sub * bsub;
+  const int b1 = min(nbk, b0 + bsub);
+  const int j = threadIdx.x;
+  if (j >= 2 * n2) return;   // no barriers below
+  const bool odd = j & 1;
+  const int y = j >> 1;
+  const int l = odd ? 1 : 0;
+  double acc[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) acc[k] = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    const float2 *col = big + ((size_t)b * n3 + z) * ext * n2 + y;
+    float2 v[M];
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      // positions beyond the x-extent read a zero column in the workspace
+      const int c = 2 * n + l;
+      const float2 *src = c < ext ? col + (size_t)c * n2 : zcol + y;
+      v[n] = *src;
+    }
+    regfft::pair_inv<float2, N>(v, odd);
+    const double f = occ[b];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      const double re = v[k].x, im = v[k].y;
+      acc[k] += f * (re * re + im * im);
+    }
+  }
+  double *out = partial + (((size_t)sub * n3 + z) * n2 + y) * N + l * M;
+#pragma unroll
+  for (int k = 0; k < M; ++k) out[k] = acc[k];
+}
+
 // rho[i] = (accumulate ? rho[i] : 0) + scale * sum_sub partial[sub][i], sub in order.
 __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__ partial,
                                                       int nsub, long npts, double scale,
@@ -901,9 +949,29 @@ template <typename C> hipError_t density_columns_impl(const qeh_ctx *c, int nbk,
   return hipGetLastError();
 }
 
+template <int N>
+hipError_t density_rows_pair_launch(const qeh_ctx *c, const DensityGeom &dg, int nbk,
+                                    const void *big, const double *occ_d, double *partial,
+                                    const void *zcol) {
+  const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
+  hipLaunchKernelGGL(k2d_rows_pair<N>, dim3((unsigned)nsub * c->n3), dim3(kRT), 0, c->stream,
+                     reinterpret_cast<const float2 *>(big), occ_d, partial,
+                     reinterpret_cast<const float2 *>(zcol), c->n2, c->n3, c->ext, nbk, dg.bsub);
+  return hipGetLastError();
+}
+
 template <typename C>
 hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
-                             const double *occ_d, double *partial) {
+                             const double *occ_d, double *partial, const void *zcol) {
+  if (dg.pair) {
+    switch (c->n1) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return density_rows_pair_launch<NN>(c, dg, nbk, big, occ_d, partial, zcol);
+      QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+      default: return hipErrorInvalidValue;
+    }
+  }
   const C *tw = reinterpret_cast<const C *>(c->d.tw);
   const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
   allow_lds(k2d_rows_density<C>, dg.lds);
@@ -966,6 +1034,11 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
   const int n1 = c->n1, n2 = c->n2;
   const size_t cs = c->prec == QEH_FP64 ? 16 : 8;
   dg->bsub = 16;
+  // lane-pair rows: mixed form, N1 a compiled size, one pair per row of a plane
+  // (QEH_DENSITY_KERNEL=generic keeps the LDS-pass rows: test hook)
+  const char *kern = std::getenv("QEH_DENSITY_KERNEL");
+  dg->pair = pair_plane_supported(c->prec, n1, n1) && n1 <= 80 && 2 * n2 <= kRT &&
+             !(kern && std::strcmp(kern, "generic") == 0);   // N1 = 90 would spill
   dg->rg = std::max(1, std::min(n2, kDensityPPT * kNT / n1));
   if ((size_t)dg->rg * n1 > (size_t)kDensityPPT * kNT) return false;
   dg->ngroups = (n2 + dg->rg - 1) / dg->rg;
@@ -981,9 +1054,9 @@ hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big) {
 }
 
 hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
-                               const double *occ_d, double *partial) {
-  return c->prec == QEH_FP64 ? density_rows_impl<double2>(c, dg, nbk, big, occ_d, partial)
-                             : density_rows_impl<float2>(c, dg, nbk, big, occ_d, partial);
+                               const double *occ_d, double *partial, const void *zcol) {
+  return c->prec == QEH_FP64 ? density_rows_impl<double2>(c, dg, nbk, big, occ_d, partial, zcol)
+                             : density_rows_impl<float2>(c, dg, nbk, big, occ_d, partial, zcol);
 }
 
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,

@@ -146,6 +146,7 @@ size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 // Charge density: row groups of rg rows, subgroups of bsub bands.
 struct DensityGeom {
   int rg, ngroups, bsub;
+  bool pair;   // lane-pair rows kernel (partial planes in the same layout)
   size_t lds;
   FastDiv rg_div, rglast_div;
 };
@@ -153,8 +154,10 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg);
 // One block of nbk bands whose sticks K1 has written: inverse y columns into
 // big, then partial[sub][z][y][x] = sum over subgroup sub of occ_b |psi_b|^2.
 hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big);
+// zcol: N2 zero complex values (single precision), read by the lane-pair rows
+// for positions beyond the x-extent
 hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
-                               const double *occ_d, double *partial);
+                               const double *occ_d, double *partial, const void *zcol);
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
                                  double *rho, int accumulate, hipStream_t s);
 

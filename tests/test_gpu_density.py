@@ -133,3 +133,19 @@ def test_density_zero_bands_and_errors():
                             ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(small.data_ptr()),
                             256)
     assert st == q.QEH_ERR_INVALID
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_density_row_kernels_agree_mixed(name, monkeypatch):
+    # lane-pair rows (default in the mixed form at these boxes) and the
+    # LDS-pass rows: both against the oracle, and against each other
+    c = cellgen.make_cell(name)
+    psi = cellgen.make_psi0(c.npw, 5, seed=86)
+    occ = [2.0, 1.0, 1.0, 0.5, 0.25]
+    a, _ = _rho(c, psi, occ, 1, 5)
+    monkeypatch.setenv("QEH_DENSITY_KERNEL", "generic")
+    b, _ = _rho(c, psi, occ, 1, 5)
+    ref = oracle.density(c, psi, occ)
+    _check(a, ref, 1)
+    _check(b, ref, 1)
+    assert np.abs(a - b).max() < 2e-6 * np.abs(ref).max()
