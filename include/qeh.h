@@ -122,7 +122,10 @@ qeh_status qeh_apply_h_part(qeh_ctx *ctx, int part, int nb, const double *psi,
  * Bands go through in blocks of the context's block size: K1 (sticks and
  * inverse z), inverse y columns into the workspace, then inverse x rows with
  * the occupation-weighted |psi|^2 summed in double in a fixed order (the
- * result does not depend on timing).  Precision: the context's (the mixed
+ * result does not depend on timing).  Mixed-form contexts on the lane-pair
+ * plane kernel run the y and x transforms as one fused pass per z plane
+ * instead (no column workspace); QEH_DENSITY_KERNEL=rows or =generic, read per
+ * call, selects the unfused lane-pair rows or the LDS-pass rows (test hooks).  Precision: the context's (the mixed
  * form transforms in FP32 and sums in FP64).  Blocking: returns after the
  * device work of the call has finished.  Errors: QEH_ERR_INVALID for null
  * pointers, ldpsi < npw, a short or misaligned workspace, a non-finite
@@ -171,8 +174,9 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
 /* Per-stage device timing of H application and of the charge density (HIP
  * events on the context stream).  Stages: 0 scatter+z-FFT, 1 plane pass,
  * 2 z-FFT+gather+kinetic, 3 beta^H psi, 4 D scaling, 5 beta ps accumulate,
- * 6 density inverse y columns, 7 density inverse x rows + |psi|^2 sums,
- * 8 density subgroup reduce (qeh_density's K1 counts as stage 0).  enable=1
+ * 6 density inverse y columns, 7 density inverse x rows + |psi|^2 sums (the
+ * fused y + x pass when it runs; stage 6 then stays empty), 8 density
+ * subgroup reduce (qeh_density's K1 counts as stage 0).  enable=1
  * starts recording (and clears totals); qeh_ctx_stage_times synchronises the
  * stream and returns total milliseconds and launch counts per stage. */
 #define QEH_NSTAGES 9

@@ -798,7 +798,7 @@ DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
   const size_t cs = c->prec == QEH_FP64 ? 16 : 8;
   const size_t nfft = (size_t)c->n1 * c->n2 * c->n3;
   const int nsub = (c->block + dg.bsub - 1) / dg.bsub;
-  w.big = bump(&cur, cs * (size_t)c->block * c->n3 * c->ext * c->n2);
+  w.big = bump(&cur, dg.fused ? 0 : cs * (size_t)c->block * c->n3 * c->ext * c->n2);
   w.partial = bump(&cur, 8 * (size_t)nsub * nfft);
   w.occ = bump(&cur, 8 * (size_t)c->block);
   w.zcol = bump(&cur, 8 * (size_t)c->n2);
@@ -847,12 +847,15 @@ qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const 
       e = launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
     }
     if (e != hipSuccess) return hip_fail(e, "K1 launch");
-    {
-      StageGuard g(c, 6);
-      e = launch_density_columns(c, nbk, W + w.big);
-    }
-    if (e != hipSuccess) return hip_fail(e, "density columns launch");
-    {
+    if (dg.fused) {
+      StageGuard g(c, 7);
+      e = launch_density_plane(c, dg, nbk, occ_d, partial);
+    } else {
+      {
+        StageGuard g(c, 6);
+        e = launch_density_columns(c, nbk, W + w.big);
+      }
+      if (e != hipSuccess) return hip_fail(e, "density columns launch");
       StageGuard g(c, 7);
       e = launch_density_rows(c, dg, nbk, W + w.big, occ_d, partial, W + w.zcol);
     }

@@ -631,6 +631,80 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int k = 0; k < M; ++k) out[k] = acc[k];
 }
 
+// Fused density plane pass on lane pairs (mixed form, N1 = N2 = N a compiled
+// size, lane-pair plane tables): one workgroup = one z plane x one subgroup of
+// bands.  Per band: the plane's sticks into the LDS column tile (natural y),
+// inverse y transforms of the x-extent columns, then the x rows, each held by
+// the same pair (y, l) for every band, whose N/2 points accumulate
+// occ_b |psi_b|^2 in double registers (the x shift of the rows is a unit-modulus
+// phase).  No HBM round trip between the column and row transforms.
+template <int N>
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(2))) void k2d_plane_pair(
+    const float2 *__restrict__ sbuf, const double *__restrict__ occ, double *__restrict__ partial,
+    const int *__restrict__ tidx, int nst, int n3, int ext, int nbk, int bsub) {
+  constexpr int LD = N | 1, M = N / 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  float2 *T = reinterpret_cast<float2 *>(smem_raw);
+  const int tile = ext * LD;
+  const float2 *zslot = T + tile;
+  const int z = blockIdx.x % n3;
+  const int sub = blockIdx.x / n3;
+  const int b0 = sub * bsub;
+  const int b1 = min(nbk, b0 + bsub);
+  const int tid = threadIdx.x;
+  const float2 zero = make_float2(0.f, 0.f);
+  if (tid == 0) T[tile] = zero;
+  const bool row_lane = tid < 2 * N;
+  const bool odd = tid & 1;
+  const int l = odd ? 1 : 0;
+  const int y = tid >> 1;
+  double acc[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) acc[k] = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    for (int i = tid; i < tile; i += kRT) T[i] = zero;
+    __syncthreads();
+    const float2 *plane = sbuf + ((size_t)b * n3 + z) * nst;
+    for (int s = tid; s < nst; s += kRT) T[tidx[s]] = plane[s];
+    __syncthreads();
+    for (int j = tid; j < 2 * ext; j += kRT) {
+      const bool jodd = j & 1;
+      float2 *col = T + (j >> 1) * LD;
+      float2 v[M];
+#pragma unroll
+      for (int n = 0; n < M; ++n) v[n] = col[2 * n + jodd];
+      regfft::pair_inv<float2, N>(v, jodd);
+      float2 *out = col + (jodd ? M : 0);
+#pragma unroll
+      for (int k = 0; k < M; ++k) out[k] = v[k];
+    }
+    __syncthreads();
+    if (row_lane) {
+      const float2 *row = T + y;
+      float2 v[M];
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        const int c = 2 * n + l;
+        const float2 *a = c < ext ? row + c * LD : zslot;
+        v[n] = *a;
+      }
+      regfft::pair_inv<float2, N>(v, odd);
+      const double f = occ[b];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        const double re = v[k].x, im = v[k].y;
+        acc[k] += f * (re * re + im * im);
+      }
+    }
+    __syncthreads();
+  }
+  if (row_lane) {
+    double *out = partial + (((size_t)sub * n3 + z) * N + y) * N + l * M;
+#pragma unroll
+    for (int k = 0; k < M; ++k) out[k] = acc[k];
+  }
+}
+
 // rho[i] = (accumulate ? rho[i] : 0) + scale * sum_sub partial[sub][i], sub in order.
 __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__ partial,
                                                       int nsub, long npts, double scale,
@@ -960,6 +1034,18 @@ hipError_t density_rows_pair_launch(const qeh_ctx *c, const DensityGeom &dg, int
   return hipGetLastError();
 }
 
+template <int N>
+hipError_t density_plane_pair_launch(const qeh_ctx *c, const DensityGeom &dg, int nbk,
+                                     const double *occ_d, double *partial) {
+  const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
+  const size_t lds = 8 * ((size_t)c->ext * (N | 1) + 1);
+  allow_lds(k2d_plane_pair<N>, lds);
+  hipLaunchKernelGGL(k2d_plane_pair<N>, dim3((unsigned)nsub * c->n3), dim3(kRT), lds, c->stream,
+                     reinterpret_cast<const float2 *>(c->d.sbuf), occ_d, partial, c->d.tidx,
+                     c->nst, c->n3, c->ext, nbk, dg.bsub);
+  return hipGetLastError();
+}
+
 template <typename C>
 hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
                              const double *occ_d, double *partial, const void *zcol) {
@@ -1039,6 +1125,14 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
   const char *kern = std::getenv("QEH_DENSITY_KERNEL");
   dg->pair = pair_plane_supported(c->prec, n1, n1) && n1 <= 80 && 2 * n2 <= kRT &&
              !(kern && std::strcmp(kern, "generic") == 0);   // N1 = 90 would spill
+  // fused plane pass: lane-pair plane tables (natural y) and a square plane
+  dg->fused = dg->pair && c->plane_path == 2 && n1 == n2 &&
+              8 * ((size_t)c->ext * (n2 | 1) + 1) <= (size_t)kLdsMax &&
+              !(kern && std::strcmp(kern, "rows") == 0);
+  // the fused pass runs its bands one after another per workgroup: smaller
+  // subgroups give more workgroups (measured: 8 bands 0.27 ms, 16 bands
+  // 0.30 ms per 128-band density at the 72^3 cell)
+  if (dg->fused) dg->bsub = 8;
   dg->rg = std::max(1, std::min(n2, kDensityPPT * kNT / n1));
   if ((size_t)dg->rg * n1 > (size_t)kDensityPPT * kNT) return false;
   dg->ngroups = (n2 + dg->rg - 1) / dg->rg;
@@ -1051,6 +1145,17 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
 hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big) {
   return c->prec == QEH_FP64 ? density_columns_impl<double2>(c, nbk, big)
                              : density_columns_impl<float2>(c, nbk, big);
+}
+
+hipError_t launch_density_plane(const qeh_ctx *c, const DensityGeom &dg, int nbk,
+                                const double *occ_d, double *partial) {
+  switch (c->n1) {
+#define QEH_PAIR_CASE(NN) \
+  case NN: return density_plane_pair_launch<NN>(c, dg, nbk, occ_d, partial);
+    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+#undef QEH_PAIR_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,

@@ -146,7 +146,8 @@ size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 // Charge density: row groups of rg rows, subgroups of bsub bands.
 struct DensityGeom {
   int rg, ngroups, bsub;
-  bool pair;   // lane-pair rows kernel (partial planes in the same layout)
+  bool pair;    // lane-pair rows kernel (partial planes in the same layout)
+  bool fused;   // lane-pair fused plane kernel: no column pass through HBM
   size_t lds;
   FastDiv rg_div, rglast_div;
 };
@@ -158,6 +159,9 @@ hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big);
 // for positions beyond the x-extent
 hipError_t launch_density_rows(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
                                const double *occ_d, double *partial, const void *zcol);
+// Fused form (dg.fused): sticks -> columns -> rows -> partial planes in one pass.
+hipError_t launch_density_plane(const qeh_ctx *c, const DensityGeom &dg, int nbk,
+                                const double *occ_d, double *partial);
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
                                  double *rho, int accumulate, hipStream_t s);
 

@@ -60,17 +60,23 @@ def test_density_ragged_blocks(prec):
     _check(got, oracle.density(c, psi, occ), prec)
 
 
-def test_density_layouts_agree_mixed(monkeypatch):
-    # mixed C1 takes the lane-pair plane tables; the generic kernel keeps the
-    # digit-reversed ones; the density uses its own digit-reversed table in both
+@pytest.mark.parametrize("env", [{}, {"QEH_DENSITY_KERNEL": "rows"},
+                                 {"QEH_DENSITY_KERNEL": "generic"},
+                                 {"QEH_PLANE_KERNEL": "generic"}])
+def test_density_paths_mixed(env, monkeypatch):
+    # the fused lane-pair plane pass (default at mixed C1), lane-pair rows after
+    # the HBM column pass, LDS-pass rows, and a context with digit-reversed
+    # plane tables: each against the oracle and against the default
     c = cellgen.make_cell("c1")
     psi = cellgen.make_psi0(c.npw, 5, seed=83)
     occ = [2.0, 2.0, 1.0, 1.0, 0.5]
-    a, ca = _rho(c, psi, occ, 1, 5)
-    monkeypatch.setenv("QEH_PLANE_KERNEL", "generic")
-    b, cb = _rho(c, psi, occ, 1, 5)
-    assert ca.info()["plane_path"] == 2 and cb.info()["plane_path"] == 0
-    assert np.array_equal(a, b)
+    ref = oracle.density(c, psi, occ)
+    a, _ = _rho(c, psi, occ, 1, 5)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    b, _ = _rho(c, psi, occ, 1, 5)
+    _check(b, ref, 1)
+    assert np.abs(a - b).max() < 2e-6 * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
