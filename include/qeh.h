@@ -237,17 +237,19 @@ qeh_status qeh_server_destroy(qeh_server *srv);
 
 /* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
  * precision, plane path (0 fused in one kernel, 1 split through HBM,
- * 2 lane-pair register kernel), stick path (0 LDS passes, 1 lane-pair
- * register z transforms)].  out has room for n values (up to 11).
+ * 2 lane-pair register kernel, 4 lane-quad register kernel), stick path
+ * (0 LDS passes, 1 lane-pair register z transforms)].  out has room for n
+ * values (up to 11).
  * The plane path is chosen by LDS fit and box shape: the lane-pair kernel
  * serves the mixed form when N1 = N2 is one of its compiled sizes (even,
- * 16..90).  Environment variables read by qeh_ctx_plan / qeh_ctx_create:
+ * 16..90), the lane-quad kernel the FP64 form when N1 = N2 is one of its
+ * compiled sizes (multiples of 4, 16..72).  Environment variables read by qeh_ctx_plan / qeh_ctx_create:
  * QEH_FORCE_SPLIT_PLANE=1 forces the split path (a test hook);
  * QEH_STICK_KERNEL=generic keeps the LDS-pass z transforms where the lane-pair
  * ones would run (mixed form, N3 a compiled size; a test hook);
- * QEH_PLANE_KERNEL=generic keeps the fused kernel where the lane-pair one
+ * QEH_PLANE_KERNEL=generic keeps the fused kernel where a register one
  * would run (a test and comparison hook); QEH_PAIR_PLANES=n sets the bands per
- * lane-pair workgroup (default 2); QEH_PLANE_ROWS=n caps the rows the fused
+ * register-kernel workgroup (default 2 lane-pair, 1 lane-quad); QEH_PLANE_ROWS=n caps the rows the fused
  * plane kernel expands at once (a tuning knob; fewer rows use less LDS). */
 qeh_status qeh_ctx_info(const qeh_ctx *ctx, long *out, int n);
 

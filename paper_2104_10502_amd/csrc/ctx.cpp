@@ -312,6 +312,22 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
     const char *kern = std::getenv("QEH_STICK_KERNEL");
     if (!(kern && std::strcmp(kern, "generic") == 0)) g->zpair = 1;
   }
+  // lane-quad kernel (FP64, N1 = N2 a compiled size): one band per workgroup
+  // by default (QEH_PAIR_PLANES overrides); QEH_PLANE_KERNEL=generic keeps the
+  // fused kernel
+  if (g->plane_path == 0 && quad_plane_supported(prec, n1, n2)) {
+    const char *kern = std::getenv("QEH_PLANE_KERNEL");
+    const bool generic = kern && std::strcmp(kern, "generic") == 0;
+    const char *pbs = std::getenv("QEH_PAIR_PLANES");
+    int pb = pbs ? std::atoi(pbs) : 1;
+    pb = std::max(1, std::min(8, pb));
+    while (pb > 1 && pair_plane_lds_bytes(prec, hm.ext, n2, pb) > (size_t)kLdsMax) --pb;
+    if (!generic && pair_plane_lds_bytes(prec, hm.ext, n2, pb) <= (size_t)kLdsMax) {
+      g->plane_path = 4;
+      g->pg.pb = pb;
+      g->pg.lds_pair = pair_plane_lds_bytes(prec, hm.ext, n2, pb);
+    }
+  }
   g->pg.ext_div = make_fastdiv(hm.ext);
   g->pg.rc_div = make_fastdiv(g->pg.rc);
   g->pg.rlast_div = make_fastdiv(n2 % g->pg.rc ? n2 % g->pg.rc : g->pg.rc);
@@ -512,7 +528,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
                                            : fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3)));
     const int ky = imod(hm.stick_k[s], n2);
     tidx_dit[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, ky);
-    tidx[s] = c->plane_path == 2 ? (hm.stick_h[s] - hm.hmin) * c->pg.ldT + ky : tidx_dit[s];
+    tidx[s] = (c->plane_path == 2 || c->plane_path == 4) ? (hm.stick_h[s] - hm.hmin) * c->pg.ldT + ky
+                                                          : tidx_dit[s];
   }
   for (int cc = 0; cc < hm.ext; ++cc) xin[fft_digit_pos(c->dx, imod(hm.hmin + cc, n1))] = cc;
   std::vector<int> colstart(hm.ext + 1, hm.nst);

@@ -716,6 +716,107 @@ __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__
   }
 }
 
+// ---------------------------------------------------------------- K2, lane quads
+// FP64 form of the register plane pass, for N1 = N2 = N a multiple of 4 with a
+// compiled form: each line belongs to four adjacent lanes holding N/4 points
+// each (quad_inv / quad_fwd; the inverse returns lane-bit-reversed blocks,
+// which is the forward's input layout, so the row chain inverse -> V ->
+// forward moves no data).  The x-extent shift of the rows and the zero /
+// discard slots are those of the lane-pair kernel.  One band per workgroup by
+// default (its column tile is 42 KB at N = 72).
+template <int N>
+__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 48 ? 3 : 2))) void k2_plane_quad(
+    double2 *__restrict__ sbuf, const double *__restrict__ vs, const int *__restrict__ tidx,
+    const double2 *__restrict__ tw_g, int nst, int n3, int ext, int pb, int nbk, int ngrp,
+    int per_xcd) {
+  constexpr int LD = N | 1, Q = N / 4;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *T = reinterpret_cast<double2 *>(smem_raw);
+  const int id = blockIdx.x;
+  const int logical = (id & 7) * per_xcd + (id >> 3);
+  if (logical >= ngrp * n3) return;
+  const int z = logical / ngrp;
+  const int g = logical - z * ngrp;
+  const int b0 = g * pb;
+  const int np = min(pb, nbk - b0);
+  const int tid = threadIdx.x;
+  const int tile = ext * LD;
+  const double2 *zslot = T + pb * tile;
+  double2 *dslot = T + pb * tile + 1 + tid;
+  double2 *twq = T + pb * tile + 1 + kRT;   // [4][Q]: row q holds W_N^{q k}
+  const double2 zero = make_double2(0.0, 0.0);
+  const int q = tid & 3;
+  const int bq = ((q & 1) << 1) | (q >> 1);   // two-bit reversal of q
+  const regfft::QuadLane<double> ql(q);
+  const double2 *tw = twq + q * Q;
+
+  for (int i = tid; i < np * tile; i += kRT) T[i] = zero;
+  if (tid == 0) T[pb * tile] = zero;
+  for (int i = tid; i < 4 * Q; i += kRT) twq[i] = tw_g[((i / Q) * (i % Q)) % N];
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    const double2 *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    double2 *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += kRT) Tp[tidx[s]] = plane[s];
+  }
+  __syncthreads();
+  for (int j = tid; j < 4 * np * ext; j += kRT) {
+    double2 *col = T + (j >> 2) * LD;
+    double2 v[Q];
+#pragma unroll
+    for (int n = 0; n < Q; ++n) v[n] = col[4 * n + q];
+    regfft::quad_inv<double2, N>(v, tw, ql);
+    double2 *out = col + Q * bq;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) out[k] = v[k];
+  }
+  __syncthreads();
+  for (int j = tid; j < 4 * np * N; j += kRT) {
+    const int r = j >> 2;
+    const int p = r / N;
+    const int y = r - p * N;
+    double2 *row = T + p * tile + y;
+    double2 v[Q];
+#pragma unroll
+    for (int n = 0; n < Q; ++n) {
+      const int c = 4 * n + q;
+      const double2 *a = c < ext ? row + c * LD : zslot;
+      v[n] = *a;
+    }
+    regfft::quad_inv<double2, N>(v, tw, ql);
+    const double *vr = vs + ((size_t)z * N + y) * N + Q * bq;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) v[k] = cscale(v[k], vr[k]);
+    regfft::quad_fwd<double2, N>(v, tw, ql);
+#pragma unroll
+    for (int m = 0; m < Q; ++m) {
+      const int c = 4 * m + q;
+      double2 *a = c < ext ? row + c * LD : dslot;
+      *a = v[m];
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < 4 * np * ext; j += kRT) {
+    double2 *col = T + (j >> 2) * LD;
+    const double2 *in = col + Q * bq;
+    double2 v[Q];
+#pragma unroll
+    for (int x = 0; x < Q; ++x) v[x] = in[x];
+    regfft::quad_fwd<double2, N>(v, tw, ql);
+#pragma unroll
+    for (int m = 0; m < Q; ++m) col[4 * m + q] = v[m];
+  }
+  __syncthreads();
+  for (int p = 0; p < np; ++p) {
+    double2 *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    const double2 *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += kRT) plane[s] = Tp[tidx[s]];
+  }
+}
+
+// Box sizes with a compiled lane-quad kernel (double precision).
+#define QEH_QUAD_SIZES(X) X(16) X(20) X(24) X(32) X(36) X(40) X(48) X(60) X(64) X(72)
+
 // Box sizes with a compiled lane-pair kernel (single precision).
 #define QEH_PAIR_SIZES(X) \
   X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(90)
@@ -1109,6 +1210,29 @@ hipError_t k3_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi
   }
 }
 
+template <int N> hipError_t k2_quad_launch(const qeh_ctx *c, int nbk) {
+  const int pb = c->pg.pb;
+  const int ngrp = (nbk + pb - 1) / pb;
+  const int per_xcd = (ngrp * c->n3 + 7) / 8;
+  allow_lds(k2_plane_quad<N>, c->pg.lds_pair);
+  hipLaunchKernelGGL(k2_plane_quad<N>, dim3(8 * per_xcd), dim3(kRT), c->pg.lds_pair, c->stream,
+                     reinterpret_cast<double2 *>(c->d.sbuf),
+                     reinterpret_cast<const double *>(c->d.vs), c->d.tidx,
+                     reinterpret_cast<const double2 *>(c->d.tw) + c->tw_off[0], c->nst, c->n3,
+                     c->ext, pb, nbk, ngrp, per_xcd);
+  return hipGetLastError();
+}
+
+hipError_t k2_quad_impl(const qeh_ctx *c, int nbk) {
+  switch (c->n1) {
+#define QEH_QUAD_CASE(NN) \
+  case NN: return k2_quad_launch<NN>(c, nbk);
+    QEH_QUAD_SIZES(QEH_QUAD_CASE)
+#undef QEH_QUAD_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 size_t plane_lds_bytes(int prec, int ext, int n1, int n2, const PlaneGeom &g) {
@@ -1174,6 +1298,17 @@ hipError_t launch_density_reduce(const double *partial, int nsub, long npts, dou
 
 bool pair_z_supported(int prec, int n3) { return pair_plane_supported(prec, n3, n3); }
 
+bool quad_plane_supported(int prec, int n1, int n2) {
+  if (prec != QEH_FP64 || n1 != n2) return false;
+  switch (n1) {
+#define QEH_QUAD_CASE(NN) \
+  case NN: return true;
+    QEH_QUAD_SIZES(QEH_QUAD_CASE)
+#undef QEH_QUAD_CASE
+    default: return false;
+  }
+}
+
 size_t pair_z_lds_bytes(int n3) { return 8 * (size_t)kPairSticks * (n3 | 1); }
 
 bool pair_plane_supported(int prec, int n1, int n2) {
@@ -1189,7 +1324,9 @@ bool pair_plane_supported(int prec, int n1, int n2) {
 
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb) {
   const size_t c = prec == QEH_FP64 ? 16 : 8;
-  return c * ((size_t)pb * ext * (n2 | 1) + 1 + kRT);
+  // column tiles, zero slot, discard slots, and (lane-quad kernel) the [4][N/4]
+  // twiddle table
+  return c * ((size_t)pb * ext * (n2 | 1) + 1 + kRT + (prec == QEH_FP64 ? n2 : 0));
 }
 
 size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
@@ -1205,6 +1342,7 @@ hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {
   if (c->plane_path == 2) return k2_pair_impl(c, nbk);
+  if (c->plane_path == 4) return k2_quad_impl(c, nbk);
   if (c->plane_path != 0)
     return c->prec == QEH_FP64 ? k2_split_impl<double2>(c, nbk) : k2_split_impl<float2>(c, nbk);
   return c->prec == QEH_FP64 ? k2_impl<double2>(c, nbk) : k2_impl<float2>(c, nbk);

@@ -157,5 +157,93 @@ __device__ __forceinline__ void pair_fwd(C *v, bool odd) {
   Fft<C, N / 2, false>::run(v);
 }
 
+// ---------------------------------------------------------------- lane quads
+// A line of N = 4Q points held by four adjacent lanes (q = lane & 3), Q points
+// each: in-lane transforms of length Q plus a 4-point transform across the
+// quad, done as two radix-2 stages through DPP swaps (partner lane q ^ 2, then
+// q ^ 1) with a quarter-turn rotation on lane 3 between them.  With br(q) the
+// two-bit reversal of q:
+//   quad_inv: lane q holds x[4n + q] (n < Q) -> X[k + Q br(q)] (k < Q);
+//   quad_fwd: lane q holds f[x + Q br(q)]    -> F[4m + q].
+// So the output of quad_inv is the input layout of quad_fwd.  All four lanes of
+// a quad must be active together.
+
+template <int CTRL> __device__ __forceinline__ float lane_perm(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ __forceinline__ double lane_perm(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+constexpr int kDppXor1 = 0xB1;   // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;   // quad_perm [2, 3, 0, 1]
+
+// Per-lane constants of a quad, computed once: the signs of the two radix-2
+// stages and the quarter-turn coefficients of lane 3.
+template <typename Rl> struct QuadLane {
+  Rl s1, s2;   // +1 / -1: own + partner or partner - own (partners q ^ 1, q ^ 2)
+  Rl rc, rs;   // lane 3: (0, 1) (times +i; the forward uses -i); others (1, 0)
+  __device__ explicit QuadLane(int q)
+      : s1((q & 1) ? Rl(-1) : Rl(1)), s2((q & 2) ? Rl(-1) : Rl(1)),
+        rc(q == 3 ? Rl(0) : Rl(1)), rs(q == 3 ? Rl(1) : Rl(0)) {}
+};
+
+// radix-2 across lanes q and q ^ mask: partner + sign * own
+template <typename C, int Q, int CTRL>
+__device__ __forceinline__ void quad_bfly(C *v, typename real_of<C>::type sgn) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const C o = v[k];
+    v[k].x = lane_perm<CTRL>(o.x) + sgn * o.x;
+    v[k].y = lane_perm<CTRL>(o.y) + sgn * o.y;
+  }
+}
+
+// lane 3 times +i (inverse) or -i (forward), as (rc + i rs) or its conjugate
+template <typename C, int Q, bool INV>
+__device__ __forceinline__ void quad_rotate(C *v, typename real_of<C>::type rc,
+                                            typename real_of<C>::type rs) {
+  const auto s = INV ? rs : -rs;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const C a = v[k];
+    v[k].x = rc * a.x - s * a.y;
+    v[k].y = s * a.x + rc * a.y;
+  }
+}
+
+// element k times tw[k] (this lane's row W_N^{q k} of a table), conjugated for
+// the inverse
+template <typename C, int Q, bool INV>
+__device__ __forceinline__ void quad_twiddle(C *v, const C *tw) {
+#pragma unroll
+  for (int k = 1; k < Q; ++k) v[k] = INV ? cmulc(v[k], tw[k]) : cmul(v[k], tw[k]);
+}
+
+// tw: this lane's table row, tw[k] = W_N^{q k} for k < Q (W_N = exp(-2 pi i / N))
+template <typename C, int N>
+__device__ __forceinline__ void quad_inv(C *v, const C *tw,
+                                         const QuadLane<typename real_of<C>::type> &ql) {
+  constexpr int Q = N / 4;
+  Fft<C, Q, true>::run(v);
+  quad_twiddle<C, Q, true>(v, tw);
+  quad_bfly<C, Q, kDppXor2>(v, ql.s2);
+  quad_rotate<C, Q, true>(v, ql.rc, ql.rs);
+  quad_bfly<C, Q, kDppXor1>(v, ql.s1);
+}
+
+template <typename C, int N>
+__device__ __forceinline__ void quad_fwd(C *v, const C *tw,
+                                         const QuadLane<typename real_of<C>::type> &ql) {
+  constexpr int Q = N / 4;
+  quad_bfly<C, Q, kDppXor1>(v, ql.s1);
+  quad_rotate<C, Q, false>(v, ql.rc, ql.rs);
+  quad_bfly<C, Q, kDppXor2>(v, ql.s2);
+  quad_twiddle<C, Q, false>(v, tw);
+  Fft<C, Q, false>::run(v);
+}
+
 }  // namespace regfft
 }  // namespace qeh

@@ -73,7 +73,7 @@ struct DevMaps {
   int *gmap;         // [npw] s*ldz + digit-reversed z position (natural z for the
                      // lane-pair K1 / K3, whose ldz is N3 | 1 as well)
   int *tidx;         // [nst] plane-tile index c*ldT + pos_y(k mod N2); the lane-pair
-                     // kernel takes natural y (pos_y = identity)
+                     // and lane-quad kernels take natural y (pos_y = identity)
   int *tidx_dit;     // [nst] the same with pos_y the y-DIT input position (always)
   int *xin;          // [N1] column c whose h sits at x-DIT input position p, or -1
   double *kin;       // [npw] |k+G|^2
@@ -100,7 +100,8 @@ struct qeh_ctx {
   int npw = 0, nst = 0, nkb = 0, nat = 0;
   int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
   int block = 0, prec = 0;
-  int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel
+  int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel,
+                        // 4 lane-quad kernel (FP64)
   int zpair = 0;        // 1: lane-pair K1 / K3 (gmap at natural z)
   int nsplit = 1, kchunk = 0;
   int nchunk = 0;
@@ -140,6 +141,7 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g);
 // box, and its LDS bytes for pb planes of ext columns.
 bool pair_plane_supported(int prec, int n1, int n2);
 bool pair_z_supported(int prec, int n3);
+bool quad_plane_supported(int prec, int n1, int n2);
 size_t pair_z_lds_bytes(int n3);
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 

@@ -253,3 +253,31 @@ def test_pair_sticks_match_generic_c2(monkeypatch):
     b, cb = run(c, psi, 1, 4)
     assert ca.info()["stick_path"] == 1 and cb.info()["stick_path"] == 0
     assert _rel_l2(a, b).max() < 2e-6
+
+
+def test_apply_h_quad_fp64_small_box():
+    # FP64 lane-quad plane kernel at N1 = N2 = 24 (6 points per lane), non-cubic
+    # lattice, general k, s/p/d projectors; against the oracle at the FP64 bar
+    c = cellgen.make_cell("t", lattice=np.diag([8.0, 8.0, 9.5]), frac=np.array(
+        [[0.1, 0.2, 0.3], [0.6, 0.5, 0.9]]), kpt=(0.11, -0.07, 0.23), ecutwfc=14.0,
+        fft=(24, 24, 28), proj="s2pd", dfixed=False, nbnd=6)
+    psi = cellgen.make_psi0(c.npw, 6, seed=48)
+    got, ctx = run(c, psi, 0, 4)
+    assert ctx.info()["plane_path"] == 4
+    ref = oracle.apply_h(c, psi)
+    assert _rel_l2(got, ref).max() < 1e-12
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("pb", [1, 2])
+def test_quad_matches_generic_fp64_c2(pb, monkeypatch):
+    # the two FP64 plane kernels on the 72^3 cell, one and two bands per
+    # lane-quad workgroup (5 bands: a ragged group)
+    c = cell("c2")
+    psi = cellgen.make_psi0(c.npw, 5, seed=49)
+    monkeypatch.setenv("QEH_PAIR_PLANES", str(pb))
+    a, ca = run(c, psi, 0, 5)
+    monkeypatch.setenv("QEH_PLANE_KERNEL", "generic")
+    b, cb = run(c, psi, 0, 5)
+    assert ca.info()["plane_path"] == 4 and cb.info()["plane_path"] == 0
+    assert _rel_l2(a, b).max() < 1e-13
