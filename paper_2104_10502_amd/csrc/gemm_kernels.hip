@@ -7,15 +7,15 @@
 // solver, which the paper runs through GPU BLAS (section "Evolution of the
 // GPU-enabled version").
 //
-// FP32: a complex product is three real MFMA products on planar (re, im)
-// tiles (Gauss's three-multiplication form):
+// A complex product is three real MFMA products on planar (re, im) tiles
+// (Gauss's three-multiplication form):
 //   P1 += Ar Br,   P2 += Ai Bi,   P3 += (Ar + Ai)(Br + Bi),
 //   Cr = P1 - P2,  Ci = P3 - P1 - P2.
 // The operand sums are formed in registers after the LDS reads.  The form is
 // normwise stable; its rounding error is a small constant multiple of that of
-// the four-product form.  FP64 keeps four products,
-//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br,
-// which measured faster there (two accumulators instead of three).
+// the four-product form (Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br), and it issues
+// a quarter fewer MFMAs.  The FP64 instances are held to three waves per SIMD
+// (their third accumulator set would otherwise push them to two).
 // 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
 // (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
 // split into fixed chunks whose partial results are summed in double by a
@@ -68,7 +68,8 @@ template <typename T> __device__ __forceinline__ T zero_of() {
 // tiles are prefetched into registers while the MFMAs consume the LDS copy of
 // the previous slice (two LDS buffers, one barrier per slice).
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
-__global__ __launch_bounds__(kGT) void cgemm_kernel(
+__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
+void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
     long ldc, int M, int N, int K, int conjA, int conjB, int accumulate, int kchunk,
     long split_stride, int tiles_m, int tiles_n, int ntiles, int per_xcd) {
@@ -105,16 +106,14 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
   const R sa = conjA ? R(-1) : R(1);
   const R sb = conjB ? R(-1) : R(1);
 
-  // Gauss form: p1, p2, p3 as above; four-product form: p1 = Cr, p2 = Ci
-  constexpr bool kGauss = sizeof(R) == 4;
-  ACC p1[TM][TN], p2[TM][TN], p3[kGauss ? TM : 1][kGauss ? TN : 1];
+  ACC p1[TM][TN], p2[TM][TN], p3[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       p1[i][j] = ACC{0, 0, 0, 0};
       p2[i][j] = ACC{0, 0, 0, 0};
-      if constexpr (kGauss) p3[i][j] = ACC{0, 0, 0, 0};
+      p3[i][j] = ACC{0, 0, 0, 0};
     }
 
   TA ra[NA];
@@ -185,29 +184,22 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
         const int off = (wm0 + i * 16 + lr) * BKP + kk + lk;
         ar[i] = As[buf][0][off];
         ai[i] = As[buf][1][off];
-        as[i] = kGauss ? ar[i] + ai[i] : R(0);
+        as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const int off = (wn0 + j * 16 + lr) * BKP + kk + lk;
         br[j] = Bs[buf][0][off];
         bi[j] = Bs[buf][1][off];
-        bs[j] = kGauss ? br[j] + bi[j] : R(0);
+        bs[j] = br[j] + bi[j];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          if constexpr (kGauss) {
-            mfma(ar[i], br[j], p1[i][j]);
-            mfma(ai[i], bi[j], p2[i][j]);
-            mfma(as[i], bs[j], p3[i][j]);
-          } else {
-            mfma(ar[i], br[j], p1[i][j]);
-            mfma(-ai[i], bi[j], p1[i][j]);
-            mfma(ar[i], bi[j], p2[i][j]);
-            mfma(ai[i], br[j], p2[i][j]);
-          }
+          mfma(ar[i], br[j], p1[i][j]);
+          mfma(ai[i], bi[j], p2[i][j]);
+          mfma(as[i], bs[j], p3[i][j]);
         }
     }
     if (more) sstore(buf ^ 1);
@@ -230,14 +222,8 @@ __global__ __launch_bounds__(kGT) void cgemm_kernel(
         if (gm < M && gn < N) {
           TC *p = Cz + (long)gm * ldc + gn;
           using RC = typename real_of<TC>::type;
-          R cr, ci;
-          if constexpr (kGauss) {
-            cr = p1[i][j][r] - p2[i][j][r];
-            ci = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
-          } else {
-            cr = p1[i][j][r];
-            ci = p2[i][j][r];
-          }
+          const R cr = p1[i][j][r] - p2[i][j][r];
+          const R ci = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
           if (accumulate) {
             TC v = *p;
             // the add happens in the result's precision

