@@ -820,6 +820,10 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 48 ? 3 
 // Box sizes with a compiled lane-pair kernel (single precision).
 #define QEH_PAIR_SIZES(X) \
   X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80) X(90)
+// ... and for the density kernels, whose per-point sums add registers (N = 90
+// would spill)
+#define QEH_DENSITY_PAIR_SIZES(X) \
+  X(16) X(18) X(20) X(24) X(30) X(32) X(36) X(40) X(48) X(50) X(54) X(60) X(64) X(72) X(80)
 
 // ---------------------------------------------------------------- K1 / K3, lane pairs
 // Mixed form with N3 = N even and a compiled form of N: the z transforms held
@@ -1154,7 +1158,7 @@ hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, c
     switch (c->n1) {
 #define QEH_PAIR_CASE(NN) \
   case NN: return density_rows_pair_launch<NN>(c, dg, nbk, big, occ_d, partial, zcol);
-      QEH_PAIR_SIZES(QEH_PAIR_CASE)
+      QEH_DENSITY_PAIR_SIZES(QEH_PAIR_CASE)
 #undef QEH_PAIR_CASE
       default: return hipErrorInvalidValue;
     }
@@ -1276,7 +1280,7 @@ hipError_t launch_density_plane(const qeh_ctx *c, const DensityGeom &dg, int nbk
   switch (c->n1) {
 #define QEH_PAIR_CASE(NN) \
   case NN: return density_plane_pair_launch<NN>(c, dg, nbk, occ_d, partial);
-    QEH_PAIR_SIZES(QEH_PAIR_CASE)
+    QEH_DENSITY_PAIR_SIZES(QEH_PAIR_CASE)
 #undef QEH_PAIR_CASE
     default: return hipErrorInvalidValue;
   }
