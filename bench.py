@@ -6,10 +6,11 @@ Workload: the 64-atom diamond-like supercell (cubic a = 20.52 bohr, one k-point
 synthetic (Gaussian model pseudopotential), resident in HBM before timing.
 
 A step = one full H|psi> (kinetic + local-potential FFT path + nonlocal
-projectors) over all 128 bands.  ``value`` is the mixed form (FP32 FFTs and
+projectors) over all 128 bands; the timed steps run without instrumentation.  ``value`` is the mixed form (FP32 FFTs and
 projector GEMMs, FP64 psi / kinetic); the plain FP64 form is reported beside
 it.  Per-kernel device times come from HIP events recorded on the context
-stream during the timed steps; ``roofline`` reports the dominant kernel.
+stream during a second, equal set of steps; ``roofline`` reports the dominant
+kernel.
 ``cpu_baseline`` times the FP64 oracle's H|psi> on a bounded band sample on
 the host cores.  The charge density of the same 128 bands (both forms) is
 timed beside it (``density``), and a 5 s replay of the served request trace
@@ -124,19 +125,22 @@ def stored_traffic(kernel, prec):
 
 
 def time_apply(q, torch, cell, prec, nb, steps, warmup):
+    """Timed steps without instrumentation (the reported rate), then the same
+    number of steps with per-stage HIP events (the kernel breakdown)."""
     ctx = q.Context.from_cell(cell, precision=prec, block=nb)
     psi = torch.from_numpy(__import__("cellgen").make_psi0(cell.npw, nb, seed=10502)).cuda()
     out = torch.empty_like(psi)
     for _ in range(warmup):
         ctx.apply_h(psi, out=out)
     torch.cuda.synchronize()
-    ctx.profile(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.apply_h(psi, out=out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.apply_h(psi, out=out)
     stages = ctx.stage_times()
     ctx.profile(False)
     shape = ctx.info()
@@ -156,12 +160,14 @@ def time_density(q, torch, cell, prec, nb, steps, warmup):
     for _ in range(warmup):
         ctx.density(psi, occ, out=rho, work=work)
     torch.cuda.synchronize()
-    ctx.profile(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.density(psi, occ, out=rho, work=work)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    ctx.profile(True)
+    for _ in range(steps):
+        ctx.density(psi, occ, out=rho, work=work)
     stages = ctx.stage_times()
     ctx.profile(False)
     n = np.prod(cell.fft)
