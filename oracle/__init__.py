@@ -23,13 +23,17 @@ exascale):
 * ``density``: the charge density generation of the same list of ported
   kernels, rho(r) = (1/Omega) sum_i f_i |psi_i(r)|^2 on the FFT grid;
   ``density_direct`` sums the plane waves point by point (tiny cells).
+* ``beta_projectors``: the projectors beta_i(k+G) built from their radial
+  functions (the "calculation of pseudopotential terms" of the quantum-engine
+  modules), with the radial Bessel transform taken by quadrature.
 
 The paper prints no formula for any of these; the forms are the standard
 plane-wave pseudopotential ones.  Every reading taken where the paper is
 silent is listed in the design notes of the repository.
 
-Pins: every function here is checked in ``tests/test_oracle_pins.py`` against
-closed forms, invariants, brute force and library routines (see that file).
+Pins: every function here is checked in ``tests/test_oracle_pins.py``,
+``tests/test_oracle_density.py`` and ``tests/test_oracle_beta.py`` against
+closed forms, invariants, brute force and library routines (see those files).
 """
 
 from .dft import dft_matrix, dft_axis, inv3, fwd3
@@ -37,7 +41,9 @@ from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, vloc_coe
                           hdiag)
 from .davidson import davidson, rayleigh_ritz
 from .density import cell_volume, density, density_direct, psi_real_space
+from .beta import beta_projectors, radial_transform, real_harmonics, spherical_bessel
 
 __all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
            "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
-           "cell_volume", "density", "density_direct", "psi_real_space"]
+           "cell_volume", "density", "density_direct", "psi_real_space", "beta_projectors",
+           "radial_transform", "real_harmonics", "spherical_bessel"]
