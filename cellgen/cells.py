@@ -62,6 +62,9 @@ class Cell:
     block: int
     proj_set: str = "sp"
     meta: dict = field(default_factory=dict)
+    # radial-table description of the projectors (see ``projgen_tables``);
+    # when set, consumers may build beta from it instead of using ``beta``
+    projgen: dict = None
 
     @property
     def npw(self) -> int:
@@ -242,6 +245,24 @@ def beta_matrix(lattice, kpt, miller, positions, proj_set: str) -> np.ndarray:
                 i += 1
     del rows
     return out
+
+
+def projgen_tables(cell, dq: float = 0.01) -> dict:
+    """Pseudopotential data of the cell's projectors in tabulated form: one
+    species, its radial channels (l, sigma) of ``PROJ_SETS[cell.proj_set]``,
+    and for each channel the radial transform F(q) sampled at q = j dq, from 0
+    to past sqrt(ecutwfc) (the largest |k+G| of the sphere) with three points
+    to spare -- the form a pseudopotential file's radial functions take once
+    transformed.  Returned as the dict the HIP binding takes as ``projgen``."""
+    chans = PROJ_SETS[cell.proj_set]
+    nq = int(math.ceil(math.sqrt(cell.ecutwfc) / dq)) + 4
+    q = np.arange(nq) * dq
+    tab = np.stack([radial_ft_closed(l, sig, q) for (l, sig) in chans])
+    return dict(tau=np.ascontiguousarray(cell.positions, dtype=np.float64),
+                ityp=np.zeros(cell.nat, dtype=np.int32),
+                nchan=np.array([len(chans)], dtype=np.int32),
+                lchan=np.array([l for (l, _) in chans], dtype=np.int32),
+                dq=float(dq), tab=tab)
 
 
 def _dmat_blocks(nat: int, proj_set: str, dvals: np.ndarray) -> np.ndarray:

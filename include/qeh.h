@@ -55,6 +55,37 @@ enum { QEH_FP64 = 0, QEH_MIXED = 1 };
  *            into fixed chunks reduced in double); the kinetic term, psi,
  *            H psi and the whole Davidson subspace algebra in double.       */
 
+/* Projectors built on the device from radial tables: the "calculation of
+ * pseudopotential terms" of the quantum-engine modules (section
+ * "Quantum-engine modules", item viii), done where the Hamiltonian lives.
+ * Standard separable form; for projector i = (atom a of species s, radial
+ * channel c of s with angular momentum l, real harmonic m) and q = k + G:
+ *   beta_i(q) = 4 pi / sqrt(Omega) (-i)^l F_c(|q|) Y_lm(q/|q|) exp(-i q . tau_a),
+ *   F_c(q)    = int_0^inf r^2 beta_c(r) j_l(q r) dr,
+ * with F_c given as a table F_c(j dq), j < nq, and evaluated at |q| by the
+ * cubic Lagrange polynomial through table points j-1 .. j+2 where
+ * j = max(1, floor(|q| / dq)).  Real harmonics of the unit vector (x, y, z)
+ * (all zero-argument values taken at (0, 0, 0) when q = 0), in this order:
+ *   l = 0: 1/sqrt(4 pi);  l = 1: sqrt(3/(4 pi)) (x, y, z);
+ *   l = 2: sqrt(15/(4 pi)) (xy, yz, zx), sqrt(5/(16 pi)) (3z^2 - 1),
+ *          sqrt(15/(16 pi)) (x^2 - y^2).
+ * Projector order: atoms in order; within an atom its species' channels in
+ * order; within a channel m as listed.  nproj[a] must equal the sum of
+ * 2 l + 1 over the channels of atom a's species.  All pointers are HOST
+ * pointers. */
+typedef struct {
+  const double *tau;      /* [nat][3] cartesian atom positions (bohr)          */
+  const int *ityp;        /* [nat] species of each atom, in [0, nsp)           */
+  int nsp;                /* species (>= 1)                                    */
+  const int *nchan;       /* [nsp] radial channels per species (>= 0)          */
+  const int *lchan;       /* [sum nchan] l (0, 1 or 2) per channel, species by
+                             species                                            */
+  int nq;                 /* table points per channel (>= 4)                   */
+  double dq;              /* table spacing (bohr^-1, > 0); every |k+G| of the
+                             sphere must satisfy |k+G| <= (nq - 3) dq          */
+  const double *tab;      /* [sum nchan][nq] F_c(j dq), same channel order     */
+} qeh_projgen;
+
 /* One cell at one k-point.  Every pointer is a HOST pointer, read during
  * qeh_ctx_plan / qeh_ctx_create only. */
 typedef struct {
@@ -75,6 +106,10 @@ typedef struct {
                              blocks (row-major), concatenated (Ry)           */
   int precision;          /* QEH_FP64 or QEH_MIXED                           */
   int block;              /* bands per H-application launch (>= 1)           */
+  const qeh_projgen *projgen;   /* optional: when beta is NULL and there are
+                             projectors, qeh_ctx_create builds beta on the
+                             device from these tables (and diag(H) with it);
+                             ignored when beta is given                        */
 } qeh_cell;
 
 typedef struct qeh_ctx qeh_ctx;
@@ -86,7 +121,10 @@ qeh_status qeh_ctx_plan(const qeh_cell *cell, size_t *arena_bytes);
  * diag(H)), copy them, V/N, beta and D into the arena, and bind the context
  * to hip_stream (a hipStream_t; NULL = the null stream).  arena must be a
  * device pointer with 256-byte alignment and >= the planned size.  The
- * copies are complete when the call returns. */
+ * copies are complete when the call returns.  With beta NULL and projgen
+ * set, beta is built on the device instead (as qeh_beta_generate, in the
+ * context's precision) and the nonlocal part of diag(H) is summed from it
+ * there; the plan then includes the generator's workspace. */
 qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
                           void *hip_stream, qeh_ctx **out);
 
@@ -134,13 +172,30 @@ qeh_status qeh_density_plan(const qeh_ctx *ctx, size_t *work_bytes);
 qeh_status qeh_density(qeh_ctx *ctx, int nb, const double *psi, int ldpsi,
                        const double *occ, double *rho, void *work, size_t work_bytes);
 
+/* Projectors of cell->projgen for the sphere of cell (lattice, kpt, npw,
+ * miller, nat, nproj; vloc, beta and dmat are not read), written on the
+ * device: beta (DEVICE) holds nkb rows of ldb >= npw complex elements, row i
+ * = projector i, as double pairs when precision is QEH_FP64 and as float
+ * pairs (each value computed in double, then rounded) when QEH_MIXED.  work:
+ * DEVICE workspace of qeh_beta_plan bytes, 256-byte aligned, caller-owned
+ * (it receives the k+G vectors, positions and tables).  Work is ordered on
+ * hip_stream (a hipStream_t, NULL = null stream); the call returns after it
+ * has finished.  Errors: QEH_ERR_INVALID for a missing or inconsistent
+ * projgen (species or l out of range, nproj not matching the channels, a
+ * table too short for the sphere, dq <= 0, nq < 4), null pointers, ldb < npw
+ * or a short / misaligned workspace; QEH_ERR_NUMERIC for a non-finite table
+ * value or position. */
+qeh_status qeh_beta_plan(const qeh_cell *cell, size_t *work_bytes);
+qeh_status qeh_beta_generate(const qeh_cell *cell, int precision, void *beta, long ldb,
+                             void *work, size_t work_bytes, void *hip_stream);
+
 /* Davidson options: nvecx = maximum basis size (>= 2 nb; 0 = 2 nb),
  * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
  * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single
  * precision limits how small the residual can get; a band also counts as
  * converged there when its Ritz value moved by <= 1e-8 Ry in one iteration,
- * or when its residual (<= 10x that threshold) has not dropped by 10% in 3
- * iterations. */
+ * or when its residual has not dropped by 10% in 3 iterations while <= 10x
+ * that threshold, or in 5 iterations while <= 100x it. */
 typedef struct {
   int nvecx;
   double rtol;

@@ -46,12 +46,19 @@ _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 
 
+class QehProjgen(ctypes.Structure):
+    _fields_ = [("tau", _c_dbl_p), ("ityp", _c_int_p), ("nsp", ctypes.c_int),
+                ("nchan", _c_int_p), ("lchan", _c_int_p), ("nq", ctypes.c_int),
+                ("dq", ctypes.c_double), ("tab", _c_dbl_p)]
+
+
 class QehCell(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_double * 9), ("fft", ctypes.c_int * 3),
                 ("kpt", ctypes.c_double * 3), ("npw", ctypes.c_int),
                 ("miller", _c_int_p), ("vloc", _c_dbl_p), ("nat", ctypes.c_int),
                 ("nproj", _c_int_p), ("beta", _c_dbl_p), ("dmat", _c_dbl_p),
-                ("precision", ctypes.c_int), ("block", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("block", ctypes.c_int),
+                ("projgen", ctypes.POINTER(QehProjgen))]
 
 
 class DavOpts(ctypes.Structure):
@@ -82,6 +89,9 @@ _SIGS = {
     "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
                       _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
     "qeh_density_plan": ([_vp, _sz_p], ctypes.c_int),
+    "qeh_beta_plan": ([ctypes.POINTER(QehCell), _sz_p], ctypes.c_int),
+    "qeh_beta_generate": ([ctypes.POINTER(QehCell), ctypes.c_int, _vp, ctypes.c_long, _vp,
+                           ctypes.c_size_t, _vp], ctypes.c_int),
     "qeh_density": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, _vp, _vp, ctypes.c_size_t],
                     ctypes.c_int),
     "qeh_ctx_profile": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -137,12 +147,38 @@ def _stream_ptr(stream):
     return _vp(stream.cuda_stream)
 
 
-def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block, keep):
-    """Fill a QehCell from host arrays; ``keep`` collects the arrays it points to."""
+def _projgen_struct(pg, keep):
+    """QehProjgen from a dict with tau (nat,3), ityp (nat,), nchan (nsp,),
+    lchan (sum nchan,), dq and tab (sum nchan, nq); ``keep`` holds the arrays."""
+    k = dict(tau=np.ascontiguousarray(pg["tau"], dtype=np.float64),
+             ityp=np.ascontiguousarray(pg["ityp"], dtype=np.int32),
+             nchan=np.ascontiguousarray(pg["nchan"], dtype=np.int32),
+             lchan=np.ascontiguousarray(pg["lchan"], dtype=np.int32),
+             tab=np.ascontiguousarray(pg["tab"], dtype=np.float64))
+    if k["tab"].ndim != 2:
+        raise ValueError("projgen tab must be (channels, nq)")
+    keep.append(k)
+    p = QehProjgen()
+    p.tau = k["tau"].ctypes.data_as(_c_dbl_p)
+    p.ityp = k["ityp"].ctypes.data_as(_c_int_p)
+    p.nsp = int(k["nchan"].shape[0])
+    p.nchan = k["nchan"].ctypes.data_as(_c_int_p)
+    p.lchan = k["lchan"].ctypes.data_as(_c_int_p)
+    p.nq = int(k["tab"].shape[1])
+    p.dq = float(pg["dq"])
+    p.tab = k["tab"].ctypes.data_as(_c_dbl_p)
+    keep.append(p)
+    return p
+
+
+def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block, keep,
+                 projgen=None):
+    """Fill a QehCell from host arrays; ``keep`` collects the arrays it points to.
+    With beta None and a projgen dict, the library builds beta on the device."""
     k = dict(miller=np.ascontiguousarray(miller, dtype=np.int32),
              vloc=np.ascontiguousarray(vloc, dtype=np.float64),
              nproj=np.ascontiguousarray(nproj, dtype=np.int32),
-             beta=np.ascontiguousarray(beta, dtype=np.complex128),
+             beta=None if beta is None else np.ascontiguousarray(beta, dtype=np.complex128),
              dmat=np.ascontiguousarray(dmat, dtype=np.complex128))
     keep.append(k)
     c = QehCell()
@@ -154,11 +190,37 @@ def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, 
     c.vloc = k["vloc"].ctypes.data_as(_c_dbl_p)
     c.nat = int(k["nproj"].shape[0])
     c.nproj = k["nproj"].ctypes.data_as(_c_int_p)
-    c.beta = k["beta"].ctypes.data_as(_c_dbl_p)
+    c.beta = k["beta"].ctypes.data_as(_c_dbl_p) if k["beta"] is not None else None
     c.dmat = k["dmat"].ctypes.data_as(_c_dbl_p)
     c.precision = int(precision)
     c.block = int(block)
+    if beta is None and projgen is not None:
+        c.projgen = ctypes.pointer(_projgen_struct(projgen, keep))
     return c
+
+
+def generate_beta(lattice, kpt, miller, nproj, projgen, precision=QEH_FP64, device=None,
+                  stream=None):
+    """Projectors of ``projgen`` on the sphere ``miller`` built on the device:
+    (nkb, npw) complex128 (QEH_FP64) or complex64 (QEH_MIXED) CUDA tensor."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda")
+    keep = []
+    miller = np.ascontiguousarray(miller, dtype=np.int32)
+    nproj = np.ascontiguousarray(nproj, dtype=np.int32)
+    c = _cell_struct(lattice, (1, 1, 1), kpt, miller, np.zeros(1), nproj, None,
+                     np.zeros(0, dtype=np.complex128), precision, 1, keep, projgen=projgen)
+    n = ctypes.c_size_t()
+    _check(_lib.qeh_beta_plan(ctypes.byref(c), ctypes.byref(n)), "qeh_beta_plan")
+    work = torch.empty(max(int(n.value), 256), dtype=torch.uint8, device=dev)
+    nkb, npw = int(nproj.sum()), int(miller.shape[0])
+    out = torch.empty((nkb, npw), dtype=torch.complex128 if precision == QEH_FP64
+                      else torch.complex64, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    _check(_lib.qeh_beta_generate(ctypes.byref(c), int(precision), _vp(out.data_ptr()), npw,
+                                  _vp(work.data_ptr()), int(work.numel()), _stream_ptr(st)),
+           "qeh_beta_generate")
+    return out
 
 
 class Server:
@@ -180,8 +242,10 @@ class Server:
         keep = []
         arr = (QehCell * len(cells))()
         for i, c in enumerate(cells):
-            arr[i] = _cell_struct(c.lattice, c.fft, c.kpt, c.miller, c.vloc, c.nproj, c.beta,
-                                  c.dmat, precision, block or nb, keep)
+            pg = getattr(c, "projgen", None)
+            arr[i] = _cell_struct(c.lattice, c.fft, c.kpt, c.miller, c.vloc, c.nproj,
+                                  None if pg is not None else c.beta, c.dmat, precision,
+                                  block or nb, keep, projgen=pg)
         psi = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).ravel()
                                                    for p in psi0s]))
         o = DavOpts(int(nvecx), float(rtol), int(maxiter))
@@ -232,33 +296,19 @@ class Context:
 
     Inputs are plain host arrays: lattice (3,3) rows a_i, fft (N1,N2,N3), kpt (3,),
     miller (npw,3) int, vloc (N3,N2,N1) float64, nproj (nat,) int,
-    beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128.
+    beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128.  With beta None,
+    ``projgen`` (a dict: tau, ityp, nchan, lchan, dq, tab) describes the radial
+    tables from which the library builds beta on the device.
     """
 
     def __init__(self, lattice, fft, kpt, miller, vloc, nproj, beta, dmat, *,
-                 precision=QEH_FP64, block=64, device=None, stream=None):
+                 precision=QEH_FP64, block=64, device=None, stream=None, projgen=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
-        self._keep = dict(
-            miller=np.ascontiguousarray(miller, dtype=np.int32),
-            vloc=np.ascontiguousarray(vloc, dtype=np.float64),
-            nproj=np.ascontiguousarray(nproj, dtype=np.int32),
-            beta=np.ascontiguousarray(beta, dtype=np.complex128),
-            dmat=np.ascontiguousarray(dmat, dtype=np.complex128))
-        k = self._keep
-        c = QehCell()
-        c.lattice[:] = [float(x) for x in np.asarray(lattice, dtype=np.float64).ravel()]
-        c.fft[:] = [int(x) for x in fft]
-        c.kpt[:] = [float(x) for x in np.asarray(kpt, dtype=np.float64).ravel()]
-        c.npw = int(k["miller"].shape[0])
-        c.miller = k["miller"].ctypes.data_as(_c_int_p)
-        c.vloc = k["vloc"].ctypes.data_as(_c_dbl_p)
-        c.nat = int(k["nproj"].shape[0])
-        c.nproj = k["nproj"].ctypes.data_as(_c_int_p)
-        c.beta = k["beta"].ctypes.data_as(_c_dbl_p)
-        c.dmat = k["dmat"].ctypes.data_as(_c_dbl_p)
-        c.precision = int(precision)
-        c.block = int(block)
+        keep = []
+        c = _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block,
+                         keep, projgen=projgen)
+        self._keep = keep
         self._cell = c
         nbytes = ctypes.c_size_t()
         _check(_lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(nbytes)), "qeh_ctx_plan")
@@ -280,8 +330,9 @@ class Context:
 
     @classmethod
     def from_cell(cls, cell, **kw):
+        pg = kw.get("projgen")
         return cls(cell.lattice, cell.fft, cell.kpt, cell.miller, cell.vloc, cell.nproj,
-                   cell.beta, cell.dmat, **kw)
+                   None if pg is not None else cell.beta, cell.dmat, **kw)
 
     # ---------------------------------------------------------------- H|psi>
     def _bands(self, psi):

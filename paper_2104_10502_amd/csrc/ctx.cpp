@@ -138,7 +138,8 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
     nkb += c->nproj[a];
     nd += (long)c->nproj[a] * c->nproj[a];
   }
-  if (nkb > 0 && (!c->beta || !c->dmat)) return invalid("beta / dmat null with projectors");
+  if (nkb > 0 && !c->dmat) return invalid("dmat null with projectors");
+  if (nkb > 0 && !c->beta && !c->projgen) return invalid("beta and projgen both null with projectors");
   for (int i = 0; i < 9; ++i)
     if (!std::isfinite(c->lattice[i])) return invalid("lattice not finite");
   for (int i = 0; i < 3; ++i)
@@ -186,11 +187,16 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
       set_error("vloc has a non-finite value");
       return QEH_ERR_NUMERIC;
     }
-  for (long i = 0; i < 2 * nkb * (long)c->npw; ++i)
-    if (!std::isfinite(c->beta[i])) {
-      set_error("beta has a non-finite value");
-      return QEH_ERR_NUMERIC;
-    }
+  if (nkb > 0 && c->beta) {
+    for (long i = 0; i < 2 * nkb * (long)c->npw; ++i)
+      if (!std::isfinite(c->beta[i])) {
+        set_error("beta has a non-finite value");
+        return QEH_ERR_NUMERIC;
+      }
+  } else if (nkb > 0) {
+    const qeh_status st = projgen_validate(c);
+    if (st != QEH_OK) return st;
+  }
   for (long i = 0; i < 2 * nd; ++i)
     if (!std::isfinite(c->dmat[i])) {
       set_error("dmat has a non-finite value");
@@ -203,7 +209,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 struct Layout {
   size_t off_stick_off, off_gmap, off_tidx, off_tidx_dit, off_xin, off_kin, off_hdiag, off_vs,
       off_tw, off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part,
-      off_ps, off_big, off_colstart, off_psi32;
+      off_ps, off_big, off_colstart, off_psi32, off_pgen;
   size_t total;
 };
 
@@ -390,6 +396,8 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
                                          : 0);
   L.off_colstart = bump(&cur, 4 * (size_t)(hm.ext + 1));
   L.off_psi32 = bump(&cur, c->precision == QEH_MIXED ? 8 * (size_t)c->block * c->npw : 0);
+  // projectors built on the device: the generator's staging area
+  L.off_pgen = bump(&cur, g.nkb > 0 && !c->beta ? projgen_layout(c).total : 0);
   L.total = cur;
   return L;
 }
@@ -571,8 +579,9 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
         pnb[i0 + i] = n;
         pdoff[i0 + i] = doff + i * n;
       }
-      // nonlocal diagonal: sum_ij Re(beta_i D_ij conj(beta_j))
-      for (int gg = 0; gg < npw; ++gg) {
+      // nonlocal diagonal: sum_ij Re(beta_i D_ij conj(beta_j)) (on the device
+      // when beta is built there)
+      for (int gg = 0; gg < npw && cell->beta; ++gg) {
         double acc = 0.0;
         for (int i = 0; i < n; ++i) {
           const double *bi = cell->beta + 2 * ((size_t)(i0 + i) * npw + gg);
@@ -631,7 +640,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   if (f64) {
     up(c->d.vs, vs64.data(), 8 * nfft);
     up(c->d.tw, tw64.data(), 16 * (size_t)ntw);
-    up(c->d.beta, cell->beta, 16 * (size_t)g.nkb * npw);
+    if (cell->beta) up(c->d.beta, cell->beta, 16 * (size_t)g.nkb * npw);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   } else {
     f32.resize(nfft);
@@ -643,7 +652,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
     up(c->d.tw, f32.data(), 4 * f32.size());
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     // beta in slices of 16M complex to bound the host staging copy
-    const size_t tot = (size_t)g.nkb * npw, sl = (size_t)1 << 24;
+    const size_t tot = cell->beta ? (size_t)g.nkb * npw : 0, sl = (size_t)1 << 24;
     for (size_t o = 0; o < tot && e == hipSuccess; o += sl) {
       const size_t nn = std::min(sl, tot - o);
       f32.resize(2 * nn);
@@ -656,6 +665,15 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "qeh_ctx_create upload");
+  }
+  if (g.nkb > 0 && !cell->beta) {
+    // beta (context precision) and the nonlocal part of diag(H) on the device
+    const qeh_status pst = projgen_run(cell, f64, c->d.beta, npw, A + L.off_pgen, s, c->d.dmat,
+                                       c->d.hdiag);
+    if (pst != QEH_OK) {
+      delete c;
+      return pst;
+    }
   }
   *out = c;
   return QEH_OK;

@@ -167,6 +167,30 @@ hipError_t launch_density_plane(const qeh_ctx *c, const DensityGeom &dg, int nbk
 hipError_t launch_density_reduce(const double *partial, int nsub, long npts, double scale,
                                  double *rho, int accumulate, hipStream_t s);
 
+// ---- projectors built on the device (beta.cpp, beta_kernels.hip) -----------
+// Workspace of the generator: k+G vectors [3][npw] (SoA), per-atom int4
+// {species, first row, projectors, D offset}, positions [nat][3], channel
+// offsets per species [nsp+1], l per channel, tables [channels][nq].
+struct ProjgenLayout {
+  size_t off_q, off_atom, off_tau, off_chan0, off_lchan, off_tab, total;
+};
+ProjgenLayout projgen_layout(const qeh_cell *c);   // c->projgen set
+// Checks c->projgen against the cell (nproj per atom, table range over the
+// sphere, finiteness); c's Miller list and lattice must already be valid.
+qeh_status projgen_validate(const qeh_cell *c);
+// Stages the generator inputs into work, writes beta (nkb rows of ldb complex,
+// double2 if f64 else float2) and, when hdiag_dev is set, adds the nonlocal
+// part of diag(H) (D blocks from dmat_dev); returns after the stream drained.
+qeh_status projgen_run(const qeh_cell *c, bool f64, void *out, long ldb, char *work,
+                       hipStream_t s, const double2 *dmat_dev, double *hdiag_dev);
+hipError_t launch_beta_gen(bool f64, const double *q, int npw, int nat, const int4 *atoms,
+                           const double *tau, const int *chan0, const int *lchan,
+                           const double *tab, int nq, double dq, double pref, void *beta,
+                           long ldb, hipStream_t s);
+hipError_t launch_nl_diag(bool f64, const void *beta, long ldb, int npw, int nat,
+                          const int4 *atoms, const double2 *dmat, double *hdiag,
+                          hipStream_t s);
+
 // ---- complex GEMM launchers (gemm_kernels.hip) ----------------------------
 // C[m][n] (+)= sum_k opA(A[m][k]) opB(B(k,n)), complex, MFMA.
 //   A: element (m,k) at A[m*lda + k], conjugated if conjA.

@@ -48,12 +48,27 @@ struct HostCell {
   qeh_cell cell{};
   std::vector<int> miller, nproj;
   std::vector<double> vloc, beta, dmat, psi0;
+  // radial-table description when beta is built on the device
+  bool has_pg = false;
+  qeh_projgen pg{};
+  std::vector<double> tau, tab;
+  std::vector<int> ityp, nchan, lchan;
   void bind() {
     cell.miller = miller.data();
     cell.vloc = vloc.data();
     cell.nproj = nproj.empty() ? nullptr : nproj.data();
     cell.beta = beta.empty() ? nullptr : beta.data();
     cell.dmat = dmat.empty() ? nullptr : dmat.data();
+    if (has_pg) {
+      pg.tau = tau.data();
+      pg.ityp = ityp.data();
+      pg.nchan = nchan.data();
+      pg.lchan = lchan.empty() ? nullptr : lchan.data();
+      pg.tab = tab.data();
+      cell.projgen = &pg;
+    } else {
+      cell.projgen = nullptr;
+    }
   }
 };
 
@@ -352,7 +367,20 @@ void copy_cell(const qeh_cell *c, const double *psi0, int nb, HostCell *h) {
       nd += (long)c->nproj[a] * c->nproj[a];
     }
   }
-  if (nkb) h->beta.assign(c->beta, c->beta + 2 * nkb * npw);
+  if (nkb && c->beta) {
+    h->beta.assign(c->beta, c->beta + 2 * nkb * npw);
+  } else if (nkb && c->projgen) {
+    const qeh_projgen *p = c->projgen;
+    h->has_pg = true;
+    h->pg = *p;
+    h->tau.assign(p->tau, p->tau + 3 * (size_t)c->nat);
+    h->ityp.assign(p->ityp, p->ityp + c->nat);
+    h->nchan.assign(p->nchan, p->nchan + p->nsp);
+    long nch = 0;
+    for (int s2 = 0; s2 < p->nsp; ++s2) nch += p->nchan[s2];
+    if (nch) h->lchan.assign(p->lchan, p->lchan + nch);
+    h->tab.assign(p->tab, p->tab + (size_t)nch * p->nq);
+  }
   if (nd) h->dmat.assign(c->dmat, c->dmat + 2 * nd);
   h->psi0.assign(psi0, psi0 + 2 * (size_t)nb * npw);
   h->bind();

@@ -48,9 +48,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "qeh.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell), offsetof(qeh_cell, npw),
-         offsetof(qeh_cell, miller), offsetof(qeh_cell, beta), offsetof(qeh_cell, block),
-         sizeof(qeh_dav_opts), sizeof(qeh_dav_info));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell),
+         offsetof(qeh_cell, npw), offsetof(qeh_cell, miller), offsetof(qeh_cell, beta),
+         offsetof(qeh_cell, block), sizeof(qeh_dav_opts), sizeof(qeh_dav_info),
+         offsetof(qeh_cell, projgen), sizeof(qeh_projgen), offsetof(qeh_projgen, dq),
+         offsetof(qeh_projgen, tab));
   return 0;
 }
 ''')
@@ -60,12 +62,27 @@ int main(void) {
     vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     C = q.QehCell
+    P = q.QehProjgen
     assert vals == [ctypes.sizeof(C), C.npw.offset, C.miller.offset, C.beta.offset,
-                    C.block.offset, ctypes.sizeof(q.DavOpts), ctypes.sizeof(q.DavInfo)]
+                    C.block.offset, ctypes.sizeof(q.DavOpts), ctypes.sizeof(q.DavInfo),
+                    C.projgen.offset, ctypes.sizeof(P), P.dq.offset, P.tab.offset]
 
 
 def _plan(cell, **kw):
     q = _q()
+    if "projgen" in kw:
+        # beta built on the device: marshalled by the binding's own helper
+        keep = []
+        c = q._cell_struct(cell.lattice, kw.get("fft", cell.fft), cell.kpt, cell.miller,
+                           cell.vloc, kw.get("nproj", cell.nproj), None, cell.dmat,
+                           kw.get("precision", 0), kw.get("block", 16), keep,
+                           projgen=kw["projgen"])
+        n = ctypes.c_size_t()
+        st = q._lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(n))
+        nb = ctypes.c_size_t()
+        stb = q._lib.qeh_beta_plan(ctypes.byref(c), ctypes.byref(nb))
+        assert stb == st
+        return st, n.value, q._lib.qeh_last_error().decode()
     miller = np.ascontiguousarray(kw.get("miller", cell.miller), dtype=np.int32)
     vloc = np.ascontiguousarray(kw.get("vloc", cell.vloc), dtype=np.float64)
     nproj = np.ascontiguousarray(cell.nproj, dtype=np.int32)
@@ -144,3 +161,50 @@ def test_status_strings():
     q = _q()
     for s in range(-8, 1):
         assert q._lib.qeh_status_str(s)
+
+
+def test_plan_with_device_projectors(c1):
+    # beta built on the device: the plan adds the generator's staging area
+    st, n, _ = _plan(c1)
+    stg, ng, msg = _plan(c1, projgen=cellgen.projgen_tables(c1))
+    assert st == 0 and stg == 0, msg
+    assert ng > n
+
+
+def test_plan_rejects_bad_projgen(c1):
+    pg = cellgen.projgen_tables(c1)
+    # table ends before the sphere does
+    short = dict(pg, tab=pg["tab"][:, :100])
+    st, _, msg = _plan(c1, projgen=short)
+    assert st == -1 and "table" in msg
+    # projector count of an atom does not match its species' channels
+    st, _, msg = _plan(c1, projgen=pg, nproj=np.array([4, 3]))
+    assert st == -1 and "nproj" in msg
+    # l out of range
+    st, _, msg = _plan(c1, projgen=dict(pg, lchan=np.array([0, 3])))
+    assert st == -1 and "l must" in msg
+    # species index out of range
+    st, _, msg = _plan(c1, projgen=dict(pg, ityp=np.array([0, 1])))
+    assert st == -1 and "ityp" in msg
+    # nq < 4 and dq <= 0
+    st, _, _ = _plan(c1, projgen=dict(pg, tab=pg["tab"][:, :3]))
+    assert st == -1
+    st, _, _ = _plan(c1, projgen=dict(pg, dq=0.0))
+    assert st == -1
+    # non-finite table value and position
+    bad = pg["tab"].copy()
+    bad[1, 7] = np.inf
+    assert _plan(c1, projgen=dict(pg, tab=bad))[0] == -3
+    tau = pg["tau"].copy()
+    tau[0, 1] = np.nan
+    assert _plan(c1, projgen=dict(pg, tau=tau))[0] == -3
+
+
+def test_plan_rejects_no_beta_no_projgen(c1):
+    q = _q()
+    keep = []
+    c = q._cell_struct(c1.lattice, c1.fft, c1.kpt, c1.miller, c1.vloc, c1.nproj, None,
+                       c1.dmat, 0, 16, keep)
+    n = ctypes.c_size_t()
+    assert q._lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(n)) == -1
+    assert "projgen" in q._lib.qeh_last_error().decode()
