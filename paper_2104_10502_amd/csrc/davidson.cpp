@@ -525,10 +525,13 @@ bool DavRun::advance() {
             ++stall_[b];
           }
           // mixed form: the single-precision floor stops the residual; accept a
-          // band whose Ritz value has settled or whose small residual has not
-          // improved by 10% in 3 iterations
+          // band whose Ritz value has settled, whose small residual has not
+          // improved by 10% in 3 iterations, or whose residual below 100x the
+          // threshold has not improved by 10% in 5 (the floor grows with the
+          // cutoff and the number of projectors)
           if (mixed_ && std::fabs(h_eps_[b] - eps_prev_[b]) <= 1e-8) conv = true;
           if (mixed_ && stall_[b] >= 3 && r <= 10.0 * thr_) conv = true;
+          if (mixed_ && stall_[b] >= 5 && r <= 100.0 * thr_) conv = true;
           if (!conv) h_idx_[nc++] = b;
         }
         for (int b = 0; b < nb; ++b) eps_prev_[b] = h_eps_[b];
