@@ -124,6 +124,42 @@ def stored_traffic(kernel, prec):
     return None if k is None else k["bytes_per_launch"]
 
 
+def time_projectors(q, torch, cell, reps=5):
+    """Projectors of the benchmark cell built on the device from radial tables
+    (wall time per qeh_beta_generate call, which includes its host-side
+    validation and staging; the generator kernel's own time is in the kernel
+    trace), and context set-up with host-built projectors (upload and host
+    diag(H) sums) against device-built ones."""
+    import cellgen
+    pg = cellgen.projgen_tables(cell)
+    out = {}
+    for prec in (q.QEH_MIXED, q.QEH_FP64):
+        name = "mixed" if prec else "fp64"
+        b = q.generate_beta(cell.lattice, cell.kpt, cell.miller, cell.nproj, pg, precision=prec)
+        del b
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            b = q.generate_beta(cell.lattice, cell.kpt, cell.miller, cell.nproj, pg,
+                                precision=prec)
+            del b
+        torch.cuda.synchronize()
+        gen_ms = (time.perf_counter() - t0) / reps * 1e3
+        setup = {}
+        for kind in ("host", "device"):
+            t0 = time.perf_counter()
+            ctx = q.Context.from_cell(cell, precision=prec, block=128,
+                                      projgen=pg if kind == "device" else None)
+            torch.cuda.synchronize()
+            setup[kind] = (time.perf_counter() - t0) * 1e3
+            ctx.close()
+        out[name] = dict(generate_call_ms=gen_ms,
+                         beta_bytes=cell.nkb * cell.npw * (8 if prec else 16),
+                         ctx_create_ms_host_beta=setup["host"],
+                         ctx_create_ms_device_beta=setup["device"])
+    return out
+
+
 def time_apply(q, torch, cell, prec, nb, steps, warmup):
     """Timed steps without instrumentation (the reported rate), then the same
     number of steps with per-stage HIP events (the kernel breakdown)."""
@@ -227,17 +263,25 @@ def cpu_baseline(cell, budget_s=12.0):
                        "cell, %.1f s" % (done, dt))
 
 
-def _make_request(r):
+def _make_request(r, device_beta=True):
+    """Cells and start vectors of one served request.  With device_beta the
+    cells carry the projectors' radial tables and the library builds beta on
+    the device; otherwise the host builds beta and the request carries it."""
+    import dataclasses
     import cellgen
-    cells = [cellgen.random_served_cell(r["nat"], r["ecutwfc"], k, r["seed"]) for k in range(r["nk"])]
+    cells = [cellgen.random_served_cell(r["nat"], r["ecutwfc"], k, r["seed"],
+                                        with_beta=not device_beta) for k in range(r["nk"])]
+    if device_beta:
+        cells = [dataclasses.replace(c, projgen=cellgen.projgen_tables(c)) for c in cells]
     psis = [cellgen.make_psi0(c.npw, c.nbnd, seed=10502 + k) for k, c in enumerate(cells)]
     return cells, psis
 
 
-def make_trace(duration, rate, seed=2104):
+def make_trace(duration, rate, seed=2104, device_beta=True):
     """Generate the served requests (host only; called before any GPU use, in a
     pool of spawned processes)."""
     import concurrent.futures as cf
+    import functools
     import multiprocessing as mp
     import cellgen
     trace = [r for r in cellgen.served_trace(int(rate * duration * 2) + 10, rate=rate, seed=seed)
@@ -245,11 +289,13 @@ def make_trace(duration, rate, seed=2104):
     t_gen = time.perf_counter()
     with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4),
                                 mp_context=mp.get_context("spawn")) as ex:
-        reqs = list(ex.map(_make_request, trace, chunksize=4))
+        reqs = list(ex.map(functools.partial(_make_request, device_beta=device_beta), trace,
+                           chunksize=4))
     return trace, reqs, time.perf_counter() - t_gen
 
 
-def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
+def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96,
+                device_beta=True):
     """Replay a Poisson trace of Davidson requests (random cubic cells, 8-128 atoms,
     ecutwfc in {20,25,30} Ry, 1-4 k-points, nb = 2 nat, mixed form) against the server."""
     srv = q.Server(int(arena_gib) << 30, max_slots=slots)
@@ -304,19 +350,22 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96):
                 mean_davidson_iters=float(np.mean(iters)), max_davidson_iters=int(max(iters)),
                 gpu_busy_fraction=st["busy_s"] / max(st["uptime_s"], 1e-9),
                 max_submit_lag_s=lag, slots=slots, arena_gib=arena_gib,
+                projectors="built on the device from radial tables" if device_beta
+                else "built on the host, copied with the request",
                 generation_s=t_gen)
 
 
 def serve_child_main(a):
     """Served-trace leg (child process): trace on the host, wait for the
     parent's go, replay, print one JSON line."""
-    served = make_trace(a.serve, a.serve_rate)
+    served = make_trace(a.serve, a.serve_rate, device_beta=not a.serve_host_beta)
     print("# serve: trace of %d requests ready" % len(served[0]), file=sys.stderr, flush=True)
     print("ready", flush=True)
     if sys.stdin.readline().strip() != "go":
         return
     import paper_2104_10502_amd as q
-    res = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate, slots=a.serve_slots)
+    res = serve_bench(q, *served, duration=a.serve, rate=a.serve_rate, slots=a.serve_slots,
+                      device_beta=not a.serve_host_beta)
     print(json.dumps(res), flush=True)
 
 
@@ -344,11 +393,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the charge density leg (128 bands, both forms)")
+    ap.add_argument("--no-projectors", action="store_true",
+                    help="skip the projector-generation leg")
     ap.add_argument("--serve", type=float, default=5.0,
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-host-beta", action="store_true",
+                    help="served requests carry host-built projectors instead of radial tables")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (the reference "
                          "kernel for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -375,7 +428,8 @@ def main():
         env.setdefault("GPU_MAX_HW_QUEUES", "16")
         child = subprocess.Popen(
             [sys.executable, os.path.abspath(__file__), "--serve-child", "--serve", str(a.serve),
-             "--serve-rate", str(a.serve_rate), "--serve-slots", str(a.serve_slots)],
+             "--serve-rate", str(a.serve_rate), "--serve-slots", str(a.serve_slots)] +
+            (["--serve-host-beta"] if a.serve_host_beta else []),
             stdin=subprocess.PIPE, stdout=subprocess.PIPE, env=env, text=True)
         # host-side trace generation uses all cores: let it finish before the
         # timed device work starts
@@ -440,6 +494,9 @@ def main():
                                                             v["bound"])
                           for k, v in per.items())), file=sys.stderr, flush=True)
         out["density"] = dens
+    if not a.no_projectors:
+        out["projectors"] = time_projectors(q, torch, cell)
+        print("# projectors: %s" % json.dumps(out["projectors"]), file=sys.stderr, flush=True)
     if a.davidson:
         psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
         dav = {}

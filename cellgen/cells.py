@@ -388,15 +388,18 @@ def make_psi0(npw: int, nb: int, seed: int = 10502) -> np.ndarray:
 SERVE_KFRAC = [(.25, .25, .25), (.25, .25, -.25), (.25, -.25, .25), (-.25, .25, .25)]
 
 
-def random_served_cell(nat: int, ecutwfc: float, kidx: int, seed: int) -> Cell:
+def random_served_cell(nat: int, ecutwfc: float, kidx: int, seed: int,
+                       with_beta: bool = True) -> Cell:
     """Random cubic cell at 8 atoms per 160 bohr^3, uniform random positions,
-    the s+p Gaussian projector form, minimal 5-smooth box, nb = 2 nat."""
+    the s+p Gaussian projector form, minimal 5-smooth box, nb = 2 nat
+    (``with_beta=False`` skips building beta on the host)."""
     a = (20.0 * nat) ** (1.0 / 3.0)
     rng = np.random.default_rng(seed)
     frac = rng.uniform(0.0, 1.0, size=(nat, 3))
     cell = make_cell("serve", seed=seed, lattice=np.diag([a, a, a]), frac=frac,
                      kfrac=SERVE_KFRAC[kidx], ecutwfc=ecutwfc, ecutrho=4 * ecutwfc,
-                     fft=None, proj="sp", dfixed=True, nbnd=2 * nat, block=2 * nat)
+                     fft=None, proj="sp", dfixed=True, nbnd=2 * nat, block=2 * nat,
+                     with_beta=with_beta)
     cell.name = f"serve_n{nat}_e{int(ecutwfc)}_k{kidx}"
     return cell
 
