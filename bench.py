@@ -307,13 +307,16 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96,
     t0 = time.perf_counter()
     lag = 0.0
     tickets = []
+    submit_s = []
     for r, (cells, psis) in zip(trace, reqs):
         delay = r["t_arrive"] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
         else:
             lag = max(lag, -delay)
+        ts = time.perf_counter()
         tickets.append(srv.submit(cells, psis, cells[0].nbnd, precision=q.QEH_MIXED))
+        submit_s.append(time.perf_counter() - ts)
     res = {}
     t_note = time.perf_counter()
     while len(res) < len(tickets):
@@ -349,7 +352,8 @@ def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96,
                 mean_running_requests=run / span, peak_running_jobs=st["peak_running"],
                 mean_davidson_iters=float(np.mean(iters)), max_davidson_iters=int(max(iters)),
                 gpu_busy_fraction=st["busy_s"] / max(st["uptime_s"], 1e-9),
-                max_submit_lag_s=lag, slots=slots, arena_gib=arena_gib,
+                max_submit_lag_s=lag, mean_submit_call_s=float(np.mean(submit_s)),
+                max_submit_call_s=float(np.max(submit_s)), slots=slots, arena_gib=arena_gib,
                 projectors="built on the device from radial tables" if device_beta
                 else "built on the host, copied with the request",
                 generation_s=t_gen)

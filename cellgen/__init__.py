@@ -17,9 +17,9 @@ standard plane-wave pseudopotential ones with Gaussian model potentials.
 from .cells import (Cell, PROJ_SETS, make_cell, make_psi0, config_names,
                     random_served_cell, served_trace, sphere_miller,
                     fft_box_min, vloc_image_sum, vloc_fourier, radial_ft_closed,
-                    real_harmonics_poly, beta_matrix, projgen_tables)
+                    real_harmonics_poly, beta_matrix, projgen_tables, gamma_half)
 
 __all__ = ["Cell", "PROJ_SETS", "make_cell", "make_psi0", "config_names",
            "random_served_cell", "served_trace", "sphere_miller", "fft_box_min",
            "vloc_image_sum", "vloc_fourier", "radial_ft_closed",
-           "real_harmonics_poly", "beta_matrix", "projgen_tables"]
+           "real_harmonics_poly", "beta_matrix", "projgen_tables", "gamma_half"]

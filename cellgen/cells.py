@@ -65,6 +65,8 @@ class Cell:
     # radial-table description of the projectors (see ``projgen_tables``);
     # when set, consumers may build beta from it instead of using ``beta``
     projgen: dict = None
+    # True: a k = 0 cell stored over the half sphere (see ``gamma_half``)
+    gamma: bool = False
 
     @property
     def npw(self) -> int:
@@ -263,6 +265,20 @@ def projgen_tables(cell, dq: float = 0.01) -> dict:
                 nchan=np.array([len(chans)], dtype=np.int32),
                 lchan=np.array([l for (l, _) in chans], dtype=np.int32),
                 dq=float(dq), tab=tab)
+
+
+def gamma_half(cell: Cell) -> Cell:
+    """The same k = 0 cell stored over half of the sphere, for real
+    wavefunctions: the Miller list from (0,0,0) on (every G that follows
+    (0,0,0) lexicographically; the others are their negatives), beta restricted
+    to those columns, ``gamma=True``."""
+    import dataclasses
+    if np.any(np.asarray(cell.kpt) != 0.0):
+        raise ValueError("gamma_half needs k = 0")
+    i0 = int(np.flatnonzero((cell.miller == 0).all(axis=1))[0])
+    beta = None if cell.beta is None else np.ascontiguousarray(cell.beta[:, i0:])
+    return dataclasses.replace(cell, miller=np.ascontiguousarray(cell.miller[i0:]), beta=beta,
+                               gamma=True)
 
 
 def _dmat_blocks(nat: int, proj_set: str, dvals: np.ndarray) -> np.ndarray:

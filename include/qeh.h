@@ -110,7 +110,25 @@ typedef struct {
                              projectors, qeh_ctx_create builds beta on the
                              device from these tables (and diag(H) with it);
                              ignored when beta is given                        */
+  int gamma;              /* 1: real wavefunctions at k = 0 (see below); 0: general k */
 } qeh_cell;
+
+/* Gamma-point cells (gamma = 1): the real-wavefunction case ("k = 0 only
+ * sampling" of section "Evolution of the GPU-enabled version").  With
+ * psi(r) real, psi(-G) = conj(psi(G)), so only half of the sphere is stored:
+ *   kpt must be (0, 0, 0);
+ *   miller lists the half sphere: (0,0,0) first, then every G of the sphere
+ *     that follows (0,0,0) lexicographically (h > 0, or h = 0 and k > 0, or
+ *     h = k = 0 and l > 0), in lexicographic order; npw counts these;
+ *   psi, hpsi, beta rows and the Davidson vectors hold those npw coefficients;
+ *     the imaginary part of psi(G = 0) is not referenced (qeh_davidson sets it
+ *     to zero in psi_inout); beta_i(G = 0) must be real and D real symmetric
+ *     (projectors real in real space);
+ *   two bands share one complex 3D FFT (psi_a + i psi_b is transformed and
+ *     the two results separated from the values at G and -G);
+ *   inner products are 2 Re sum_G conj(a_G) b_G - a_0 b_0 over the stored
+ *     half, so the subspace problem is real symmetric.
+ * qeh_density does not take Gamma contexts (QEH_ERR_INVALID). */
 
 typedef struct qeh_ctx qeh_ctx;
 

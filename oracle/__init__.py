@@ -23,6 +23,8 @@ exascale):
 * ``density``: the charge density generation of the same list of ported
   kernels, rho(r) = (1/Omega) sum_i f_i |psi_i(r)|^2 on the FFT grid;
   ``density_direct`` sums the plane waves point by point (tiny cells).
+* ``gamma.expand`` / ``gamma.restrict``: real wavefunctions at k = 0 stored
+  over half the sphere, rebuilt as full-sphere vectors for the operators above.
 * ``beta_projectors``: the projectors beta_i(k+G) built from their radial
   functions (the "calculation of pseudopotential terms" of the quantum-engine
   modules), with the radial Bessel transform taken by quadrature.
@@ -42,8 +44,9 @@ from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, vloc_coe
 from .davidson import davidson, rayleigh_ritz
 from .density import cell_volume, density, density_direct, psi_real_space
 from .beta import beta_projectors, radial_transform, real_harmonics, spherical_bessel
+from . import gamma
 
 __all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
            "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
            "cell_volume", "density", "density_direct", "psi_real_space", "beta_projectors",
-           "radial_transform", "real_harmonics", "spherical_bessel"]
+           "radial_transform", "real_harmonics", "spherical_bessel", "gamma"]

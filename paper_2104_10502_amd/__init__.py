@@ -58,7 +58,7 @@ class QehCell(ctypes.Structure):
                 ("miller", _c_int_p), ("vloc", _c_dbl_p), ("nat", ctypes.c_int),
                 ("nproj", _c_int_p), ("beta", _c_dbl_p), ("dmat", _c_dbl_p),
                 ("precision", ctypes.c_int), ("block", ctypes.c_int),
-                ("projgen", ctypes.POINTER(QehProjgen))]
+                ("projgen", ctypes.POINTER(QehProjgen)), ("gamma", ctypes.c_int)]
 
 
 class DavOpts(ctypes.Structure):
@@ -172,7 +172,7 @@ def _projgen_struct(pg, keep):
 
 
 def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block, keep,
-                 projgen=None):
+                 projgen=None, gamma=False):
     """Fill a QehCell from host arrays; ``keep`` collects the arrays it points to.
     With beta None and a projgen dict, the library builds beta on the device."""
     k = dict(miller=np.ascontiguousarray(miller, dtype=np.int32),
@@ -196,6 +196,7 @@ def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, 
     c.block = int(block)
     if beta is None and projgen is not None:
         c.projgen = ctypes.pointer(_projgen_struct(projgen, keep))
+    c.gamma = 1 if gamma else 0
     return c
 
 
@@ -245,7 +246,8 @@ class Server:
             pg = getattr(c, "projgen", None)
             arr[i] = _cell_struct(c.lattice, c.fft, c.kpt, c.miller, c.vloc, c.nproj,
                                   None if pg is not None else c.beta, c.dmat, precision,
-                                  block or nb, keep, projgen=pg)
+                                  block or nb, keep, projgen=pg,
+                                  gamma=getattr(c, "gamma", False))
         psi = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).ravel()
                                                    for p in psi0s]))
         o = DavOpts(int(nvecx), float(rtol), int(maxiter))
@@ -298,16 +300,18 @@ class Context:
     miller (npw,3) int, vloc (N3,N2,N1) float64, nproj (nat,) int,
     beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128.  With beta None,
     ``projgen`` (a dict: tau, ityp, nchan, lchan, dq, tab) describes the radial
-    tables from which the library builds beta on the device.
+    tables from which the library builds beta on the device.  ``gamma=True``:
+    real wavefunctions at k = 0, miller (and psi, beta) over the half sphere.
     """
 
     def __init__(self, lattice, fft, kpt, miller, vloc, nproj, beta, dmat, *,
-                 precision=QEH_FP64, block=64, device=None, stream=None, projgen=None):
+                 precision=QEH_FP64, block=64, device=None, stream=None, projgen=None,
+                 gamma=False):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         keep = []
         c = _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block,
-                         keep, projgen=projgen)
+                         keep, projgen=projgen, gamma=gamma)
         self._keep = keep
         self._cell = c
         nbytes = ctypes.c_size_t()
@@ -331,6 +335,7 @@ class Context:
     @classmethod
     def from_cell(cls, cell, **kw):
         pg = kw.get("projgen")
+        kw.setdefault("gamma", getattr(cell, "gamma", False))
         return cls(cell.lattice, cell.fft, cell.kpt, cell.miller, cell.vloc, cell.nproj,
                    None if pg is not None else cell.beta, cell.dmat, **kw)
 

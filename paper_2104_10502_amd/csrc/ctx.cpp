@@ -107,7 +107,10 @@ namespace {
 
 struct HostMaps {
   int nst = 0, hmin = 0, ext = 0;
+  int npw_fft = 0;                  // G-vectors the FFT path places (the full sphere)
   std::vector<int> stick_off, stick_h, stick_k;
+  std::vector<int> full;            // Gamma cells: the full sphere's Miller list
+  const int *miller_fft = nullptr;  // Miller list of the FFT sphere (cell's or full)
 };
 
 inline int imod(int a, int n) {
@@ -144,14 +147,34 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
     if (!std::isfinite(c->lattice[i])) return invalid("lattice not finite");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(c->kpt[i])) return invalid("kpt not finite");
-  // Miller list: lexicographic, sticks are contiguous runs, fits the box
-  const int *m = c->miller;
+  if (c->gamma != 0 && c->gamma != 1) return invalid("gamma must be 0 or 1");
+  // Gamma cells store the half sphere, (0,0,0) first; the FFT path places the
+  // full sphere: the negated list reversed (all before (0,0,0)), then the half
+  int npw_fft = c->npw;
+  hm->full.clear();
+  if (c->gamma) {
+    if (c->kpt[0] != 0.0 || c->kpt[1] != 0.0 || c->kpt[2] != 0.0)
+      return invalid("gamma cells need kpt = (0, 0, 0)");
+    if (c->miller[0] != 0 || c->miller[1] != 0 || c->miller[2] != 0)
+      return invalid("gamma cells list (0,0,0) first");
+    npw_fft = 2 * c->npw - 1;
+    hm->full.resize(3 * (size_t)npw_fft);
+    for (int h = 1; h < c->npw; ++h)
+      for (int i = 0; i < 3; ++i) hm->full[3 * (size_t)(c->npw - 1 - h) + i] = -c->miller[3 * h + i];
+    for (int h = 0; h < c->npw; ++h)
+      for (int i = 0; i < 3; ++i) hm->full[3 * (size_t)(c->npw - 1 + h) + i] = c->miller[3 * h + i];
+  }
+  hm->npw_fft = npw_fft;
+  hm->miller_fft = c->gamma ? hm->full.data() : c->miller;
+  // Miller list: lexicographic, sticks are contiguous runs, fits the box (for a
+  // Gamma cell this also checks that the half list follows (0,0,0))
+  const int *m = hm->miller_fft;
   int lo[3], hi[3];
   for (int i = 0; i < 3; ++i) lo[i] = hi[i] = m[i];
   hm->stick_off.clear();
   hm->stick_h.clear();
   hm->stick_k.clear();
-  for (int g = 0; g < c->npw; ++g) {
+  for (int g = 0; g < npw_fft; ++g) {
     const int *mg = m + 3 * g;
     for (int i = 0; i < 3; ++i) {
       lo[i] = std::min(lo[i], mg[i]);
@@ -173,7 +196,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
       hm->stick_k.push_back(mg[1]);
     }
   }
-  hm->stick_off.push_back(c->npw);
+  hm->stick_off.push_back(npw_fft);
   for (int i = 0; i < 3; ++i)
     if (hi[i] - lo[i] >= c->fft[i])
       return invalid("Miller index range exceeds the FFT box on axis " + std::to_string(i));
@@ -202,6 +225,15 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
       set_error("dmat has a non-finite value");
       return QEH_ERR_NUMERIC;
     }
+  if (c->gamma) {
+    // real projectors: beta_i(G = 0) real, D real symmetric
+    for (long i = 0; i < nd; ++i)
+      if (c->dmat[2 * i + 1] != 0.0) return invalid("gamma cells need a real D");
+    if (c->beta)
+      for (long i = 0; i < nkb; ++i)
+        if (c->beta[2 * i * (long)c->npw + 1] != 0.0)
+          return invalid("gamma cells need beta_i(G = 0) real");
+  }
   return QEH_OK;
 }
 
@@ -209,7 +241,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 struct Layout {
   size_t off_stick_off, off_gmap, off_tidx, off_tidx_dit, off_xin, off_kin, off_hdiag, off_vs,
       off_tw, off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part,
-      off_ps, off_big, off_colstart, off_psi32, off_pgen;
+      off_ps, off_big, off_colstart, off_psi32, off_pgen, off_gbuf;
   size_t total;
 };
 
@@ -374,7 +406,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   const size_t rs = c->precision == QEH_FP64 ? 8 : 4;
   const size_t nfft = (size_t)c->fft[0] * c->fft[1] * c->fft[2];
   L.off_stick_off = bump(&cur, 4 * (hm.nst + 1));
-  L.off_gmap = bump(&cur, 4 * (size_t)c->npw);
+  L.off_gmap = bump(&cur, 4 * (size_t)hm.npw_fft);
   L.off_tidx = bump(&cur, 4 * (size_t)hm.nst);
   L.off_tidx_dit = bump(&cur, 4 * (size_t)hm.nst);
   L.off_xin = bump(&cur, 4 * (size_t)c->fft[0]);
@@ -395,9 +427,11 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
                                                c->fft[1]
                                          : 0);
   L.off_colstart = bump(&cur, 4 * (size_t)(hm.ext + 1));
-  L.off_psi32 = bump(&cur, c->precision == QEH_MIXED ? 8 * (size_t)c->block * c->npw : 0);
+  L.off_psi32 = bump(&cur, c->precision == QEH_MIXED ? 8 * (size_t)c->block * hm.npw_fft : 0);
   // projectors built on the device: the generator's staging area
   L.off_pgen = bump(&cur, g.nkb > 0 && !c->beta ? projgen_layout(c).total : 0);
+  // Gamma: band pairs packed over the full sphere (FP64), reused for the result
+  L.off_gbuf = bump(&cur, c->gamma ? 16 * (size_t)((c->block + 1) / 2) * hm.npw_fft : 0);
   L.total = cur;
   return L;
 }
@@ -478,6 +512,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   }
   qeh_ctx *c = new qeh_ctx();
   c->npw = cell->npw;
+  c->npw_fft = hm.npw_fft;
+  c->gamma = cell->gamma;
   c->nst = hm.nst;
   c->nkb = g.nkb;
   c->nat = cell->nat;
@@ -524,16 +560,18 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.big = g.plane_path == 1 ? A + L.off_big : nullptr;
   c->d.colstart = reinterpret_cast<int *>(A + L.off_colstart);
   c->d.psi32 = c->prec == QEH_MIXED ? reinterpret_cast<float2 *>(A + L.off_psi32) : nullptr;
+  c->d.gbuf = c->gamma ? reinterpret_cast<double2 *>(A + L.off_gbuf) : nullptr;
 
   const int npw = cell->npw, n1 = c->n1, n2 = c->n2, n3 = c->n3;
   const size_t nfft = (size_t)n1 * n2 * n3;
   const bool f64 = c->prec == QEH_FP64;
   // ---- host-side maps
-  std::vector<int> gmap(npw), tidx(hm.nst), tidx_dit(hm.nst), xin(n1, -1);
+  std::vector<int> gmap(hm.npw_fft), tidx(hm.nst), tidx_dit(hm.nst), xin(n1, -1);
+  const int *mf = hm.miller_fft;
   for (int s = 0; s < hm.nst; ++s) {
     for (int gg = hm.stick_off[s]; gg < hm.stick_off[s + 1]; ++gg)
-      gmap[gg] = s * c->sg.ldz + (c->zpair ? imod(cell->miller[3 * gg + 2], n3)
-                                           : fft_digit_pos(c->dz, imod(cell->miller[3 * gg + 2], n3)));
+      gmap[gg] = s * c->sg.ldz + (c->zpair ? imod(mf[3 * gg + 2], n3)
+                                           : fft_digit_pos(c->dz, imod(mf[3 * gg + 2], n3)));
     const int ky = imod(hm.stick_k[s], n2);
     tidx_dit[s] = (hm.stick_h[s] - hm.hmin) * c->pg.ldT + fft_digit_pos(c->dy, ky);
     tidx[s] = (c->plane_path == 2 || c->plane_path == 4) ? (hm.stick_h[s] - hm.hmin) * c->pg.ldT + ky
@@ -720,7 +758,31 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
                        double2 *hpsi, int ldh) {
   hipError_t e;
   const bool f64 = c->prec == QEH_FP64;
-  if (part == 0 || part == 2) {
+  if ((part == 0 || part == 2) && c->gamma) {
+    // Gamma: bands 2p, 2p+1 go through one complex FFT as psi_2p + i psi_2p+1
+    // over the full sphere (packed into gbuf, whose space then takes the
+    // result), and are separated again with the kinetic term added
+    const int np = (nbk + 1) / 2;
+    {
+      StageGuard g(c, 0);
+      e = launch_gamma_pack(psi, ldpsi, nbk, c->npw, c->d.gbuf, c->npw_fft, c->stream);
+      if (e == hipSuccess) e = launch_k1(c, np, c->d.gbuf, c->npw_fft);
+    }
+    if (e != hipSuccess) return hip_fail(e, "K1 launch");
+    {
+      StageGuard g(c, 1);
+      e = launch_k2(c, np);
+    }
+    if (e != hipSuccess) return hip_fail(e, "K2 launch");
+    {
+      StageGuard g(c, 2);
+      e = launch_k3(c, np, c->d.gbuf, c->npw_fft, c->d.gbuf, c->npw_fft, 0);
+      if (e == hipSuccess)
+        e = launch_gamma_unpack(c->d.gbuf, c->npw_fft, nbk, c->npw, psi, ldpsi, c->d.kin, hpsi,
+                                ldh, c->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "K3 launch");
+  } else if (part == 0 || part == 2) {
     {
       StageGuard g(c, 0);
       e = launch_k1(c, nbk, psi, ldpsi);
@@ -739,9 +801,10 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
   }
   if ((part == 1 || part == 2) && c->nkb > 0) {
     GemmDesc g1{};
-    const bool use32 = !f64 && part == 2;   // K1 has just written psi32
+    // K1 has just written psi32 (not for Gamma: there it holds packed band pairs)
+    const bool use32 = !f64 && part == 2 && !c->gamma;
     g1.A = use32 ? static_cast<const void *>(c->d.psi32) : static_cast<const void *>(psi);
-    g1.lda = use32 ? c->npw : ldpsi;
+    g1.lda = use32 ? c->npw_fft : ldpsi;
     g1.ta = use32 ? T_F2 : T_D2;
     g1.tile = 0;
     g1.B = c->d.beta;
@@ -766,7 +829,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     if (e != hipSuccess) return hip_fail(e, "beta^H psi launch");
     {
       StageGuard g(c, 4);
-      e = launch_dscale(c, nbk);
+      e = launch_dscale(c, nbk, psi, ldpsi);
     }
     if (e != hipSuccess) return hip_fail(e, "D scaling launch");
     GemmDesc g3{};
@@ -844,6 +907,7 @@ DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
 qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const double *occ,
                         double *rho, void *work, size_t work_bytes) {
   if (!c) return invalid("ctx is null");
+  if (c->gamma) return invalid("qeh_density does not take Gamma contexts");
   if (nb < 0) return invalid("nb < 0");
   if (!rho) return invalid("rho is null");
   if (nb > 0 && (!psi || !occ)) return invalid("psi / occ null");
@@ -924,6 +988,7 @@ qeh_status qeh_apply_h_part(qeh_ctx *c, int part, int nb, const double *psi, int
 
 qeh_status qeh_density_plan(const qeh_ctx *c, size_t *work_bytes) {
   if (!c || !work_bytes) return invalid("null argument");
+  if (c->gamma) return invalid("qeh_density does not take Gamma contexts");
   DensityGeom dg{};
   if (!density_geometry(c, &dg)) return invalid("box too large for the density row kernel");
   *work_bytes = density_work(c, dg).total;

@@ -23,11 +23,17 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// Weight of stored coefficient g in a squared norm: 1, or for Gamma vectors
+// (half sphere, G = 0 first) 2 for every G != 0, which stands for G and -G.
+__device__ __forceinline__ double norm_weight(int g, int gamma) {
+  return (gamma && g > 0) ? 2.0 : 1.0;
+}
+
 // one workgroup per band
 __global__ __launch_bounds__(kDT) void resid_norms_kernel(const double2 *__restrict__ P,
                                                           const double2 *__restrict__ Q, long ld,
                                                           int npw, const double *__restrict__ eps,
-                                                          double *__restrict__ norms) {
+                                                          double *__restrict__ norms, int gamma) {
   __shared__ double sh[kDT];
   const int b = blockIdx.x;
   const double e = eps[b];
@@ -37,7 +43,7 @@ __global__ __launch_bounds__(kDT) void resid_norms_kernel(const double2 *__restr
   for (int g = threadIdx.x; g < npw; g += kDT) {
     const double2 a = p[g], h = q[g];
     const double rx = h.x - e * a.x, ry = h.y - e * a.y;
-    acc += rx * rx + ry * ry;
+    acc += norm_weight(g, gamma) * (rx * rx + ry * ry);
   }
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) norms[b] = s;
@@ -46,7 +52,7 @@ __global__ __launch_bounds__(kDT) void resid_norms_kernel(const double2 *__restr
 __global__ __launch_bounds__(kDT) void precond_kernel(
     const double2 *__restrict__ P, const double2 *__restrict__ Q, long ld, int npw,
     const int *__restrict__ idx, const double *__restrict__ eps,
-    const double *__restrict__ hdiag, double2 *__restrict__ V, long ldv) {
+    const double *__restrict__ hdiag, double2 *__restrict__ V, long ldv, int gamma) {
   __shared__ double sh[kDT];
   const int j = blockIdx.x;
   const int b = idx[j];
@@ -61,7 +67,7 @@ __global__ __launch_bounds__(kDT) void precond_kernel(
     const double w = 1.0 / sqrt(1.0 + x * x);
     const double rx = (h.x - e * a.x) * w, ry = (h.y - e * a.y) * w;
     v[g] = make_double2(rx, ry);
-    acc += rx * rx + ry * ry;
+    acc += norm_weight(g, gamma) * (rx * rx + ry * ry);
   }
   const double s = block_sum(acc, sh);
   const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
@@ -128,6 +134,80 @@ __global__ void fill_int_kernel(int *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
+// ---- Gamma point: two real bands per complex FFT ---------------------------
+// The full sphere of nh stored coefficients has 2 nh - 1 entries: index
+// f < nh - 1 is -G of stored h = nh - 1 - f, index f >= nh - 1 is stored
+// h = f - (nh - 1).  Band pair p holds c = psi_2p + i psi_2p+1 (a missing
+// partner is zero) with psi(-G) = conj(psi(G)); the imaginary part of psi at
+// G = 0 is not referenced.
+__global__ void gamma_pack_kernel(const double2 *__restrict__ psi, long ldpsi, int nbk, int nh,
+                                  double2 *__restrict__ out, long ldo) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (f >= 2 * nh - 1) return;
+  const int a = 2 * p, b = 2 * p + 1;
+  const bool neg = f < nh - 1;
+  const int h = neg ? nh - 1 - f : f - (nh - 1);
+  double2 va = psi[(long)a * ldpsi + h];
+  double2 vb = b < nbk ? psi[(long)b * ldpsi + h] : make_double2(0.0, 0.0);
+  if (h == 0) {
+    va.y = 0.0;
+    vb.y = 0.0;
+  }
+  if (neg) {
+    va.y = -va.y;
+    vb.y = -vb.y;
+  }
+  out[(long)p * ldo + f] = make_double2(va.x - vb.y, va.y + vb.x);
+}
+
+// From C = F(V psi_a) + i F(V psi_b) on the full sphere: F(V psi_a)(G) =
+// (C(G) + conj C(-G)) / 2, F(V psi_b)(G) = (C(G) - conj C(-G)) / (2i); plus
+// the kinetic term.  Writes hpsi (overwrites).
+__global__ void gamma_unpack_kernel(const double2 *__restrict__ hc, long ldc, int nbk, int nh,
+                                    const double2 *__restrict__ psi, long ldpsi,
+                                    const double *__restrict__ kin, double2 *__restrict__ hpsi,
+                                    long ldh) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  const int p = blockIdx.y;
+  if (h >= nh) return;
+  const double2 cp = hc[(long)p * ldc + (nh - 1) + h];
+  const double2 cm = hc[(long)p * ldc + (nh - 1) - h];
+  const double k = kin[h];
+  const int a = 2 * p, b = 2 * p + 1;
+  {
+    double2 v = psi[(long)a * ldpsi + h];
+    if (h == 0) v.y = 0.0;
+    hpsi[(long)a * ldh + h] =
+        make_double2(0.5 * (cp.x + cm.x) + k * v.x, 0.5 * (cp.y - cm.y) + k * v.y);
+  }
+  if (b < nbk) {
+    double2 v = psi[(long)b * ldpsi + h];
+    if (h == 0) v.y = 0.0;
+    hpsi[(long)b * ldh + h] =
+        make_double2(0.5 * (cp.y + cm.y) + k * v.x, -0.5 * (cp.x - cm.x) + k * v.y);
+  }
+}
+
+// Inner products of Gamma vectors from the half-sphere sums S(i, j) =
+// sum_h conj(X_i[h]) Y_j[h]: <X_i|Y_j> = 2 Re S(i, j) - X_i[0] Y_j[0] (real
+// parts at G = 0), stored with zero imaginary part.  M col-major (ld), rows
+// i < nrow, columns j < ncol.
+__global__ void gamma_inner_kernel(double2 *M, long ld, int nrow, const double2 *__restrict__ X,
+                                   const double2 *__restrict__ Y, long npw) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nrow; i += gridDim.x * blockDim.x) {
+    const double2 v = M[i + (long)j * ld];
+    M[i + (long)j * ld] =
+        make_double2(2.0 * v.x - X[(long)i * npw].x * Y[(long)j * npw].x, 0.0);
+  }
+}
+
+__global__ void zero_g0_imag_kernel(double2 *psi, long ldpsi, int nb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nb) psi[(long)b * ldpsi].y = 0.0;
+}
+
 }  // namespace
 
 hipError_t launch_tril_adjoint(const double2 *M, double2 *L, double2 *LH, long ld, int n,
@@ -145,20 +225,55 @@ hipError_t launch_fill_int(int *p, int n, int v, hipStream_t s) {
 }
 
 hipError_t launch_resid_norms(const double2 *P, const double2 *Q, long ld, int npw, int nb,
-                              const double *eps, double *norms, hipStream_t s) {
+                              const double *eps, double *norms, int gamma, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(resid_norms_kernel, dim3(nb), dim3(kDT), 0, s, P, Q, ld, npw, eps, norms);
+  hipLaunchKernelGGL(resid_norms_kernel, dim3(nb), dim3(kDT), 0, s, P, Q, ld, npw, eps, norms,
+                     gamma);
   return hipGetLastError();
 }
 
 hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw, const int *idx,
                           int nc, const double *eps, const double *hdiag, double2 *V, long ldv,
-                          hipStream_t s) {
+                          int gamma, hipStream_t s) {
   if (nc <= 0) return hipSuccess;
   hipLaunchKernelGGL(precond_kernel, dim3(nc), dim3(kDT), 0, s, P, Q, ld, npw, idx, eps, hdiag,
-                     V, ldv);
+                     V, ldv, gamma);
   return hipGetLastError();
 }
+
+hipError_t launch_gamma_pack(const double2 *psi, long ldpsi, int nbk, int nh, double2 *out,
+                             long ldo, hipStream_t s) {
+  if (nbk <= 0) return hipSuccess;
+  const int nf = 2 * nh - 1;
+  hipLaunchKernelGGL(gamma_pack_kernel, dim3((nf + 255) / 256, (nbk + 1) / 2), dim3(256), 0, s,
+                     psi, ldpsi, nbk, nh, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_unpack(const double2 *hc, long ldc, int nbk, int nh, const double2 *psi,
+                               long ldpsi, const double *kin, double2 *hpsi, long ldh,
+                               hipStream_t s) {
+  if (nbk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_unpack_kernel, dim3((nh + 255) / 256, (nbk + 1) / 2), dim3(256), 0, s,
+                     hc, ldc, nbk, nh, psi, ldpsi, kin, hpsi, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_inner(double2 *M, long ld, int nrow, int ncol, const double2 *X,
+                              const double2 *Y, long npw, hipStream_t s) {
+  if (nrow <= 0 || ncol <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_inner_kernel, dim3((nrow + 255) / 256, ncol), dim3(256), 0, s, M, ld,
+                     nrow, X, Y, npw);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_g0_imag(double2 *psi, long ldpsi, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_g0_imag_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, psi, ldpsi,
+                     nb);
+  return hipGetLastError();
+}
+
 
 hipError_t launch_copy_rows(const double2 *src, long lds, double2 *dst, long ldd, int npw,
                             int nrows, hipStream_t s) {

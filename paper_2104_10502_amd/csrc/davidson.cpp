@@ -45,19 +45,19 @@ size_t bump2(size_t *cur, size_t bytes) {
 }
 
 qeh_status solver_bytes(int n, size_t *out) {
-  // the answer depends on n only: cache it (the query needs a handle)
+  // the answer depends on n only: cache it; the query needs a handle, made
+  // once (creating one per query cost more than the query itself)
   static std::mutex mu;
   static std::map<int, size_t> cache;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find(n);
-    if (it != cache.end()) {
-      *out = it->second;
-      return QEH_OK;
-    }
+  static rocblas_handle h = nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(n);
+  if (it != cache.end()) {
+    *out = it->second;
+    return QEH_OK;
   }
-  rocblas_handle h;
-  if (rocblas_create_handle(&h) != rocblas_status_success) {
+  if (!h && rocblas_create_handle(&h) != rocblas_status_success) {
+    h = nullptr;
     set_error("rocblas_create_handle failed");
     return QEH_ERR_DEVICE;
   }
@@ -68,9 +68,7 @@ qeh_status solver_bytes(int n, size_t *out) {
                    nullptr);
   size_t sz = 0;
   rocblas_stop_device_memory_size_query(h, &sz);
-  rocblas_destroy_handle(h);
   *out = sz;
-  std::lock_guard<std::mutex> lk(mu);
   cache[n] = sz;
   return QEH_OK;
 }
@@ -101,22 +99,28 @@ hipError_t reduce_cols(const qeh_ctx *c, const double2 *X, int nrow, const doubl
   g.N = nrow;
   g.K = c->npw;
   g.prec = G_F64;
+  hipError_t e;
   if (ns == 1) {
     g.C = out;
     g.ldc = ld;
     g.nsplit = 1;
     g.kchunk = c->npw;
-    return launch_cgemm(g, c->stream);
+    e = launch_cgemm(g, c->stream);
+  } else {
+    g.C = part;
+    g.ldc = nrow;
+    g.nsplit = ns;
+    g.kchunk = kc;
+    g.split_stride = (long)ncol * nrow;
+    e = launch_cgemm(g, c->stream);
+    if (e == hipSuccess)
+      e = launch_splitk_reduce(part, T_D2, (long)ncol * nrow, ns, ncol, nrow, nrow, out, ld, 0,
+                               c->stream);
   }
-  g.C = part;
-  g.ldc = nrow;
-  g.nsplit = ns;
-  g.kchunk = kc;
-  g.split_stride = (long)ncol * nrow;
-  hipError_t e = launch_cgemm(g, c->stream);
-  if (e != hipSuccess) return e;
-  return launch_splitk_reduce(part, T_D2, (long)ncol * nrow, ns, ncol, nrow, nrow, out, ld, 0,
-                              c->stream);
+  // Gamma: half-sphere sums -> real inner products of the full-sphere vectors
+  if (e == hipSuccess && c->gamma)
+    e = launch_gamma_inner(out, ld, nrow, ncol, X, Y, c->npw, c->stream);
+  return e;
 }
 
 // Column-major products of n x n matrices (ld): out = P Q with P given by
@@ -393,6 +397,7 @@ bool DavRun::advance() {
           ok(launch_check_finite(reinterpret_cast<const double *>(psi_ + (size_t)b * ldpsi_),
                                  2 * (long)npw, flag_d_, s));
         ok(launch_copy_rows(psi_, ldpsi_, V_, npw, npw, nb, s));
+        if (c_->gamma) ok(launch_zero_g0_imag(V_, npw, nb, s));   // psi(G = 0) real
         ok(hipMemcpyAsync(h_int_, flag_d_, 4, hipMemcpyDeviceToHost, s));
         phase_ = kCheckInput;
         return false;
@@ -499,7 +504,7 @@ bool DavRun::advance() {
         ev_s_.start(s);
         ok(rotate(c_, Y_, nvecx, nbase_, nb, V_, P_));
         ok(rotate(c_, Y_, nvecx, nbase_, nb, W_, Q_));
-        ok(launch_resid_norms(P_, Q_, npw, npw, nb, eps_d_, norms_d_, s));
+        ok(launch_resid_norms(P_, Q_, npw, npw, nb, eps_d_, norms_d_, c_->gamma, s));
         ev_s_.stop(s);
         have_ritz_ = true;
         ok(hipMemcpyAsync(h_eps_, eps_d_, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
@@ -558,7 +563,7 @@ bool DavRun::advance() {
           nbase_ = nb;
         }
         ok(launch_precond(P_, Q_, npw, npw, idx_d_, nc, eps_d_, c_->d.hdiag,
-                          V_ + (size_t)nbase_ * npw, npw, s));
+                          V_ + (size_t)nbase_ * npw, npw, c_->gamma, s));
         qeh_status st = hpsi(V_ + (size_t)nbase_ * npw, W_ + (size_t)nbase_ * npw, nc);
         if (st != QEH_OK) {
           result_ = st;

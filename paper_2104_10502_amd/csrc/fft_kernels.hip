@@ -1033,7 +1033,7 @@ hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
   hipLaunchKernelGGL(k1_scatter_zinv<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream, psi,
                      ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
                      c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div,
-                     c->prec == QEH_MIXED ? c->d.psi32 : nullptr, c->npw);
+                     c->prec == QEH_MIXED ? c->d.psi32 : nullptr, c->npw_fft);
   return hipGetLastError();
 }
 
@@ -1178,7 +1178,7 @@ template <int N> hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const doub
   allow_lds(k1_pair<N>, lds);
   hipLaunchKernelGGL(k1_pair<N>, dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk), dim3(kNT),
                      lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
-                     c->d.stick_off, c->d.gmap, c->nst, c->d.psi32, c->npw);
+                     c->d.stick_off, c->d.gmap, c->nst, c->d.psi32, c->npw_fft);
   return hipGetLastError();
 }
 

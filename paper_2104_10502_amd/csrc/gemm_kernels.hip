@@ -312,11 +312,15 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP *__restrict
 
 // ---------------------------------------------------------------- D scaling
 // grid (chunk, band).  Chunk c covers whole atoms [p0, p1), p1 - p0 <= 256.
+// Gamma contexts (gpsi set): the partials sum conj(beta) psi over the stored
+// half sphere, and the full-sphere projection is real:
+//   becp = 2 Re(sum) - beta(0) psi(0)   (G = 0 counted once; beta(0) real).
 template <typename TP, typename TS>
 __global__ __launch_bounds__(256) void dscale_kernel(
     const TP *__restrict__ part, long split_stride, int nsplit, int nkb, TS *__restrict__ ps,
     const double2 *__restrict__ dmat, const int *__restrict__ pj0, const int *__restrict__ pnb,
-    const int *__restrict__ pdoff, const int *__restrict__ chunk) {
+    const int *__restrict__ pdoff, const int *__restrict__ chunk,
+    const double2 *__restrict__ gpsi, long ldpsi, const TP *__restrict__ gbeta, long ldb) {
   __shared__ double2 becp[256];
   const int p0 = chunk[blockIdx.x], p1 = chunk[blockIdx.x + 1];
   const int b = blockIdx.y;
@@ -342,6 +346,12 @@ __global__ __launch_bounds__(256) void dscale_kernel(
       const TP v = pp[(long)s * split_stride];
       sr += static_cast<double>(v.x);
       si += static_cast<double>(v.y);
+    }
+    if (gpsi) {
+      const double p0 = gpsi[(long)b * ldpsi].x;
+      const double b0 = static_cast<double>(gbeta[(long)j * ldb].x);
+      sr = 2.0 * sr - b0 * p0;
+      si = 0.0;
     }
     becp[t] = make_double2(sr, si);
   }
@@ -392,20 +402,23 @@ hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nspli
   return hipGetLastError();
 }
 
-hipError_t launch_dscale(const qeh_ctx *c, int nbk) {
+hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi) {
   if (c->nkb == 0) return hipSuccess;
   dim3 grid(c->nchunk, nbk);
   const long ss = (long)c->block * c->nkb;
+  const double2 *gpsi = c->gamma ? psi : nullptr;
   if (c->prec == QEH_FP64) {
     hipLaunchKernelGGL((dscale_kernel<double2, double2>), grid, dim3(256), 0, c->stream,
                        reinterpret_cast<const double2 *>(c->d.part), ss, c->nsplit, c->nkb,
                        reinterpret_cast<double2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
-                       c->d.pdoff, c->d.chunk);
+                       c->d.pdoff, c->d.chunk, gpsi, ldpsi,
+                       reinterpret_cast<const double2 *>(c->d.beta), (long)c->npw);
   } else {
     hipLaunchKernelGGL((dscale_kernel<float2, float2>), grid, dim3(256), 0, c->stream,
                        reinterpret_cast<const float2 *>(c->d.part), ss, c->nsplit, c->nkb,
                        reinterpret_cast<float2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
-                       c->d.pdoff, c->d.chunk);
+                       c->d.pdoff, c->d.chunk, gpsi, ldpsi,
+                       reinterpret_cast<const float2 *>(c->d.beta), (long)c->npw);
   }
   return hipGetLastError();
 }

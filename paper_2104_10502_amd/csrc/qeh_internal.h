@@ -91,6 +91,7 @@ struct DevMaps {
   void *ps;          // [block][nkb] D * becp (working complex type)
   float2 *psi32;     // mixed form: [block][npw] single-precision copy of psi (K1)
   void *big;         // split plane path: [block][N3][ext][N2] (or null)
+  double2 *gbuf;     // Gamma: [(block+1)/2][npw_fft] packed band pairs / their H (or null)
   int *colstart;     // [ext+1] first stick of each x-extent column
 };
 
@@ -98,6 +99,8 @@ struct DevMaps {
 
 struct qeh_ctx {
   int npw = 0, nst = 0, nkb = 0, nat = 0;
+  int npw_fft = 0;      // G-vectors of the FFT sphere (2 npw - 1 for Gamma cells, else npw)
+  int gamma = 0;        // 1: real wavefunctions at k = 0, half sphere stored
   int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
   int block = 0, prec = 0;
   int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel,
@@ -217,17 +220,35 @@ hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nspli
 
 // Sum split-K partials (double2 or float2 partials, double accumulation) and
 // apply the block-diagonal D: ps[b][i] = sum_j D_ij sum_s part[s][b][j].
-hipError_t launch_dscale(const qeh_ctx *c, int nbk);
+// Gamma contexts: psi (ldpsi) are the block's bands, whose G = 0 values enter
+// the real full-sphere projection (ignored otherwise).
+hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi);
 
 // ---- Davidson helpers (dav_kernels.hip) ----------------------------------
-// norms[b] = || Q_b - eps_b P_b ||^2 over npw (double), one launch.
+// norms[b] = || Q_b - eps_b P_b ||^2 over npw (double), one launch; gamma = 1:
+// half-sphere vectors, every G != 0 counted twice (G and -G).
 hipError_t launch_resid_norms(const double2 *P, const double2 *Q, long ld, int npw,
-                              int nb, const double *eps, double *norms, hipStream_t s);
+                              int nb, const double *eps, double *norms, int gamma,
+                              hipStream_t s);
 // V[dst_b] = t / ||t||, t = (Q_b - eps_b P_b) / sqrt(1 + (h - eps_b)^2) for the
-// listed bands b = idx[j], dst row j.
+// listed bands b = idx[j], dst row j (norm as above).
 hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw,
                           const int *idx, int nc, const double *eps, const double *hdiag,
-                          double2 *V, long ldv, hipStream_t s);
+                          double2 *V, long ldv, int gamma, hipStream_t s);
+// Gamma point (real wavefunctions, half sphere of nh coefficients, G = 0 first):
+// pack band pairs psi_2p + i psi_2p+1 over the full sphere (2 nh - 1 entries,
+// -G before G), and split the full-sphere result of the local operator back
+// into the two bands (+ kinetic term), writing hpsi.
+hipError_t launch_gamma_pack(const double2 *psi, long ldpsi, int nbk, int nh, double2 *out,
+                             long ldo, hipStream_t s);
+hipError_t launch_gamma_unpack(const double2 *hc, long ldc, int nbk, int nh, const double2 *psi,
+                               long ldpsi, const double *kin, double2 *hpsi, long ldh,
+                               hipStream_t s);
+// M(i, j) <- 2 Re M(i, j) - Re X_i[0] Re Y_j[0] (imaginary part zero): half-sphere
+// sums turned into full-sphere inner products of real functions.
+hipError_t launch_gamma_inner(double2 *M, long ld, int nrow, int ncol, const double2 *X,
+                              const double2 *Y, long npw, hipStream_t s);
+hipError_t launch_zero_g0_imag(double2 *psi, long ldpsi, int nb, hipStream_t s);
 // Copy rows; Hermitian fill; diag set etc.
 hipError_t launch_copy_rows(const double2 *src, long lds, double2 *dst, long ldd, int npw,
                             int nrows, hipStream_t s);

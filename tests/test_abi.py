@@ -208,3 +208,36 @@ def test_plan_rejects_no_beta_no_projgen(c1):
     n = ctypes.c_size_t()
     assert q._lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(n)) == -1
     assert "projgen" in q._lib.qeh_last_error().decode()
+
+
+def _plan_gamma(cell, miller=None, kpt=None, dmat=None, beta="keep"):
+    q = _q()
+    keep = []
+    c = q._cell_struct(cell.lattice, cell.fft, cell.kpt if kpt is None else kpt,
+                       cell.miller if miller is None else miller, cell.vloc, cell.nproj,
+                       cell.beta if isinstance(beta, str) else beta,
+                       cell.dmat if dmat is None else dmat, 0, 16, keep, gamma=True)
+    n = ctypes.c_size_t()
+    st = q._lib.qeh_ctx_plan(ctypes.byref(c), ctypes.byref(n))
+    return st, n.value, q._lib.qeh_last_error().decode()
+
+
+def test_plan_gamma(c1):
+    # the half-sphere cell plans; its arena holds the packed band pairs
+    h = cellgen.gamma_half(c1)
+    st, n, msg = _plan_gamma(h)
+    assert st == 0, msg
+    assert n > 16 * (16 // 2) * c1.npw
+    # k != 0, a list not starting at (0,0,0), a G before (0,0,0), complex D,
+    # complex beta(G = 0): rejected
+    assert _plan_gamma(h, kpt=np.array([0.0, 0.0, 0.01]))[0] == -1
+    assert _plan_gamma(h, miller=h.miller[1:])[0] == -1
+    bad = h.miller.copy()
+    bad[5] = -bad[5]
+    assert _plan_gamma(h, miller=bad)[0] == -1
+    d = h.dmat.copy()
+    d[0] += 0.1j
+    assert _plan_gamma(h, dmat=d)[0] == -1
+    b = h.beta.copy()
+    b[0, 0] += 1e-3j
+    assert _plan_gamma(h, beta=b)[0] == -1
