@@ -184,6 +184,27 @@ def time_apply(q, torch, cell, prec, nb, steps, warmup):
     return dt, stages, shape
 
 
+def time_gamma(q, torch, nb, steps, warmup):
+    """The benchmark's 64-atom cell moved to k = 0: H|psi> with complex
+    wavefunctions over the full sphere against the Gamma-point path (real
+    wavefunctions over half the sphere, two bands per complex FFT)."""
+    import cellgen
+    full = cellgen.make_cell("c2", kfrac=(0.0, 0.0, 0.0))
+    half = cellgen.gamma_half(full)
+    out = {}
+    for prec in (q.QEH_MIXED, q.QEH_FP64):
+        r = {}
+        for kind, cell in (("complex", full), ("gamma", half)):
+            dt, stages, _ = time_apply(q, torch, cell, prec, nb, steps, warmup)
+            r[kind] = dict(band_applies_per_s=nb * steps / dt, ms_per_step=dt / steps * 1e3,
+                           stage_us={k: v[0] / max(v[1], 1) * 1e3 for k, v in stages.items()
+                                     if v[1]})
+        r["speedup"] = r["gamma"]["band_applies_per_s"] / r["complex"]["band_applies_per_s"]
+        out["mixed" if prec else "fp64"] = r
+    out["npw_full"], out["npw_half"] = full.npw, half.npw
+    return out
+
+
 def time_density(q, torch, cell, prec, nb, steps, warmup):
     """Charge density of nb bands (occupation 2 each): seconds for `steps`
     calls, per-stage device times, context shape."""
@@ -397,6 +418,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the charge density leg (128 bands, both forms)")
+    ap.add_argument("--no-gamma", action="store_true",
+                    help="skip the Gamma-point leg (the 64-atom cell at k = 0)")
     ap.add_argument("--no-projectors", action="store_true",
                     help="skip the projector-generation leg")
     ap.add_argument("--serve", type=float, default=5.0,
@@ -498,6 +521,9 @@ def main():
                                                             v["bound"])
                           for k, v in per.items())), file=sys.stderr, flush=True)
         out["density"] = dens
+    if not a.no_gamma:
+        out["gamma_point"] = time_gamma(q, torch, nb, a.steps, a.warmup)
+        print("# gamma point: %s" % json.dumps(out["gamma_point"]), file=sys.stderr, flush=True)
     if not a.no_projectors:
         out["projectors"] = time_projectors(q, torch, cell)
         print("# projectors: %s" % json.dumps(out["projectors"]), file=sys.stderr, flush=True)

@@ -171,3 +171,19 @@ def test_gamma_served_request_and_density_rejected():
     ctx = q.Context.from_cell(h, precision=0, block=4)
     with pytest.raises(q.QehError):
         ctx.density(torch.from_numpy(_psi_half(h.npw, 2, 1)).cuda(), [1.0, 1.0])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gamma_c2_bench_launch(prec):
+    # the benchmark's Gamma leg: the 64-atom cell at k = 0, 128 bands in one
+    # block (64 packed pairs); sampled bands (both members of a pair, and a
+    # band from another pair) against the oracle on the full sphere
+    c = cellgen.make_cell("c2", kfrac=(0.0, 0.0, 0.0))
+    h = cellgen.gamma_half(c)
+    psi = _psi_half(h.npw, 128, 10502)
+    print("case gamma c2 bench launch prec", prec, flush=True)
+    got, _ = _apply(h, psi, prec, 128)
+    idx = [0, 1, 77]
+    ref = gamma.restrict(oracle.apply_h(c, gamma.expand(psi[idx])))
+    err = _rel_l2(got[idx], ref)
+    assert err.max() < (1e-12 if prec == 0 else 1e-5), err
