@@ -822,6 +822,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     g1.kchunk = c->kchunk;
     g1.split_stride = (long)c->block * c->nkb;
     g1.prec = f64 ? G_F64 : G_F32;
+    g1.rmode = c->gamma ? 1 : 0;   // Gamma: only the real part enters becp
     {
       StageGuard g(c, 3);
       e = launch_cgemm(g1, c->stream);
@@ -850,6 +851,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     g3.nsplit = 1;
     g3.kchunk = c->nkb;
     g3.prec = f64 ? G_F64 : G_F32;
+    g3.rmode = c->gamma ? 2 : 0;   // Gamma: ps is real
     {
       StageGuard g(c, 5);
       e = launch_cgemm(g3, c->stream);

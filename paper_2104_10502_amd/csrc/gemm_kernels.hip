@@ -16,6 +16,9 @@
 // the four-product form (Cr = Ar Br - Ai Bi, Ci = Ar Bi + Ai Br), and it issues
 // a quarter fewer MFMAs.  The FP64 instances are held to three waves per SIMD
 // (their third accumulator set would otherwise push them to two).
+// Two cheaper forms serve the Gamma-point projections (RM = 1: only the real
+// part of C is wanted, Cr = P1 - P2; RM = 2: A is real, Cr = sum Ar Br and
+// Ci = sum Ar Bi): two MFMA products per step instead of three.
 // 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
 // (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
 // split into fixed chunks whose partial results are summed in double by a
@@ -67,7 +70,8 @@ template <typename T> __device__ __forceinline__ T zero_of() {
 // One workgroup: a BM x BN tile of C over the K slice [kbeg, kend).  Global
 // tiles are prefetched into registers while the MFMAs consume the LDS copy of
 // the previous slice (two LDS buffers, one barrier per slice).
-template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
+template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
+          int RM>
 __global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
 void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
@@ -198,8 +202,12 @@ void cgemm_kernel(
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           mfma(ar[i], br[j], p1[i][j]);
-          mfma(ai[i], bi[j], p2[i][j]);
-          mfma(as[i], bs[j], p3[i][j]);
+          if (RM == 2) {
+            mfma(ar[i], bi[j], p2[i][j]);
+          } else {
+            mfma(ai[i], bi[j], p2[i][j]);
+            if (RM == 0) mfma(as[i], bs[j], p3[i][j]);
+          }
         }
     }
     if (more) sstore(buf ^ 1);
@@ -222,8 +230,10 @@ void cgemm_kernel(
         if (gm < M && gn < N) {
           TC *p = Cz + (long)gm * ldc + gn;
           using RC = typename real_of<TC>::type;
-          const R cr = p1[i][j][r] - p2[i][j][r];
-          const R ci = p3[i][j][r] - p1[i][j][r] - p2[i][j][r];
+          const R cr = RM == 2 ? p1[i][j][r] : p1[i][j][r] - p2[i][j][r];
+          const R ci = RM == 0   ? p3[i][j][r] - p1[i][j][r] - p2[i][j][r]
+                       : RM == 2 ? p2[i][j][r]
+                                 : R(0);
           if (accumulate) {
             TC v = *p;
             // the add happens in the result's precision
@@ -240,14 +250,15 @@ void cgemm_kernel(
       }
 }
 
-template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK>
+template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
+          int RM = 0>
 hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   const long total = (long)tm * tn * g.nsplit;
   if (total > (1L << 30)) return hipErrorInvalidValue;
   const int per_xcd = (int)((total + 7) / 8);
   const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
-  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK>), dim3(8 * per_xcd),
+  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK, RM>), dim3(8 * per_xcd),
                      dim3(kGT), 0, s, reinterpret_cast<const TA *>(g.A), g.lda,
                      reinterpret_cast<const TB *>(g.B), g.ldb, reinterpret_cast<TC *>(g.C), g.ldc,
                      g.M, g.N, g.K, g.conjA, g.conjB, g.accumulate, kchunk, g.split_stride, tm, tn,
@@ -375,8 +386,28 @@ __global__ __launch_bounds__(256) void dscale_kernel(
 
 }  // namespace
 
+// The Gamma-point forms, 64 x 64 tiles: RM = 1 for beta^H psi (bmode 0, psi
+// read in double), RM = 2 for beta ps (bmode 1, A = ps real, C = hpsi).
+hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
+  if (g.prec == G_F64) {
+    if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
+    if (g.rmode == 1 && g.bmode == 0)
+      return run_tile<double, double2, double2, double2, 0, 64, 64, 8, 1>(g, s);
+    if (g.rmode == 2 && g.bmode == 1)
+      return run_tile<double, double2, double2, double2, 1, 64, 64, 8, 2>(g, s);
+    return hipErrorInvalidValue;
+  }
+  if (g.tb != T_F2) return hipErrorInvalidValue;
+  if (g.rmode == 1 && g.bmode == 0 && g.ta == T_D2 && g.tc == T_F2)
+    return run_tile<float, double2, float2, float2, 0, 64, 64, 16, 1>(g, s);
+  if (g.rmode == 2 && g.bmode == 1 && g.ta == T_F2 && g.tc == T_D2)
+    return run_tile<float, float2, float2, double2, 1, 64, 64, 16, 2>(g, s);
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+  if (g.rmode != 0) return launch_cgemm_real(g, s);
   if (g.prec == G_F64) {
     if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
     return g.bmode == 0 ? run_tile<double, double2, double2, double2, 0, 64, 64, 8>(g, s)

@@ -212,6 +212,7 @@ struct GemmDesc {
   int nsplit, kchunk; long split_stride;
   int prec;
   int tile;   // FP32 tiles: 0 = 64 x 64, 1 = 128 x 64
+  int rmode;  // 0 complex; 1 only Re(C) wanted (Im written 0); 2 A real (Im A ignored)
 };
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
 // C[m][n] (+)= sum_s part[s*stride + m*ldp + n], summed in double in split order.
