@@ -255,6 +255,12 @@ def roofline_for(stages, shape, prec, nb):
         if name == "k2_plane":   # its HBM side, for the ridge between the two bounds
             gbs = plane_bytes(shape, prec, nb) / avg_s / 1e9
             per[name].update(hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
+            if prec != 0:
+                # the FP32 vector peak counts packed (two-wide) FP32 issue, which
+                # every HIP source here is compiled without; one-wide issue peaks
+                # at the FP64 figure
+                per[name].update(peak_one_wide_fp32=VALU_F64_TFLOPS,
+                                 frac_one_wide_fp32=achieved / VALU_F64_TFLOPS)
         if best is None or ms > stages[best][0]:
             best = name
     return best, per

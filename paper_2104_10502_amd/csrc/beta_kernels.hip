@@ -107,19 +107,36 @@ __global__ __launch_bounds__(kBT) void nl_diag_kernel(const T2 *__restrict__ bet
                                                       double *__restrict__ hdiag) {
   const int g = blockIdx.x * kBT + threadIdx.x;
   if (g >= npw) return;
+  constexpr int kReg = 16;   // atoms with up to this many projectors: values in registers
   double acc = 0.0;
   for (int a = 0; a < nat; ++a) {
     const int4 at = atoms[a];
     const int n = at.z;
     const T2 *b = beta + (long)at.y * ldb + g;
     const double2 *D = dmat + at.w;
-    for (int i = 0; i < n; ++i) {
-      const double2 bi = ld2<T2>(b + (long)i * ldb);
-      for (int k = 0; k < n; ++k) {
-        const double2 d = D[i * n + k];
-        const double2 bk = ld2<T2>(b + (long)k * ldb);
-        const double tr = bi.x * d.x - bi.y * d.y, ti = bi.x * d.y + bi.y * d.x;
-        acc += tr * bk.x + ti * bk.y;
+    if (n <= kReg) {
+      double2 v[kReg];
+#pragma unroll
+      for (int i = 0; i < kReg; ++i)
+        v[i] = i < n ? ld2<T2>(b + (long)i * ldb) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < kReg; ++i)
+#pragma unroll
+        for (int k = 0; k < kReg; ++k)
+          if (i < n && k < n) {
+            const double2 d = D[i * n + k];
+            const double tr = v[i].x * d.x - v[i].y * d.y, ti = v[i].x * d.y + v[i].y * d.x;
+            acc += tr * v[k].x + ti * v[k].y;
+          }
+    } else {
+      for (int i = 0; i < n; ++i) {
+        const double2 bi = ld2<T2>(b + (long)i * ldb);
+        for (int k = 0; k < n; ++k) {
+          const double2 d = D[i * n + k];
+          const double2 bk = ld2<T2>(b + (long)k * ldb);
+          const double tr = bi.x * d.x - bi.y * d.y, ti = bi.x * d.y + bi.y * d.x;
+          acc += tr * bk.x + ti * bk.y;
+        }
       }
     }
   }

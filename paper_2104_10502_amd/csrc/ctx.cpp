@@ -760,13 +760,13 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
   const bool f64 = c->prec == QEH_FP64;
   if ((part == 0 || part == 2) && c->gamma) {
     // Gamma: bands 2p, 2p+1 go through one complex FFT as psi_2p + i psi_2p+1
-    // over the full sphere (packed into gbuf, whose space then takes the
-    // result), and are separated again with the kinetic term added
+    // over the full sphere (K1 reads the pairs from the stored halves; K3
+    // writes the full-sphere result to gbuf), and are separated again with the
+    // kinetic term added
     const int np = (nbk + 1) / 2;
     {
       StageGuard g(c, 0);
-      e = launch_gamma_pack(psi, ldpsi, nbk, c->npw, c->d.gbuf, c->npw_fft, c->stream);
-      if (e == hipSuccess) e = launch_k1(c, np, c->d.gbuf, c->npw_fft);
+      e = launch_k1_gamma(c, nbk, psi, ldpsi);
     }
     if (e != hipSuccess) return hip_fail(e, "K1 launch");
     {

@@ -135,32 +135,10 @@ __global__ void fill_int_kernel(int *p, int n, int v) {
 }
 
 // ---- Gamma point: two real bands per complex FFT ---------------------------
-// The full sphere of nh stored coefficients has 2 nh - 1 entries: index
-// f < nh - 1 is -G of stored h = nh - 1 - f, index f >= nh - 1 is stored
-// h = f - (nh - 1).  Band pair p holds c = psi_2p + i psi_2p+1 (a missing
-// partner is zero) with psi(-G) = conj(psi(G)); the imaginary part of psi at
-// G = 0 is not referenced.
-__global__ void gamma_pack_kernel(const double2 *__restrict__ psi, long ldpsi, int nbk, int nh,
-                                  double2 *__restrict__ out, long ldo) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (f >= 2 * nh - 1) return;
-  const int a = 2 * p, b = 2 * p + 1;
-  const bool neg = f < nh - 1;
-  const int h = neg ? nh - 1 - f : f - (nh - 1);
-  double2 va = psi[(long)a * ldpsi + h];
-  double2 vb = b < nbk ? psi[(long)b * ldpsi + h] : make_double2(0.0, 0.0);
-  if (h == 0) {
-    va.y = 0.0;
-    vb.y = 0.0;
-  }
-  if (neg) {
-    va.y = -va.y;
-    vb.y = -vb.y;
-  }
-  out[(long)p * ldo + f] = make_double2(va.x - vb.y, va.y + vb.x);
-}
-
+// K1 reads band pairs psi_2p + i psi_2p+1 straight from the half-sphere bands;
+// the full-sphere result of K3 (2 nh - 1 entries: index f < nh - 1 is -G of
+// stored h = nh - 1 - f, index f >= nh - 1 is stored h = f - (nh - 1)) is
+// separated here.
 // From C = F(V psi_a) + i F(V psi_b) on the full sphere: F(V psi_a)(G) =
 // (C(G) + conj C(-G)) / 2, F(V psi_b)(G) = (C(G) - conj C(-G)) / (2i); plus
 // the kinetic term.  Writes hpsi (overwrites).
@@ -238,15 +216,6 @@ hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw, 
   if (nc <= 0) return hipSuccess;
   hipLaunchKernelGGL(precond_kernel, dim3(nc), dim3(kDT), 0, s, P, Q, ld, npw, idx, eps, hdiag,
                      V, ldv, gamma);
-  return hipGetLastError();
-}
-
-hipError_t launch_gamma_pack(const double2 *psi, long ldpsi, int nbk, int nh, double2 *out,
-                             long ldo, hipStream_t s) {
-  if (nbk <= 0) return hipSuccess;
-  const int nf = 2 * nh - 1;
-  hipLaunchKernelGGL(gamma_pack_kernel, dim3((nf + 255) / 256, (nbk + 1) / 2), dim3(256), 0, s,
-                     psi, ldpsi, nbk, nh, out, ldo);
   return hipGetLastError();
 }
 

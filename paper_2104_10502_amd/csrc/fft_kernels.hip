@@ -122,15 +122,38 @@ __device__ void fft_fwd_dif(C *buf, const FastDiv &lines, int ld, const FftDim &
 constexpr int kNT = 256;
 
 // ---------------------------------------------------------------- K1
+// Gamma contexts (real wavefunctions, half sphere of nh stored coefficients):
+// "band" p of a launch is the pair c = psi_2p + i psi_2p+1 at full-sphere
+// index f, where f < nh - 1 is -G of stored h = nh - 1 - f (read conjugated)
+// and f >= nh - 1 is stored h = f - (nh - 1); the imaginary part at G = 0 is
+// not referenced, and a missing partner (2p + 1 = nbk) is zero.
+__device__ __forceinline__ double2 gamma_pair(const double2 *__restrict__ psi, int ldpsi, int p,
+                                              int f, int nh, int nbk) {
+  const bool neg = f < nh - 1;
+  const int h = neg ? nh - 1 - f : f - (nh - 1);
+  double2 va = psi[(size_t)(2 * p) * ldpsi + h];
+  double2 vb = 2 * p + 1 < nbk ? psi[(size_t)(2 * p + 1) * ldpsi + h] : make_double2(0.0, 0.0);
+  if (h == 0) {
+    va.y = 0.0;
+    vb.y = 0.0;
+  }
+  if (neg) {
+    va.y = -va.y;
+    vb.y = -vb.y;
+  }
+  return make_double2(va.x - vb.y, va.y + vb.x);
+}
+
 // One workgroup: S consecutive sticks of one band.  Their sphere runs are one
 // contiguous range of psi (lexicographic Miller order), so the read is
-// coalesced; the output rows [z][s0 .. s0+S) are contiguous too.
-template <typename C>
+// coalesced; the output rows [z][s0 .. s0+S) are contiguous too.  GAM: the
+// Gamma band-pair reading above (nbk bands, nh stored coefficients).
+template <typename C, bool GAM = false>
 __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
     const double2 *__restrict__ psi, int ldpsi, C *__restrict__ sbuf,
     const int *__restrict__ stick_off, const int *__restrict__ gmap,
     const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, FastDiv sdiv,
-    FastDiv slast, float2 *__restrict__ psi32, int npw) {
+    FastDiv slast, float2 *__restrict__ psi32, int npw, int nbk, int nh) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tile = reinterpret_cast<C *>(smem_raw);
   C *tw = tile + S * ldz;
@@ -147,7 +170,10 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
   const double2 *pb = psi + (size_t)b * ldpsi;
   const int base = s0 * ldz;
   // mixed form: also leave a single-precision copy of psi for the projector GEMM
-  if (psi32) {
+  if (GAM) {
+    for (int g = g0 + tid; g < g1; g += kNT)
+      tile[gmap[g] - base] = ccast<C>(gamma_pair(psi, ldpsi, b, g, nh, nbk));
+  } else if (psi32) {
     float2 *p32 = psi32 + (size_t)b * npw;
     for (int g = g0 + tid; g < g1; g += kNT) {
       const double2 v = pb[g];
@@ -837,11 +863,11 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 48 ? 3 
 // for the sphere gather.
 constexpr int kPairSticks = 64;   // 37 KB of LDS at N = 72: four workgroups per CU
 
-template <int N>
+template <int N, bool GAM = false>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 : 2))) void
 k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
         const int *__restrict__ stick_off, const int *__restrict__ gmap, int nst,
-        float2 *__restrict__ psi32, int npw) {
+        float2 *__restrict__ psi32, int npw, int nbk, int nh) {
   constexpr int LD = N | 1, M = N / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2 *tile = reinterpret_cast<float2 *>(smem_raw);
@@ -853,14 +879,12 @@ k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
   for (int i = tid; i < ns * LD; i += kNT) tile[i] = zero;
   __syncthreads();
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
-  const double2 *pb = psi + (size_t)b * ldpsi;
   const int base = s0 * LD;
-  float2 *p32 = psi32 + (size_t)b * npw;
   for (int g = g0 + tid; g < g1; g += kNT) {
-    const double2 v = pb[g];
+    const double2 v = GAM ? gamma_pair(psi, ldpsi, b, g, nh, nbk) : psi[(size_t)b * ldpsi + g];
     const float2 f = make_float2((float)v.x, (float)v.y);
     tile[gmap[g] - base] = f;
-    p32[g] = f;
+    if (!GAM) psi32[(size_t)b * npw + g] = f;
   }
   __syncthreads();
   float2 *out = sbuf + (size_t)b * N * nst + s0;
@@ -1025,15 +1049,17 @@ template <typename K> void allow_lds(K kern, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename C>
-hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+// GAM: nbk launch "bands" are Gamma band pairs of nb_gam bands (nh = npw).
+template <typename C, bool GAM>
+hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
   const C *tw = reinterpret_cast<const C *>(c->d.tw) + c->tw_off[2];
   dim3 grid((c->nst + c->sg.S - 1) / c->sg.S, nbk);
-  allow_lds(k1_scatter_zinv<C>, c->sg.lds_bytes);
-  hipLaunchKernelGGL(k1_scatter_zinv<C>, grid, dim3(kNT), c->sg.lds_bytes, c->stream, psi,
-                     ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
+  allow_lds(k1_scatter_zinv<C, GAM>, c->sg.lds_bytes);
+  hipLaunchKernelGGL((k1_scatter_zinv<C, GAM>), grid, dim3(kNT), c->sg.lds_bytes, c->stream,
+                     psi, ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
                      c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div,
-                     c->prec == QEH_MIXED ? c->d.psi32 : nullptr, c->npw_fft);
+                     (c->prec == QEH_MIXED && !GAM) ? c->d.psi32 : nullptr, c->npw_fft, nb_gam,
+                     c->npw);
   return hipGetLastError();
 }
 
@@ -1173,12 +1199,14 @@ hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, c
   return hipGetLastError();
 }
 
-template <int N> hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+template <int N, bool GAM>
+hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
   const size_t lds = 8 * (size_t)kPairSticks * (N | 1);
-  allow_lds(k1_pair<N>, lds);
-  hipLaunchKernelGGL(k1_pair<N>, dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk), dim3(kNT),
-                     lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
-                     c->d.stick_off, c->d.gmap, c->nst, c->d.psi32, c->npw_fft);
+  allow_lds(k1_pair<N, GAM>, lds);
+  hipLaunchKernelGGL((k1_pair<N, GAM>), dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk),
+                     dim3(kNT), lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
+                     c->d.stick_off, c->d.gmap, c->nst, GAM ? nullptr : c->d.psi32, c->npw_fft,
+                     nb_gam, c->npw);
   return hipGetLastError();
 }
 
@@ -1193,10 +1221,11 @@ hipError_t k3_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldp
   return hipGetLastError();
 }
 
-hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+template <bool GAM>
+hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
   switch (c->n3) {
 #define QEH_PAIR_CASE(NN) \
-  case NN: return k1_pair_launch<NN>(c, nbk, psi, ldpsi);
+  case NN: return k1_pair_launch<NN, GAM>(c, nbk, psi, ldpsi, nb_gam);
     QEH_PAIR_SIZES(QEH_PAIR_CASE)
 #undef QEH_PAIR_CASE
     default: return hipErrorInvalidValue;
@@ -1339,9 +1368,16 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
 }
 
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
-  if (c->zpair) return k1_pair_impl(c, nbk, psi, ldpsi);
-  return c->prec == QEH_FP64 ? k1_impl<double2>(c, nbk, psi, ldpsi)
-                             : k1_impl<float2>(c, nbk, psi, ldpsi);
+  if (c->zpair) return k1_pair_impl<false>(c, nbk, psi, ldpsi, 0);
+  return c->prec == QEH_FP64 ? k1_impl<double2, false>(c, nbk, psi, ldpsi, 0)
+                             : k1_impl<float2, false>(c, nbk, psi, ldpsi, 0);
+}
+
+hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
+  const int np = (nbk + 1) / 2;
+  if (c->zpair) return k1_pair_impl<true>(c, np, psi, ldpsi, nbk);
+  return c->prec == QEH_FP64 ? k1_impl<double2, true>(c, np, psi, ldpsi, nbk)
+                             : k1_impl<float2, true>(c, np, psi, ldpsi, nbk);
 }
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {

@@ -135,6 +135,9 @@ qeh_status hip_fail(hipError_t e, const char *what);
 // ---- FFT path launchers (fft_kernels.hip) --------------------------------
 // All take band count nbk (<= ctx block) and operate on the ctx stick buffer.
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
+// Gamma contexts: K1 of ceil(nbk/2) band pairs psi_2p + i psi_2p+1, read from
+// the half-sphere bands (nbk rows, ldpsi) and expanded to the full sphere.
+hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
 hipError_t launch_k2(const qeh_ctx *c, int nbk);
 hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
                      double2 *hpsi, int ldh, int add_kinetic);
@@ -237,11 +240,9 @@ hipError_t launch_precond(const double2 *P, const double2 *Q, long ld, int npw,
                           const int *idx, int nc, const double *eps, const double *hdiag,
                           double2 *V, long ldv, int gamma, hipStream_t s);
 // Gamma point (real wavefunctions, half sphere of nh coefficients, G = 0 first):
-// pack band pairs psi_2p + i psi_2p+1 over the full sphere (2 nh - 1 entries,
-// -G before G), and split the full-sphere result of the local operator back
-// into the two bands (+ kinetic term), writing hpsi.
-hipError_t launch_gamma_pack(const double2 *psi, long ldpsi, int nbk, int nh, double2 *out,
-                             long ldo, hipStream_t s);
+// split the full-sphere result (2 nh - 1 entries, -G before G) of the local
+// operator on band pairs psi_2p + i psi_2p+1 back into the two bands (+ kinetic
+// term), writing hpsi.
 hipError_t launch_gamma_unpack(const double2 *hc, long ldc, int nbk, int nh, const double2 *psi,
                                long ldpsi, const double *kin, double2 *hpsi, long ldh,
                                hipStream_t s);
