@@ -127,8 +127,10 @@ typedef struct {
  *   two bands share one complex 3D FFT (psi_a + i psi_b is transformed and
  *     the two results separated from the values at G and -G);
  *   inner products are 2 Re sum_G conj(a_G) b_G - a_0 b_0 over the stored
- *     half, so the subspace problem is real symmetric.
- * qeh_density does not take Gamma contexts (QEH_ERR_INVALID). */
+ *     half, so the subspace problem is real symmetric;
+ *   qeh_density pairs consecutive bands of equal occupation into one complex
+ *     transform (|psi_a + i psi_b|^2 = psi_a^2 + psi_b^2 for real functions);
+ *     other bands go alone. */
 
 typedef struct qeh_ctx qeh_ctx;
 

@@ -889,7 +889,7 @@ qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldp
 // ---- charge density (charge density generation among the ported kernels,
 // section "Evolution of the GPU-enabled version")
 struct DensityWork {
-  size_t big, partial, occ, zcol, total;
+  size_t big, partial, occ, zcol, pairs, total;
 };
 
 DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
@@ -902,6 +902,7 @@ DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
   w.partial = bump(&cur, 8 * (size_t)nsub * nfft);
   w.occ = bump(&cur, 8 * (size_t)c->block);
   w.zcol = bump(&cur, 8 * (size_t)c->n2);
+  w.pairs = bump(&cur, c->gamma ? 8 * (size_t)c->block : 0);
   w.total = cur;
   return w;
 }
@@ -909,7 +910,6 @@ DensityWork density_work(const qeh_ctx *c, const DensityGeom &dg) {
 qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const double *occ,
                         double *rho, void *work, size_t work_bytes) {
   if (!c) return invalid("ctx is null");
-  if (c->gamma) return invalid("qeh_density does not take Gamma contexts");
   if (nb < 0) return invalid("nb < 0");
   if (!rho) return invalid("rho is null");
   if (nb > 0 && (!psi || !occ)) return invalid("psi / occ null");
@@ -937,15 +937,40 @@ qeh_status density_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, const 
   // the zero column of the lane-pair rows (a kernel, not a memset)
   e = launch_fill_int(reinterpret_cast<int *>(W + w.zcol), 2 * c->n2, 0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "density zero column");
-  for (int b0 = 0; b0 < nb; b0 += c->block) {
-    const int nbk = std::min(c->block, nb - b0);
-    // the previous block's kernels read occ_d; the copy below is ordered after
-    // them on the same stream
-    e = hipMemcpyAsync(occ_d, occ + b0, 8 * (size_t)nbk, hipMemcpyHostToDevice, c->stream);
+  // Gamma: consecutive bands of equal occupation share one complex transform,
+  // psi_a + i psi_b, whose |.|^2 is psi_a^2 + psi_b^2 (both real in real
+  // space); a band without such a partner goes alone.  Each transform is one
+  // "slot" with its occupation; without Gamma a slot is a band.
+  std::vector<int2> slot_pair;
+  std::vector<double> slot_occ;
+  if (c->gamma) {
+    for (int b = 0; b < nb;) {
+      if (b + 1 < nb && occ[b] == occ[b + 1]) {
+        slot_pair.push_back(make_int2(b, b + 1));
+        b += 2;
+      } else {
+        slot_pair.push_back(make_int2(b, -1));
+        b += 1;
+      }
+      slot_occ.push_back(occ[slot_pair.back().x]);
+    }
+  }
+  const int nslots = c->gamma ? (int)slot_pair.size() : nb;
+  const double *socc = c->gamma ? slot_occ.data() : occ;
+  int2 *pairs_d = reinterpret_cast<int2 *>(W + w.pairs);
+  for (int b0 = 0; b0 < nslots; b0 += c->block) {
+    const int nbk = std::min(c->block, nslots - b0);
+    // the previous block's kernels read occ_d (and the pair table); the copies
+    // below are ordered after them on the same stream
+    e = hipMemcpyAsync(occ_d, socc + b0, 8 * (size_t)nbk, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && c->gamma)
+      e = hipMemcpyAsync(pairs_d, slot_pair.data() + b0, 8 * (size_t)nbk, hipMemcpyHostToDevice,
+                         c->stream);
     if (e != hipSuccess) return hip_fail(e, "occupation upload");
     {
       StageGuard g(c, 0);
-      e = launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
+      e = c->gamma ? launch_k1_gamma(c, nb, p, ldpsi, pairs_d, nbk)
+                   : launch_k1(c, nbk, p + (size_t)b0 * ldpsi, ldpsi);
     }
     if (e != hipSuccess) return hip_fail(e, "K1 launch");
     if (dg.fused) {
@@ -990,7 +1015,6 @@ qeh_status qeh_apply_h_part(qeh_ctx *c, int part, int nb, const double *psi, int
 
 qeh_status qeh_density_plan(const qeh_ctx *c, size_t *work_bytes) {
   if (!c || !work_bytes) return invalid("null argument");
-  if (c->gamma) return invalid("qeh_density does not take Gamma contexts");
   DensityGeom dg{};
   if (!density_geometry(c, &dg)) return invalid("box too large for the density row kernel");
   *work_bytes = density_work(c, dg).total;

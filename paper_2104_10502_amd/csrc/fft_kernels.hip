@@ -123,16 +123,24 @@ constexpr int kNT = 256;
 
 // ---------------------------------------------------------------- K1
 // Gamma contexts (real wavefunctions, half sphere of nh stored coefficients):
-// "band" p of a launch is the pair c = psi_2p + i psi_2p+1 at full-sphere
-// index f, where f < nh - 1 is -G of stored h = nh - 1 - f (read conjugated)
-// and f >= nh - 1 is stored h = f - (nh - 1); the imaginary part at G = 0 is
-// not referenced, and a missing partner (2p + 1 = nbk) is zero.
+// "band" p of a launch is the pair c = psi_a + i psi_b at full-sphere index f,
+// where f < nh - 1 is -G of stored h = nh - 1 - f (read conjugated) and
+// f >= nh - 1 is stored h = f - (nh - 1); the imaginary part at G = 0 is not
+// referenced.  The rows (a, b) are (2p, 2p + 1), or pairs[p] when a pair table
+// is given; a missing partner (b = nbk, or b < 0 in a table) is zero.
 __device__ __forceinline__ double2 gamma_pair(const double2 *__restrict__ psi, int ldpsi, int p,
-                                              int f, int nh, int nbk) {
+                                              int f, int nh, int nbk,
+                                              const int2 *__restrict__ pairs) {
+  int ia = 2 * p, ib = 2 * p + 1 < nbk ? 2 * p + 1 : -1;
+  if (pairs) {
+    const int2 t = pairs[p];
+    ia = t.x;
+    ib = t.y;
+  }
   const bool neg = f < nh - 1;
   const int h = neg ? nh - 1 - f : f - (nh - 1);
-  double2 va = psi[(size_t)(2 * p) * ldpsi + h];
-  double2 vb = 2 * p + 1 < nbk ? psi[(size_t)(2 * p + 1) * ldpsi + h] : make_double2(0.0, 0.0);
+  double2 va = psi[(size_t)ia * ldpsi + h];
+  double2 vb = ib >= 0 ? psi[(size_t)ib * ldpsi + h] : make_double2(0.0, 0.0);
   if (h == 0) {
     va.y = 0.0;
     vb.y = 0.0;
@@ -153,7 +161,8 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
     const double2 *__restrict__ psi, int ldpsi, C *__restrict__ sbuf,
     const int *__restrict__ stick_off, const int *__restrict__ gmap,
     const C *__restrict__ twz, FftDim dz, int nst, int S, int ldz, FastDiv sdiv,
-    FastDiv slast, float2 *__restrict__ psi32, int npw, int nbk, int nh) {
+    FastDiv slast, float2 *__restrict__ psi32, int npw, int nbk, int nh,
+    const int2 *__restrict__ pairs) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tile = reinterpret_cast<C *>(smem_raw);
   C *tw = tile + S * ldz;
@@ -172,7 +181,7 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
   // mixed form: also leave a single-precision copy of psi for the projector GEMM
   if (GAM) {
     for (int g = g0 + tid; g < g1; g += kNT)
-      tile[gmap[g] - base] = ccast<C>(gamma_pair(psi, ldpsi, b, g, nh, nbk));
+      tile[gmap[g] - base] = ccast<C>(gamma_pair(psi, ldpsi, b, g, nh, nbk, pairs));
   } else if (psi32) {
     float2 *p32 = psi32 + (size_t)b * npw;
     for (int g = g0 + tid; g < g1; g += kNT) {
@@ -867,7 +876,7 @@ template <int N, bool GAM = false>
 __global__ __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(N < 90 ? 3 : 2))) void
 k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
         const int *__restrict__ stick_off, const int *__restrict__ gmap, int nst,
-        float2 *__restrict__ psi32, int npw, int nbk, int nh) {
+        float2 *__restrict__ psi32, int npw, int nbk, int nh, const int2 *__restrict__ pairs) {
   constexpr int LD = N | 1, M = N / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float2 *tile = reinterpret_cast<float2 *>(smem_raw);
@@ -881,7 +890,8 @@ k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
   const int base = s0 * LD;
   for (int g = g0 + tid; g < g1; g += kNT) {
-    const double2 v = GAM ? gamma_pair(psi, ldpsi, b, g, nh, nbk) : psi[(size_t)b * ldpsi + g];
+    const double2 v =
+        GAM ? gamma_pair(psi, ldpsi, b, g, nh, nbk, pairs) : psi[(size_t)b * ldpsi + g];
     const float2 f = make_float2((float)v.x, (float)v.y);
     tile[gmap[g] - base] = f;
     if (!GAM) psi32[(size_t)b * npw + g] = f;
@@ -1049,9 +1059,11 @@ template <typename K> void allow_lds(K kern, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// GAM: nbk launch "bands" are Gamma band pairs of nb_gam bands (nh = npw).
+// GAM: nbk launch "bands" are Gamma band pairs of nb_gam bands (nh = npw), or
+// the pairs of a table.
 template <typename C, bool GAM>
-hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
+hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
+                   const int2 *pairs) {
   const C *tw = reinterpret_cast<const C *>(c->d.tw) + c->tw_off[2];
   dim3 grid((c->nst + c->sg.S - 1) / c->sg.S, nbk);
   allow_lds(k1_scatter_zinv<C, GAM>, c->sg.lds_bytes);
@@ -1059,7 +1071,7 @@ hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int
                      psi, ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
                      c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div,
                      (c->prec == QEH_MIXED && !GAM) ? c->d.psi32 : nullptr, c->npw_fft, nb_gam,
-                     c->npw);
+                     c->npw, pairs);
   return hipGetLastError();
 }
 
@@ -1200,13 +1212,14 @@ hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, c
 }
 
 template <int N, bool GAM>
-hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
+hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
+                          const int2 *pairs) {
   const size_t lds = 8 * (size_t)kPairSticks * (N | 1);
   allow_lds(k1_pair<N, GAM>, lds);
   hipLaunchKernelGGL((k1_pair<N, GAM>), dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk),
                      dim3(kNT), lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
                      c->d.stick_off, c->d.gmap, c->nst, GAM ? nullptr : c->d.psi32, c->npw_fft,
-                     nb_gam, c->npw);
+                     nb_gam, c->npw, pairs);
   return hipGetLastError();
 }
 
@@ -1222,10 +1235,11 @@ hipError_t k3_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldp
 }
 
 template <bool GAM>
-hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam) {
+hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
+                        const int2 *pairs) {
   switch (c->n3) {
 #define QEH_PAIR_CASE(NN) \
-  case NN: return k1_pair_launch<NN, GAM>(c, nbk, psi, ldpsi, nb_gam);
+  case NN: return k1_pair_launch<NN, GAM>(c, nbk, psi, ldpsi, nb_gam, pairs);
     QEH_PAIR_SIZES(QEH_PAIR_CASE)
 #undef QEH_PAIR_CASE
     default: return hipErrorInvalidValue;
@@ -1368,16 +1382,17 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
 }
 
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
-  if (c->zpair) return k1_pair_impl<false>(c, nbk, psi, ldpsi, 0);
-  return c->prec == QEH_FP64 ? k1_impl<double2, false>(c, nbk, psi, ldpsi, 0)
-                             : k1_impl<float2, false>(c, nbk, psi, ldpsi, 0);
+  if (c->zpair) return k1_pair_impl<false>(c, nbk, psi, ldpsi, 0, nullptr);
+  return c->prec == QEH_FP64 ? k1_impl<double2, false>(c, nbk, psi, ldpsi, 0, nullptr)
+                             : k1_impl<float2, false>(c, nbk, psi, ldpsi, 0, nullptr);
 }
 
-hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
-  const int np = (nbk + 1) / 2;
-  if (c->zpair) return k1_pair_impl<true>(c, np, psi, ldpsi, nbk);
-  return c->prec == QEH_FP64 ? k1_impl<double2, true>(c, np, psi, ldpsi, nbk)
-                             : k1_impl<float2, true>(c, np, psi, ldpsi, nbk);
+hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
+                           const int2 *pairs, int npairs) {
+  const int np = pairs ? npairs : (nbk + 1) / 2;
+  if (c->zpair) return k1_pair_impl<true>(c, np, psi, ldpsi, nbk, pairs);
+  return c->prec == QEH_FP64 ? k1_impl<double2, true>(c, np, psi, ldpsi, nbk, pairs)
+                             : k1_impl<float2, true>(c, np, psi, ldpsi, nbk, pairs);
 }
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {

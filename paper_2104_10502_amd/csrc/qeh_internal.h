@@ -136,8 +136,11 @@ qeh_status hip_fail(hipError_t e, const char *what);
 // All take band count nbk (<= ctx block) and operate on the ctx stick buffer.
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
 // Gamma contexts: K1 of ceil(nbk/2) band pairs psi_2p + i psi_2p+1, read from
-// the half-sphere bands (nbk rows, ldpsi) and expanded to the full sphere.
-hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
+// the half-sphere bands (nbk rows, ldpsi) and expanded to the full sphere; with
+// a device pair table, K1 of npairs pairs (rows pairs[p].x, pairs[p].y, the
+// second < 0 for none).
+hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
+                           const int2 *pairs = nullptr, int npairs = 0);
 hipError_t launch_k2(const qeh_ctx *c, int nbk);
 hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
                      double2 *hpsi, int ldh, int add_kinetic);

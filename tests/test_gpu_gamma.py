@@ -153,7 +153,7 @@ def test_gamma_davidson_restarts_odd_blocks():
     assert np.abs(np.sort(eig) - ref).max() < 1e-9
 
 
-def test_gamma_served_request_and_density_rejected():
+def test_gamma_served_request():
     q = _q()
     c = cellgen.make_cell("c1")
     h = cellgen.gamma_half(c)
@@ -168,9 +168,23 @@ def test_gamma_served_request_and_density_rejected():
     srv.close()
     assert r is not None and r["status"] == 0, r
     assert np.abs(r["eig"][0] - ref).max() < 1e-9
-    ctx = q.Context.from_cell(h, precision=0, block=4)
-    with pytest.raises(q.QehError):
-        ctx.density(torch.from_numpy(_psi_half(h.npw, 2, 1)).cuda(), [1.0, 1.0])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("block", [16, 3])
+def test_gamma_density(prec, block):
+    # occupations with runs of equal values (bands paired in one transform)
+    # and isolated values (bands alone), in blocks of 16 and of 3 transforms
+    q = _q()
+    c = cellgen.make_cell("c1")
+    h = cellgen.gamma_half(c)
+    occ = np.array([2.0, 2.0, 2.0, 1.5, 1.5, 0.3, 2.0, 2.0, 1.0, 0.0, 0.0])
+    psi = _psi_half(h.npw, occ.size, 25)
+    ctx = q.Context.from_cell(h, precision=prec, block=block)
+    got = ctx.density(torch.from_numpy(psi).cuda(), occ).cpu().numpy()
+    ref = oracle.density(c, gamma.expand(psi), occ)
+    tol = 1e-12 if prec == 0 else 1e-5
+    assert np.abs(got - ref).max() < tol * np.abs(ref).max()
 
 
 @pytest.mark.parametrize("prec", [0, 1])
