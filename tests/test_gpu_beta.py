@@ -201,3 +201,24 @@ def test_generate_errors():
     p = pad.cpu().numpy()
     assert (p[:, c.npw:] == 3.0).all()
     assert np.abs(p[:, :c.npw] - _oracle_beta(c)).max() < 1e-8 * np.abs(p[:, :c.npw]).max()
+
+
+def test_generate_species_without_projectors():
+    # a species with no radial channels: its atoms own no rows, the others'
+    # rows follow in atom order
+    c = _aniso_cell()
+    pos = np.array([[0.5, 0.7, 1.1], [4.1, 3.9, 6.6], [2.2, 6.1, 0.4]])
+    ityp = np.array([0, 1, 0])
+    species = [cellgen.PROJ_SETS["sp"], []]
+    dq = 0.01
+    nq = int(np.ceil(np.sqrt(c.ecutwfc) / dq)) + 4
+    qg = np.arange(nq) * dq
+    tab = np.stack([cellgen.radial_ft_closed(l, s, qg) for sp in species for (l, s) in sp])
+    pg = dict(tau=pos, ityp=ityp, nchan=np.array([2, 0]), lchan=np.array([0, 1]), dq=dq,
+              tab=tab)
+    nproj = np.array([4, 0, 4])
+    q = _q()
+    got = q.generate_beta(c.lattice, c.kpt, c.miller, nproj, pg).cpu().numpy()
+    ref = oracle.beta_projectors(c.lattice, c.kpt, c.miller, pos, ityp, species)
+    assert got.shape == ref.shape == (8, c.npw)
+    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()

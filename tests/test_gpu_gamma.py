@@ -201,3 +201,17 @@ def test_gamma_c2_bench_launch(prec):
     ref = gamma.restrict(oracle.apply_h(c, gamma.expand(psi[idx])))
     err = _rel_l2(got[idx], ref)
     assert err.max() < (1e-12 if prec == 0 else 1e-5), err
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gamma_single_band_and_empty(prec):
+    # one band (a pair with no partner), and zero bands (nothing launched)
+    q = _q()
+    c = cellgen.make_cell("c1")
+    h = cellgen.gamma_half(c)
+    psi = _psi_half(h.npw, 1, 26)
+    got, ctx = _apply(h, psi, prec, 8)
+    ref = gamma.restrict(oracle.apply_h(c, gamma.expand(psi)))
+    _check(got, ref, prec)
+    empty = torch.zeros((0, h.npw), dtype=torch.complex128, device="cuda")
+    assert ctx.apply_h(empty).shape == (0, h.npw)
