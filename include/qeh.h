@@ -180,11 +180,12 @@ qeh_status qeh_apply_h_part(qeh_ctx *ctx, int part, int nb, const double *psi,
  * Bands go through in blocks of the context's block size: K1 (sticks and
  * inverse z), inverse y columns into the workspace, then inverse x rows with
  * the occupation-weighted |psi|^2 summed in double in a fixed order (the
- * result does not depend on timing).  Mixed-form contexts on the lane-pair
- * plane kernel run the y and x transforms as one fused pass per z plane
- * instead (no column workspace); QEH_DENSITY_KERNEL=rows or =generic, read per
- * call, selects the unfused lane-pair rows or the LDS-pass rows (test hooks).  Precision: the context's (the mixed
- * form transforms in FP32 and sums in FP64).  Blocking: returns after the
+ * result does not depend on timing).  Contexts on the register plane
+ * kernels (lane pairs in the mixed form, lane quads in FP64) run the y and x
+ * transforms as one fused pass per z plane instead (no column workspace);
+ * QEH_DENSITY_KERNEL=rows or =generic, read per call, selects the unfused
+ * lane-pair rows or the LDS-pass rows (test hooks).  Precision: the
+ * context's (the mixed form transforms in FP32 and sums in FP64).  Blocking: returns after the
  * device work of the call has finished.  Errors: QEH_ERR_INVALID for null
  * pointers, ldpsi < npw, a short or misaligned workspace, a non-finite
  * occupation, or a box whose rows exceed the row kernel (N1 > 2048). */

@@ -740,6 +740,81 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(2))) void k
   }
 }
 
+// Fused density plane pass on lane quads (FP64 form, N1 = N2 = N a compiled
+// lane-quad size, natural-y plane tables): as the lane-pair form above, with
+// each column and row held by four lanes (quad_inv); 512 threads so that every
+// row has its own quad ((y, q) = (tid / 4, tid % 4), 4 N <= 512).  The inverse
+// leaves lane q with x positions k + (N/4) br(q), k < N/4; the x shift is a
+// unit-modulus phase again.  The per-point sums live in LDS (each lane owns
+// its N/4 entries; in registers they spilled at N = 72).
+constexpr int kDQT = 512;
+
+template <int N>
+__global__ __launch_bounds__(kDQT) __attribute__((amdgpu_waves_per_eu(2))) void k2d_plane_quad(
+    const double2 *__restrict__ sbuf, const double *__restrict__ occ,
+    double *__restrict__ partial, const int *__restrict__ tidx, const double2 *__restrict__ tw_g,
+    int nst, int n3, int ext, int nbk, int bsub) {
+  constexpr int LD = N | 1, Q = N / 4;
+  static_assert(4 * N <= kDQT, "one quad per row");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double2 *T = reinterpret_cast<double2 *>(smem_raw);
+  const int tile = ext * LD;
+  const double2 *zslot = T + tile;
+  double2 *twq = T + tile + 1;   // [4][Q]: row q holds W_N^{q k}
+  double *acc = reinterpret_cast<double *>(twq + 4 * Q);   // [N][N] sums of the plane
+  const int z = blockIdx.x % n3;
+  const int sub = blockIdx.x / n3;
+  const int b0 = sub * bsub;
+  const int b1 = min(nbk, b0 + bsub);
+  const int tid = threadIdx.x;
+  const double2 zero = make_double2(0.0, 0.0);
+  const int q = tid & 3;
+  const int bq = ((q & 1) << 1) | (q >> 1);   // two-bit reversal of q
+  const regfft::QuadLane<double> ql(q);
+  const double2 *tw = twq + q * Q;
+  const bool row_lane = tid < 4 * N;
+  const int y = tid >> 2;
+  if (tid == 0) T[tile] = zero;
+  for (int i = tid; i < 4 * Q; i += kDQT) twq[i] = tw_g[((i / Q) * (i % Q)) % N];
+  for (int i = tid; i < N * N; i += kDQT) acc[i] = 0.0;
+  double *mine = acc + y * N + Q * bq;   // this lane's points (row lanes only)
+  for (int b = b0; b < b1; ++b) {
+    for (int i = tid; i < tile; i += kDQT) T[i] = zero;
+    __syncthreads();
+    const double2 *plane = sbuf + ((size_t)b * n3 + z) * nst;
+    for (int s = tid; s < nst; s += kDQT) T[tidx[s]] = plane[s];
+    __syncthreads();
+    for (int j = tid; j < 4 * ext; j += kDQT) {
+      double2 *col = T + (j >> 2) * LD;
+      double2 v[Q];
+#pragma unroll
+      for (int n = 0; n < Q; ++n) v[n] = col[4 * n + q];
+      regfft::quad_inv<double2, N>(v, tw, ql);
+      double2 *out = col + Q * bq;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) out[k] = v[k];
+    }
+    __syncthreads();
+    if (row_lane) {
+      const double2 *row = T + y;
+      double2 v[Q];
+#pragma unroll
+      for (int n = 0; n < Q; ++n) {
+        const int c = 4 * n + q;
+        const double2 *a = c < ext ? row + c * LD : zslot;
+        v[n] = *a;
+      }
+      regfft::quad_inv<double2, N>(v, tw, ql);
+      const double f = occ[b];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) mine[k] += f * (v[k].x * v[k].x + v[k].y * v[k].y);
+    }
+    __syncthreads();
+  }
+  double *out = partial + ((size_t)sub * n3 + z) * N * N;
+  for (int i = tid; i < N * N; i += kDQT) out[i] = acc[i];
+}
+
 // rho[i] = (accumulate ? rho[i] : 0) + scale * sum_sub partial[sub][i], sub in order.
 __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__ partial,
                                                       int nsub, long npts, double scale,
@@ -1189,6 +1264,19 @@ hipError_t density_plane_pair_launch(const qeh_ctx *c, const DensityGeom &dg, in
   return hipGetLastError();
 }
 
+template <int N>
+hipError_t density_plane_quad_launch(const qeh_ctx *c, const DensityGeom &dg, int nbk,
+                                     const double *occ_d, double *partial) {
+  const int nsub = (nbk + dg.bsub - 1) / dg.bsub;
+  const size_t lds = 16 * ((size_t)c->ext * (N | 1) + 1 + N) + 8 * (size_t)N * N;
+  allow_lds(k2d_plane_quad<N>, lds);
+  hipLaunchKernelGGL(k2d_plane_quad<N>, dim3((unsigned)nsub * c->n3), dim3(kDQT), lds, c->stream,
+                     reinterpret_cast<const double2 *>(c->d.sbuf), occ_d, partial, c->d.tidx,
+                     reinterpret_cast<const double2 *>(c->d.tw) + c->tw_off[0], c->nst, c->n3,
+                     c->ext, nbk, dg.bsub);
+  return hipGetLastError();
+}
+
 template <typename C>
 hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, const void *big,
                              const double *occ_d, double *partial, const void *zcol) {
@@ -1296,10 +1384,18 @@ bool density_geometry(const qeh_ctx *c, DensityGeom *dg) {
   const char *kern = std::getenv("QEH_DENSITY_KERNEL");
   dg->pair = pair_plane_supported(c->prec, n1, n1) && n1 <= 80 && 2 * n2 <= kRT &&
              !(kern && std::strcmp(kern, "generic") == 0);   // N1 = 90 would spill
-  // fused plane pass: lane-pair plane tables (natural y) and a square plane
+  // fused plane pass: lane-pair plane tables (natural y) and a square plane;
+  // in FP64 the lane-quad form on the lane-quad plane tables
+  const bool unfused =
+      kern && (std::strcmp(kern, "rows") == 0 || std::strcmp(kern, "generic") == 0);
   dg->fused = dg->pair && c->plane_path == 2 && n1 == n2 &&
-              8 * ((size_t)c->ext * (n2 | 1) + 1) <= (size_t)kLdsMax &&
-              !(kern && std::strcmp(kern, "rows") == 0);
+              8 * ((size_t)c->ext * (n2 | 1) + 1) <= (size_t)kLdsMax && !unfused;
+  dg->fused_quad = c->prec == QEH_FP64 && c->plane_path == 4 && n1 == n2 && 4 * n1 <= kDQT &&
+                   quad_plane_supported(c->prec, n1, n2) &&
+                   16 * ((size_t)c->ext * (n2 | 1) + 1 + n1) + 8 * (size_t)n1 * n1 <=
+                       (size_t)kLdsMax &&
+                   !unfused;
+  if (dg->fused_quad) dg->fused = true;
   // the fused pass runs its bands one after another per workgroup: smaller
   // subgroups give more workgroups (measured: 8 bands 0.27 ms, 16 bands
   // 0.30 ms per 128-band density at the 72^3 cell)
@@ -1320,6 +1416,15 @@ hipError_t launch_density_columns(const qeh_ctx *c, int nbk, void *big) {
 
 hipError_t launch_density_plane(const qeh_ctx *c, const DensityGeom &dg, int nbk,
                                 const double *occ_d, double *partial) {
+  if (dg.fused_quad) {
+    switch (c->n1) {
+#define QEH_QUAD_CASE(NN) \
+  case NN: return density_plane_quad_launch<NN>(c, dg, nbk, occ_d, partial);
+      QEH_QUAD_SIZES(QEH_QUAD_CASE)
+#undef QEH_QUAD_CASE
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (c->n1) {
 #define QEH_PAIR_CASE(NN) \
   case NN: return density_plane_pair_launch<NN>(c, dg, nbk, occ_d, partial);

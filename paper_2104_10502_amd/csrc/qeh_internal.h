@@ -158,7 +158,9 @@ size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
 struct DensityGeom {
   int rg, ngroups, bsub;
   bool pair;    // lane-pair rows kernel (partial planes in the same layout)
-  bool fused;   // lane-pair fused plane kernel: no column pass through HBM
+  bool fused;   // fused plane kernel (lane pairs, or lane quads in FP64): no column
+                // pass through HBM
+  bool fused_quad;   // the FP64 lane-quad form of the fused kernel
   size_t lds;
   FastDiv rg_div, rglast_div;
 };

@@ -155,3 +155,20 @@ def test_density_row_kernels_agree_mixed(name, monkeypatch):
     _check(a, ref, 1)
     _check(b, ref, 1)
     assert np.abs(a - b).max() < 2e-6 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("fft", [(32, 32, 32), (24, 24, 30)])
+def test_density_fp64_fused_quad(fft, monkeypatch):
+    # FP64 contexts on the lane-quad plane kernel take the fused lane-quad
+    # density pass (11 bands: subgroups of 8 and 3); against the oracle and
+    # against the unfused LDS-pass rows
+    c = cellgen.make_cell("c1", fft=fft)
+    psi = cellgen.make_psi0(c.npw, 11, seed=87)
+    occ = np.linspace(2.0, 0.2, 11)
+    a, ctx = _rho(c, psi, occ, 0, 11)
+    assert ctx.info()["plane_path"] == 4
+    ref = oracle.density(c, psi, occ)
+    _check(a, ref, 0)
+    monkeypatch.setenv("QEH_DENSITY_KERNEL", "generic")
+    b, _ = _rho(c, psi, occ, 0, 11)
+    _check(b, ref, 0)
