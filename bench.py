@@ -205,6 +205,39 @@ def time_gamma(q, torch, nb, steps, warmup):
     return out
 
 
+def davidson_c3_gamma(q, torch):
+    """Block Davidson on the 256-atom cell at k = 0 (135^3 box, 512 bands, H in
+    blocks of 64) on the Gamma path, projectors built on the device: time to
+    the converged eigenvalues in the mixed and FP64 forms, and their largest
+    difference."""
+    import cellgen
+    full = cellgen.make_cell("c3", with_beta=False)
+    pg = cellgen.projgen_tables(full)
+    half = cellgen.gamma_half(full)
+    nb = full.nbnd
+    psi0 = cellgen.make_psi0(half.npw, nb, seed=10502)
+    res, eigs = {}, {}
+    for prec in (q.QEH_MIXED, q.QEH_FP64):
+        ctx = q.Context.from_cell(half, precision=prec, block=64, projgen=pg)
+        p = torch.from_numpy(psi0).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        eig, info = ctx.davidson(p, rtol=1e-8, allow_notconv=True)
+        torch.cuda.synchronize()
+        name = "mixed" if prec else "fp64"
+        eigs[name] = np.sort(eig)
+        res[name] = dict(seconds=time.perf_counter() - t0, status=info["status"],
+                         iters=info["iters"], band_applies=info["band_applies"],
+                         t_hpsi=info["t_hpsi"], t_subspace=info["t_subspace"],
+                         resid_max=info["resid_max"])
+        ctx.close()
+        del p
+        torch.cuda.empty_cache()
+    res["max_eig_diff_mixed_vs_fp64_Ry"] = float(np.abs(eigs["mixed"] - eigs["fp64"]).max())
+    res["npw_stored"], res["bands"] = half.npw, nb
+    return res
+
+
 def time_density(q, torch, cell, prec, nb, steps, warmup):
     """Charge density of nb bands (occupation 2 each): seconds for `steps`
     calls, per-stage device times, context shape."""
@@ -421,6 +454,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--davidson", action="store_true")
+    ap.add_argument("--davidson-c3", action="store_true",
+                    help="also run Davidson on the 256-atom Gamma cell (512 bands)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the charge density leg (128 bands, both forms)")
@@ -550,6 +585,10 @@ def main():
                 eig_min=float(eig[0]), eig_max=float(eig[-1]))
             ctx.close()
         out["davidson"] = dav
+    if a.davidson_c3:
+        out["davidson_c3_gamma"] = davidson_c3_gamma(q, torch)
+        print("# davidson c3 gamma: %s" % json.dumps(out["davidson_c3_gamma"]), file=sys.stderr,
+              flush=True)
     if a.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

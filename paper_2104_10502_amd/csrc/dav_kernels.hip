@@ -181,6 +181,22 @@ __global__ void gamma_inner_kernel(double2 *M, long ld, int nrow, const double2 
   }
 }
 
+// n x n blocks (column-major, leading dimensions given): real part out, and a
+// real matrix back in as complex with zero imaginary part.
+__global__ void real_part_kernel(const double2 *__restrict__ M, long ld, double *__restrict__ R,
+                                 long ldr, int n) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    R[i + (long)j * ldr] = M[i + (long)j * ld].x;
+}
+
+__global__ void real_to_complex_kernel(const double *__restrict__ R, long ldr,
+                                       double2 *__restrict__ M, long ld, int n) {
+  const int j = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    M[i + (long)j * ld] = make_double2(R[i + (long)j * ldr], 0.0);
+}
+
 __global__ void zero_g0_imag_kernel(double2 *psi, long ldpsi, int nb) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nb) psi[(long)b * ldpsi].y = 0.0;
@@ -233,6 +249,22 @@ hipError_t launch_gamma_inner(double2 *M, long ld, int nrow, int ncol, const dou
   if (nrow <= 0 || ncol <= 0) return hipSuccess;
   hipLaunchKernelGGL(gamma_inner_kernel, dim3((nrow + 255) / 256, ncol), dim3(256), 0, s, M, ld,
                      nrow, X, Y, npw);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_part(const double2 *M, long ld, double *R, long ldr, int n,
+                            hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(real_part_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, M, ld, R, ldr,
+                     n);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_to_complex(const double *R, long ldr, double2 *M, long ld, int n,
+                                  hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(real_to_complex_kernel, dim3((n + 255) / 256, n), dim3(256), 0, s, R, ldr, M,
+                     ld, n);
   return hipGetLastError();
 }
 

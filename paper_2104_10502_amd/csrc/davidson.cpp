@@ -66,6 +66,11 @@ qeh_status solver_bytes(int n, size_t *out) {
   rocsolver_ztrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
   rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
                    nullptr);
+  // the real routines of the Gamma-point path
+  rocsolver_dpotrf(h, rocblas_fill_lower, n, nullptr, n, nullptr);
+  rocsolver_dtrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
+  rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
+                   nullptr);
   size_t sz = 0;
   rocblas_stop_device_memory_size_query(h, &sz);
   *out = sz;
@@ -431,9 +436,21 @@ bool DavRun::advance() {
         const int n = nbase_;
         ok(launch_hermitise_copy(Hr_, nvecx, Hw_, nvecx, n, s));
         ok(launch_hermitise_copy(Sr_, nvecx, Sw_, nvecx, n, s));
-        rocblas_status rs = rocsolver_zpotrf(rh_, rocblas_fill_lower, n,
-                                             reinterpret_cast<rocblas_double_complex *>(Sw_),
-                                             nvecx, info_d_ + 1);
+        rocblas_status rs;
+        if (c_->gamma) {
+          // Gamma: the reduced matrices are real symmetric; the real routines
+          // work on a real copy in X's space (rocSOLVER's complex eigensolver
+          // returned non-finite vectors for complex input with all imaginary
+          // parts zero at n >= 128)
+          double *xr = reinterpret_cast<double *>(X_);
+          ok(launch_real_part(Sw_, nvecx, xr, nvecx, n, s));
+          rs = rocsolver_dpotrf(rh_, rocblas_fill_lower, n, xr, nvecx, info_d_ + 1);
+          ok(launch_real_to_complex(xr, nvecx, Sw_, nvecx, n, s));
+        } else {
+          rs = rocsolver_zpotrf(rh_, rocblas_fill_lower, n,
+                                reinterpret_cast<rocblas_double_complex *>(Sw_), nvecx,
+                                info_d_ + 1);
+        }
         ev_s_.stop(s);
         if (rs != rocblas_status_success) {
           set_error("rocsolver_zpotrf failed to launch");
@@ -453,16 +470,31 @@ bool DavRun::advance() {
         }
         const int n = nbase_;
         ev_s_.start(s);
-        rocblas_status rs = rocsolver_ztrtri(rh_, rocblas_fill_lower, rocblas_diagonal_non_unit,
-                                             n, reinterpret_cast<rocblas_double_complex *>(Sw_),
-                                             nvecx, info_d_ + 2);
+        double *xr = reinterpret_cast<double *>(X_);   // Gamma: real scratch
+        rocblas_status rs;
+        if (c_->gamma) {
+          ok(launch_real_part(Sw_, nvecx, xr, nvecx, n, s));
+          rs = rocsolver_dtrtri(rh_, rocblas_fill_lower, rocblas_diagonal_non_unit, n, xr, nvecx,
+                                info_d_ + 2);
+          ok(launch_real_to_complex(xr, nvecx, Sw_, nvecx, n, s));
+        } else {
+          rs = rocsolver_ztrtri(rh_, rocblas_fill_lower, rocblas_diagonal_non_unit, n,
+                                reinterpret_cast<rocblas_double_complex *>(Sw_), nvecx,
+                                info_d_ + 2);
+        }
         ok(launch_tril_adjoint(Sw_, Lc_, LcH_, nvecx, n, s));
         ok(square_product(c_, Hw_, Lc_, X_, n, nvecx));     // X = L^-1 Hr
         ok(square_product(c_, LcH_, X_, Hw_, n, nvecx));    // A = X L^-H
-        if (rs == rocblas_status_success)
+        if (rs == rocblas_status_success && c_->gamma) {
+          ok(launch_real_part(Hw_, nvecx, xr, nvecx, n, s));
+          rs = rocsolver_dsyevd(rh_, rocblas_evect_original, rocblas_fill_upper, n, xr, nvecx,
+                                eps_d_, E_d_, info_d_ + 3);
+          ok(launch_real_to_complex(xr, nvecx, Hw_, nvecx, n, s));
+        } else if (rs == rocblas_status_success) {
           rs = rocsolver_zheevd(rh_, rocblas_evect_original, rocblas_fill_upper, n,
                                 reinterpret_cast<rocblas_double_complex *>(Hw_), nvecx, eps_d_,
                                 E_d_, info_d_ + 3);
+        }
         ok(square_product_cols(c_, Hw_, LcH_, Y_, n, nb, nvecx));   // Y = L^-H Z
         ev_s_.stop(s);
         if (rs != rocblas_status_success) {

@@ -256,6 +256,11 @@ hipError_t launch_gamma_unpack(const double2 *hc, long ldc, int nbk, int nh, con
 hipError_t launch_gamma_inner(double2 *M, long ld, int nrow, int ncol, const double2 *X,
                               const double2 *Y, long npw, hipStream_t s);
 hipError_t launch_zero_g0_imag(double2 *psi, long ldpsi, int nb, hipStream_t s);
+// n x n blocks, column-major: R = Re M, and M = R + 0 i.
+hipError_t launch_real_part(const double2 *M, long ld, double *R, long ldr, int n,
+                            hipStream_t s);
+hipError_t launch_real_to_complex(const double *R, long ldr, double2 *M, long ld, int n,
+                                  hipStream_t s);
 // Copy rows; Hermitian fill; diag set etc.
 hipError_t launch_copy_rows(const double2 *src, long lds, double2 *dst, long ldd, int npw,
                             int nrows, hipStream_t s);
