@@ -205,20 +205,21 @@ def time_gamma(q, torch, nb, steps, warmup):
     return out
 
 
-def davidson_c3_gamma(q, torch):
-    """Block Davidson on the 256-atom cell at k = 0 (135^3 box, 512 bands, H in
-    blocks of 64) on the Gamma path, projectors built on the device: time to
+def davidson_gamma(q, torch, name="c3"):
+    """Block Davidson on a Gamma-point cell on the Gamma path, projectors built
+    on the device: the 256-atom cell (135^3 box, 512 bands, H in blocks of 64)
+    or the 512-atom cell (160x160x168, 1024 bands in blocks of 128).  Time to
     the converged eigenvalues in the mixed and FP64 forms, and their largest
     difference."""
     import cellgen
-    full = cellgen.make_cell("c3", with_beta=False)
+    full = cellgen.make_cell(name, with_beta=False)
     pg = cellgen.projgen_tables(full)
     half = cellgen.gamma_half(full)
     nb = full.nbnd
     psi0 = cellgen.make_psi0(half.npw, nb, seed=10502)
     res, eigs = {}, {}
     for prec in (q.QEH_MIXED, q.QEH_FP64):
-        ctx = q.Context.from_cell(half, precision=prec, block=64, projgen=pg)
+        ctx = q.Context.from_cell(half, precision=prec, block=full.block, projgen=pg)
         p = torch.from_numpy(psi0).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -456,6 +457,8 @@ def main():
     ap.add_argument("--davidson", action="store_true")
     ap.add_argument("--davidson-c3", action="store_true",
                     help="also run Davidson on the 256-atom Gamma cell (512 bands)")
+    ap.add_argument("--davidson-c5", action="store_true",
+                    help="also run Davidson on the 512-atom Gamma cell (1024 bands)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-density", action="store_true",
                     help="skip the charge density leg (128 bands, both forms)")
@@ -585,10 +588,10 @@ def main():
                 eig_min=float(eig[0]), eig_max=float(eig[-1]))
             ctx.close()
         out["davidson"] = dav
-    if a.davidson_c3:
-        out["davidson_c3_gamma"] = davidson_c3_gamma(q, torch)
-        print("# davidson c3 gamma: %s" % json.dumps(out["davidson_c3_gamma"]), file=sys.stderr,
-              flush=True)
+    for name in (["c3"] if a.davidson_c3 else []) + (["c5"] if a.davidson_c5 else []):
+        key = "davidson_%s_gamma" % name
+        out[key] = davidson_gamma(q, torch, name)
+        print("# %s: %s" % (key, json.dumps(out[key])), file=sys.stderr, flush=True)
     if a.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
