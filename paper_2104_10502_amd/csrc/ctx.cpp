@@ -430,7 +430,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   L.off_psi32 = bump(&cur, c->precision == QEH_MIXED ? 8 * (size_t)c->block * hm.npw_fft : 0);
   // projectors built on the device: the generator's staging area
   L.off_pgen = bump(&cur, g.nkb > 0 && !c->beta ? projgen_layout(c).total : 0);
-  // Gamma: band pairs packed over the full sphere (FP64), reused for the result
+  // Gamma: the full-sphere H of the band pairs (FP64), written by K3
   L.off_gbuf = bump(&cur, c->gamma ? 16 * (size_t)((c->block + 1) / 2) * hm.npw_fft : 0);
   L.total = cur;
   return L;

@@ -91,7 +91,7 @@ struct DevMaps {
   void *ps;          // [block][nkb] D * becp (working complex type)
   float2 *psi32;     // mixed form: [block][npw] single-precision copy of psi (K1)
   void *big;         // split plane path: [block][N3][ext][N2] (or null)
-  double2 *gbuf;     // Gamma: [(block+1)/2][npw_fft] packed band pairs / their H (or null)
+  double2 *gbuf;     // Gamma: [(block+1)/2][npw_fft] full-sphere H of band pairs (or null)
   int *colstart;     // [ext+1] first stick of each x-extent column
 };
 
