@@ -29,6 +29,7 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <utility>
 
 namespace qeh {
 qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldpsi,
@@ -44,14 +45,16 @@ size_t bump2(size_t *cur, size_t bytes) {
   return o;
 }
 
-qeh_status solver_bytes(int n, size_t *out) {
-  // the answer depends on n only: cache it; the query needs a handle, made
-  // once (creating one per query cost more than the query itself)
+qeh_status solver_bytes(int n, bool real, size_t *out) {
+  // the answer depends on n and the routine set only: cache it; the query
+  // needs a handle, made once (creating one per query cost more than the
+  // query itself)
   static std::mutex mu;
-  static std::map<int, size_t> cache;
+  static std::map<std::pair<int, bool>, size_t> cache;
   static rocblas_handle h = nullptr;
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(n);
+  const std::pair<int, bool> key(n, real);
+  auto it = cache.find(key);
   if (it != cache.end()) {
     *out = it->second;
     return QEH_OK;
@@ -66,15 +69,18 @@ qeh_status solver_bytes(int n, size_t *out) {
   rocsolver_ztrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
   rocsolver_zheevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
                    nullptr);
-  // the real routines of the Gamma-point path
-  rocsolver_dpotrf(h, rocblas_fill_lower, n, nullptr, n, nullptr);
-  rocsolver_dtrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
-  rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr, nullptr,
-                   nullptr);
+  if (real) {
+    // the real routines of the Gamma-point path (queried for Gamma contexts
+    // only: general-k solves run the complex set alone)
+    rocsolver_dpotrf(h, rocblas_fill_lower, n, nullptr, n, nullptr);
+    rocsolver_dtrtri(h, rocblas_fill_lower, rocblas_diagonal_non_unit, n, nullptr, n, nullptr);
+    rocsolver_dsyevd(h, rocblas_evect_original, rocblas_fill_upper, n, nullptr, n, nullptr,
+                     nullptr, nullptr);
+  }
   size_t sz = 0;
   rocblas_stop_device_memory_size_query(h, &sz);
   *out = sz;
-  cache[n] = sz;
+  cache[key] = sz;
   return QEH_OK;
 }
 
@@ -274,7 +280,7 @@ qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
   L->idx = bump2(&cur, 4 * (size_t)nb);
   L->info = bump2(&cur, 16);
   L->flag = bump2(&cur, 4);
-  qeh_status st = solver_bytes(nvecx, &L->solver_bytes);
+  qeh_status st = solver_bytes(nvecx, c->gamma != 0, &L->solver_bytes);
   if (st != QEH_OK) return st;
   L->solver = bump2(&cur, std::max<size_t>(L->solver_bytes, 256));
   L->total = cur;

@@ -336,9 +336,10 @@ void server_loop(qeh_server *s) {
 qeh_status plan_job(const qeh_cell *cell, int nb, const qeh_dav_opts *o, Job *j) {
   qeh_status st = qeh_ctx_plan(cell, &j->ctx_bytes);
   if (st != QEH_OK) return st;
-  // the Davidson plan needs only npw from a context
+  // the Davidson plan needs only npw and the Gamma flag from a context
   qeh_ctx probe;
   probe.npw = cell->npw;
+  probe.gamma = cell->gamma ? 1 : 0;
   int nvecx, maxiter;
   double rtol;
   st = dav_check_opts(&probe, nb, o, &nvecx, &rtol, &maxiter);
