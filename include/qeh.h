@@ -247,6 +247,17 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
                         double *eig, const qeh_dav_opts *opts, void *work,
                         size_t work_bytes, qeh_dav_info *info);
 
+/* Diagonal of H over the context's plane waves (npw doubles, the cell's G
+ * order): |k+G|^2 + the mean of V(r) + sum over atoms of
+ * sum_ij Re(beta_i(G) D_ij conj(beta_j(G))), the diagonal that the Davidson
+ * preconditioner divides by (the preconditioner is among the kernels of the
+ * GPU port, section "Evolution of the GPU-enabled version").  Built when the
+ * context is created (the nonlocal sum on the device when the projectors come
+ * from radial tables).  Copied to hdiag (DEVICE, npw doubles, caller-owned)
+ * on the context stream; returns after enqueueing the copy.  Null arguments:
+ * QEH_ERR_INVALID. */
+qeh_status qeh_ctx_hdiag(const qeh_ctx *ctx, double *hdiag);
+
 /* Per-stage device timing of H application and of the charge density (HIP
  * events on the context stream).  Stages: 0 scatter+z-FFT, 1 plane pass,
  * 2 z-FFT+gather+kinetic, 3 beta^H psi, 4 D scaling, 5 beta ps accumulate,

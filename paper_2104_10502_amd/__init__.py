@@ -98,6 +98,7 @@ _SIGS = {
     "qeh_ctx_stage_times": ([_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_long), ctypes.c_int],
                             ctypes.c_int),
     "qeh_ctx_info": ([_vp, ctypes.POINTER(ctypes.c_long), ctypes.c_int], ctypes.c_int),
+    "qeh_ctx_hdiag": ([_vp, _vp], ctypes.c_int),
     "qeh_server_create": ([_vp, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)],
                           ctypes.c_int),
     "qeh_submit": ([_vp, ctypes.POINTER(QehCell), ctypes.c_int, ctypes.c_int, _c_dbl_p,
@@ -427,6 +428,13 @@ class Context:
         n = (ctypes.c_long * NSTAGES)()
         _check(_lib.qeh_ctx_stage_times(self._h, ms, n, NSTAGES), "qeh_ctx_stage_times")
         return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(NSTAGES)}
+
+    def hdiag(self):
+        """diag(H) over the plane waves (float64 device tensor, npw values),
+        the preconditioner's diagonal; copied on the context stream."""
+        out = torch.empty(self.npw, dtype=torch.float64, device=self.device)
+        _check(_lib.qeh_ctx_hdiag(self._h, ctypes.c_void_p(out.data_ptr())), "qeh_ctx_hdiag")
+        return out
 
     def info(self):
         out = (ctypes.c_long * 11)()

@@ -97,50 +97,65 @@ template <> __device__ __forceinline__ double2 ld2<float2>(const float2 *p) {
   return make_double2(v.x, v.y);
 }
 
-// hdiag[G] += sum_a sum_ij Re(beta_i(G) D_ij conj(beta_j(G))), atoms and
-// projectors in order (one thread per G, deterministic).
+// hdiag[G] += sum_a sum_ij Re(beta_i(G) D_ij conj(beta_j(G))).  A workgroup
+// holds 64 consecutive G (one per lane) and kDW waves; wave w sums the atoms
+// w, w + kDW, ... in order, and wave 0 adds the kDW partial sums in wave
+// order, so the result does not depend on scheduling.  Spreading the atoms
+// over the waves gives kDW times the workgroups' parallelism of a thread per G.
+constexpr int kDW = 16;
+
 template <typename T2>
-__global__ __launch_bounds__(kBT) void nl_diag_kernel(const T2 *__restrict__ beta, long ldb,
-                                                      int npw, int nat,
-                                                      const int4 *__restrict__ atoms,
-                                                      const double2 *__restrict__ dmat,
-                                                      double *__restrict__ hdiag) {
-  const int g = blockIdx.x * kBT + threadIdx.x;
-  if (g >= npw) return;
+__global__ __launch_bounds__(64 * kDW) void nl_diag_kernel(const T2 *__restrict__ beta, long ldb,
+                                                           int npw, int nat,
+                                                           const int4 *__restrict__ atoms,
+                                                           const double2 *__restrict__ dmat,
+                                                           double *__restrict__ hdiag) {
+  __shared__ double part[kDW][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = blockIdx.x * 64 + lane;
   constexpr int kReg = 16;   // atoms with up to this many projectors: values in registers
   double acc = 0.0;
-  for (int a = 0; a < nat; ++a) {
-    const int4 at = atoms[a];
-    const int n = at.z;
-    const T2 *b = beta + (long)at.y * ldb + g;
-    const double2 *D = dmat + at.w;
-    if (n <= kReg) {
-      double2 v[kReg];
+  if (g < npw) {
+    for (int a = w; a < nat; a += kDW) {
+      const int4 at = atoms[a];
+      const int n = at.z;
+      const T2 *b = beta + (long)at.y * ldb + g;
+      const double2 *D = dmat + at.w;
+      if (n <= kReg) {
+        double2 v[kReg];
 #pragma unroll
-      for (int i = 0; i < kReg; ++i)
-        v[i] = i < n ? ld2<T2>(b + (long)i * ldb) : make_double2(0.0, 0.0);
+        for (int i = 0; i < kReg; ++i)
+          v[i] = i < n ? ld2<T2>(b + (long)i * ldb) : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < kReg; ++i)
+        for (int i = 0; i < kReg; ++i)
 #pragma unroll
-        for (int k = 0; k < kReg; ++k)
-          if (i < n && k < n) {
+          for (int k = 0; k < kReg; ++k)
+            if (i < n && k < n) {
+              const double2 d = D[i * n + k];
+              const double tr = v[i].x * d.x - v[i].y * d.y, ti = v[i].x * d.y + v[i].y * d.x;
+              acc += tr * v[k].x + ti * v[k].y;
+            }
+      } else {
+        for (int i = 0; i < n; ++i) {
+          const double2 bi = ld2<T2>(b + (long)i * ldb);
+          for (int k = 0; k < n; ++k) {
             const double2 d = D[i * n + k];
-            const double tr = v[i].x * d.x - v[i].y * d.y, ti = v[i].x * d.y + v[i].y * d.x;
-            acc += tr * v[k].x + ti * v[k].y;
+            const double2 bk = ld2<T2>(b + (long)k * ldb);
+            const double tr = bi.x * d.x - bi.y * d.y, ti = bi.x * d.y + bi.y * d.x;
+            acc += tr * bk.x + ti * bk.y;
           }
-    } else {
-      for (int i = 0; i < n; ++i) {
-        const double2 bi = ld2<T2>(b + (long)i * ldb);
-        for (int k = 0; k < n; ++k) {
-          const double2 d = D[i * n + k];
-          const double2 bk = ld2<T2>(b + (long)k * ldb);
-          const double tr = bi.x * d.x - bi.y * d.y, ti = bi.x * d.y + bi.y * d.x;
-          acc += tr * bk.x + ti * bk.y;
         }
       }
     }
   }
-  hdiag[g] += acc;
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && g < npw) {
+    double t = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < kDW; ++k) t += part[k][lane];
+    hdiag[g] += t;
+  }
 }
 
 }  // namespace
@@ -166,12 +181,12 @@ hipError_t launch_nl_diag(bool f64, const void *beta, long ldb, int npw, int nat
                           const int4 *atoms, const double2 *dmat, double *hdiag,
                           hipStream_t s) {
   if (npw <= 0 || nat <= 0) return hipSuccess;
-  const dim3 grid((npw + kBT - 1) / kBT);
+  const dim3 grid((npw + 63) / 64);
   if (f64)
-    hipLaunchKernelGGL(nl_diag_kernel<double2>, grid, dim3(kBT), 0, s,
+    hipLaunchKernelGGL(nl_diag_kernel<double2>, grid, dim3(64 * kDW), 0, s,
                        static_cast<const double2 *>(beta), ldb, npw, nat, atoms, dmat, hdiag);
   else
-    hipLaunchKernelGGL(nl_diag_kernel<float2>, grid, dim3(kBT), 0, s,
+    hipLaunchKernelGGL(nl_diag_kernel<float2>, grid, dim3(64 * kDW), 0, s,
                        static_cast<const float2 *>(beta), ldb, npw, nat, atoms, dmat, hdiag);
   return hipGetLastError();
 }

@@ -1058,6 +1058,14 @@ qeh_status qeh_ctx_stage_times(qeh_ctx *c, double *ms, long *launches, int nstag
   return QEH_OK;
 }
 
+qeh_status qeh_ctx_hdiag(const qeh_ctx *c, double *hdiag) {
+  if (!c || !hdiag) return invalid("null argument");
+  const hipError_t e = hipMemcpyAsync(hdiag, c->d.hdiag, 8 * (size_t)c->npw,
+                                      hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hdiag copy");
+  return QEH_OK;
+}
+
 qeh_status qeh_ctx_info(const qeh_ctx *c, long *out, int n) {
   if (!c || !out) return invalid("null argument");
   const long v[11] = {c->npw, c->nst, c->nkb, c->n1, c->n2, c->n3, c->ext, c->block, c->prec,

@@ -157,6 +157,13 @@ def test_plan_rejects_bad_block_and_precision(c1):
     assert _plan(c1, precision=7)[0] == -1
 
 
+def test_null_context_arguments():
+    # argument checks that return before any device call
+    q = _q()
+    assert q._lib.qeh_ctx_hdiag(None, None) == -1
+    assert b"null" in q._lib.qeh_last_error()
+
+
 def test_status_strings():
     q = _q()
     for s in range(-8, 1):

@@ -222,3 +222,44 @@ def test_generate_species_without_projectors():
     ref = oracle.beta_projectors(c.lattice, c.kpt, c.miller, pos, ityp, species)
     assert got.shape == ref.shape == (8, c.npw)
     assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("which", ["c1", "aniso_s2pd", "c2"])
+def test_hdiag_matches_oracle(which, prec):
+    # diag(H) of a context (the preconditioner's diagonal) against the
+    # oracle's on the cell's closed-form projectors: with those projectors
+    # given (nonlocal sum on the host in FP64), and with the tables instead
+    # (nonlocal sum on the device over the generated beta: FP64, or FP32 in
+    # the mixed form; interpolation error as for beta itself).  The 64-atom
+    # cell spreads its atoms over every wave of a workgroup.
+    q = _q()
+    c = cellgen.make_cell(which) if which != "aniso_s2pd" else _aniso_cell()
+    print("case hdiag", which, "prec", prec, flush=True)
+    ref = oracle.hdiag(c)
+    scale = np.abs(ref).max()
+    # the nonlocal part is not negligible here
+    assert np.abs(ref - oracle.kinetic(c) - np.mean(c.vloc)).max() > 1e-3 * scale
+    ctx_h = q.Context.from_cell(c, precision=prec, block=8)
+    assert np.abs(ctx_h.hdiag().cpu().numpy() - ref).max() < 1e-12 * scale
+    ctx_h.close()
+    ctx_d = q.Context.from_cell(dataclasses.replace(c, beta=None), precision=prec, block=8,
+                                projgen=cellgen.projgen_tables(c))
+    got = ctx_d.hdiag().cpu().numpy()
+    assert got.shape == (c.npw,)
+    tol = 1e-8 if prec == 0 else 1e-6
+    assert np.abs(got - ref).max() < tol * scale
+
+
+def test_hdiag_gamma_half():
+    # Gamma cell: diag(H) over the stored half sphere, both projector sources
+    q = _q()
+    from oracle import gamma
+    c = cellgen.make_cell("c1")
+    h = cellgen.gamma_half(c)
+    ref = gamma.restrict(oracle.hdiag(c)[None, :])[0]
+    got = q.Context.from_cell(h, precision=0, block=8).hdiag().cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
+    got = q.Context.from_cell(h, precision=0, block=8,
+                              projgen=cellgen.projgen_tables(c)).hdiag().cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
