@@ -238,8 +238,10 @@ def test_hdiag_matches_oracle(which, prec):
     print("case hdiag", which, "prec", prec, flush=True)
     ref = oracle.hdiag(c)
     scale = np.abs(ref).max()
-    # the nonlocal part is not negligible here
-    assert np.abs(ref - oracle.kinetic(c) - np.mean(c.vloc)).max() > 1e-3 * scale
+    # the nonlocal part (small next to the kinetic energy at the sphere's
+    # edge) sets the bar for the device sum
+    nl = np.abs(ref - oracle.kinetic(c) - np.mean(c.vloc)).max()
+    assert nl > 1e-5 * scale
     ctx_h = q.Context.from_cell(c, precision=prec, block=8)
     assert np.abs(ctx_h.hdiag().cpu().numpy() - ref).max() < 1e-12 * scale
     ctx_h.close()
@@ -248,7 +250,7 @@ def test_hdiag_matches_oracle(which, prec):
     got = ctx_d.hdiag().cpu().numpy()
     assert got.shape == (c.npw,)
     tol = 1e-8 if prec == 0 else 1e-6
-    assert np.abs(got - ref).max() < tol * scale
+    assert np.abs(got - ref).max() < tol * nl + 1e-13 * scale
 
 
 def test_hdiag_gamma_half():
@@ -262,4 +264,5 @@ def test_hdiag_gamma_half():
     assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
     got = q.Context.from_cell(h, precision=0, block=8,
                               projgen=cellgen.projgen_tables(c)).hdiag().cpu().numpy()
-    assert np.abs(got - ref).max() < 1e-8 * np.abs(ref).max()
+    nl = np.abs(oracle.hdiag(c) - oracle.kinetic(c) - np.mean(c.vloc)).max()
+    assert np.abs(got - ref).max() < 1e-8 * nl + 1e-13 * np.abs(ref).max()
