@@ -432,6 +432,7 @@ class Context:
     def hdiag(self):
         """diag(H) over the plane waves (float64 device tensor, npw values),
         the preconditioner's diagonal; copied on the context stream."""
+        torch = _torch()
         out = torch.empty(self.npw, dtype=torch.float64, device=self.device)
         _check(_lib.qeh_ctx_hdiag(self._h, ctypes.c_void_p(out.data_ptr())), "qeh_ctx_hdiag")
         return out
