@@ -93,3 +93,29 @@ def test_admission_reject_wait_cancel():
         assert a <= s <= b <= f
     assert all(np.array_equal(res[ts[0]]["eig"], res[t]["eig"]) for t in ts)
     small.close()
+
+
+def test_gamma_and_general_k_requests_together():
+    # a Gamma request and a general-k request with the same subspace size run
+    # side by side: the Davidson plan of each carries its own solver
+    # workspace (the real routines' for Gamma), and both match LAPACK
+    q = _q()
+    cg = cellgen.make_cell("c1")
+    ck = cellgen.make_cell("c1", kfrac=(0.25, 0.25, 0.25))
+    h = cellgen.gamma_half(cg)
+    nb = cg.nbnd
+    ref_g = sla.eigh(oracle.dense_h(cg), eigvals_only=True, subset_by_index=[0, nb - 1])
+    ref_k = sla.eigh(oracle.dense_h(ck), eigvals_only=True, subset_by_index=[0, nb - 1])
+    srv = q.Server(1 << 30, max_slots=4)
+    kw = dict(precision=q.QEH_FP64, rtol=1e-9)
+    tickets = []
+    for _ in range(2):
+        tickets.append(srv.submit([h], [cellgen.make_psi0(h.npw, nb, seed=7)], nb, **kw))
+        tickets.append(srv.submit([ck], [cellgen.make_psi0(ck.npw, nb, seed=8)], nb, **kw))
+    out = _wait(srv, tickets)
+    srv.close()
+    for i, t in enumerate(tickets):
+        r = out[t]
+        assert r["status"] == 0, r["error"]
+        ref = ref_g if i % 2 == 0 else ref_k
+        assert np.abs(np.sort(r["eig"][0]) - ref).max() < 1e-9
