@@ -355,7 +355,7 @@ def make_trace(duration, rate, seed=2104, device_beta=True):
     return trace, reqs, time.perf_counter() - t_gen
 
 
-def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=32, arena_gib=96,
+def serve_bench(q, trace, reqs, t_gen, duration, rate, slots=8, arena_gib=96,
                 device_beta=True):
     """Replay a Poisson trace of Davidson requests (random cubic cells, 8-128 atoms,
     ecutwfc in {20,25,30} Ry, 1-4 k-points, nb = 2 nat, mixed form) against the server."""
@@ -470,7 +470,7 @@ def main():
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-child", action="store_true", help=argparse.SUPPRESS)
-    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-host-beta", action="store_true",
                     help="served requests carry host-built projectors instead of radial tables")
     ap.add_argument("--calibrate-copy", action="store_true",

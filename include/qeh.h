@@ -288,7 +288,10 @@ qeh_status qeh_ctx_stage_times(qeh_ctx *ctx, double *ms, long *launches, int nst
 typedef struct qeh_server qeh_server;
 
 /* arena: DEVICE memory (256-byte aligned) used for every admitted job; the
- * server never allocates device memory.  max_slots in [1, 64]. */
+ * server never allocates device memory.  max_slots in [1, 64].  Eight slots
+ * already keep the device busy on served Davidson solves (their dense
+ * eigensolver is launch-bound); with 16 or more slots the serving process has
+ * ended with a segmentation fault now and then, a fault not yet located. */
 qeh_status qeh_server_create(void *arena, size_t arena_bytes, int max_slots,
                              qeh_server **out);
 

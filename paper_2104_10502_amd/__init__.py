@@ -228,7 +228,7 @@ def generate_beta(lattice, kpt, miller, nproj, projgen, precision=QEH_FP64, devi
 class Server:
     """Continuous-batching Davidson server over a device arena of ``arena_bytes``."""
 
-    def __init__(self, arena_bytes, max_slots=16, device=None):
+    def __init__(self, arena_bytes, max_slots=8, device=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
