@@ -209,7 +209,10 @@ bool start_job(qeh_server *s, Job *j) {
     return false;
   }
   double2 *psi = reinterpret_cast<double2 *>(base + j->ctx_bytes);
-  hipError_t e = hipMemcpyAsync(psi, j->hc.psi0.data(), j->psi_bytes, hipMemcpyHostToDevice, st);
+  // exactly the host copy's bytes (psi_bytes is that size rounded up to the
+  // arena alignment; reading that far would run past the end of the vector)
+  hipError_t e = hipMemcpyAsync(psi, j->hc.psi0.data(), sizeof(double) * j->hc.psi0.size(),
+                                hipMemcpyHostToDevice, st);
   if (e != hipSuccess) {
     j->st = hip_fail(e, "psi0 upload");
     return false;
