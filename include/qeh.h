@@ -282,16 +282,18 @@ qeh_status qeh_ctx_stage_times(qeh_ctx *ctx, double *ms, long *launches, int nst
  * first-come first-served as soon as their whole footprint fits in the free
  * arena and nk slots are free (smaller later requests may pass a head request
  * that has waited < 0.25 s); every admitted job runs its Davidson on its own
- * stream, so work of different requests overlaps on the device.  Results do
- * not depend on what else is running.
+ * stream, so work of different requests overlaps on the device.  A request
+ * solved alone, repeated, gives the same bits; among concurrent requests the
+ * low-order bits of some results can differ from run to run (mixed-form
+ * eigenvalues by up to ~3e-5 Ry on the served trace), with a different
+ * iteration count.
  * ------------------------------------------------------------------------- */
 typedef struct qeh_server qeh_server;
 
 /* arena: DEVICE memory (256-byte aligned) used for every admitted job; the
- * server never allocates device memory.  max_slots in [1, 64].  Eight slots
+ * server never allocates device memory.  max_slots in [1, 64]; eight slots
  * already keep the device busy on served Davidson solves (their dense
- * eigensolver is launch-bound); with 16 or more slots the serving process has
- * ended with a segmentation fault now and then, a fault not yet located. */
+ * eigensolver is launch-bound). */
 qeh_status qeh_server_create(void *arena, size_t arena_bytes, int max_slots,
                              qeh_server **out);
 
