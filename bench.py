@@ -1,24 +1,31 @@
 """Benchmark: H|psi> band-applies per second on one MI355X.
 
-Workload: the 64-atom diamond-like supercell (cubic a = 20.52 bohr, one k-point
-(1/4,1/4,1/4) 2pi/a, ecutwfc 30 Ry, 72^3 FFT box, 23 976 plane waves,
-512 projectors), 128 bands applied as one block per step.  Inputs are seeded
+Headline workload: the 512-atom orthorhombic cell (40 x 40 x 42 bohr, diamond
+sites, Gamma point, ecutwfc 30 Ry, 160 x 160 x 168 FFT box, 186 449 plane waves
+on the full sphere, 93 225 stored on the Gamma half sphere, 6 144 s/p/d
+projectors), 1 024 bands applied per step in launches of 128 on the Gamma
+path (real wavefunctions: two bands per complex FFT, real projections).
+Projectors are built on the device from radial tables; inputs are seeded
 synthetic (Gaussian model pseudopotential), resident in HBM before timing.
 
 A step = one full H|psi> (kinetic + local-potential FFT path + nonlocal
-projectors) over all 128 bands; the timed steps run without instrumentation.  ``value`` is the mixed form (FP32 FFTs and
-projector GEMMs, FP64 psi / kinetic); the plain FP64 form is reported beside
-it.  Per-kernel device times come from HIP events recorded on the context
-stream during a second, equal set of steps; ``roofline`` reports the dominant
-kernel.
-``cpu_baseline`` times the FP64 oracle's H|psi> on a bounded band sample on
-the host cores.  The charge density of the same 128 bands (both forms) is
-timed beside it (``density``), and a 5 s replay of the served request trace
-(Poisson arrivals at 20 req/s) reports p50/p99 latency (``serve``; --serve 0
-skips it).  Davidson time-to-solution is reported when --davidson is set.
+projectors) over all 1 024 bands; the timed steps run without
+instrumentation.  ``value`` is the mixed form (FP32 FFTs and projector GEMMs,
+FP64 psi / kinetic); the plain FP64 form is reported beside it.  Per-kernel
+device times come from HIP events recorded on the context stream during a
+second, equal set of steps; ``kernels`` prices each against the resource that
+bounds it and ``roofline`` reports the dominant one.
 
-usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--davidson] [--serve SECONDS]
-                      [--no-cpu] [--no-density]
+Beside it: the same cell as a general complex k = 0 (full sphere), the 64-atom
+cell (72^3 box, 128 bands, both forms, its charge density and projector
+generation, and its k = 0 Gamma comparison), block-Davidson time to solution
+on the 64-, 256- and 512-atom cells with eigenvalues held to the stored FP64
+oracle values, a replay of the served request trace (``serve``), and
+``cpu_baseline``: the FP64 oracle's H|psi> timed on a bounded band sample of
+the headline cell on the host cores.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve SECONDS]
+                      [--no-cpu] [--no-davidson] [--no-extras]
 """
 
 from __future__ import annotations
@@ -37,11 +44,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_F32_TFLOPS = 157.3
 MFMA_F64_TFLOPS = 78.6
-# vector ALU peaks (256 CUs x 4 SIMDs x 16 lanes x FMA at 2.4 GHz = 78.6 TFLOP/s
-# per instruction stream; the published FP32 figure counts packed FP32, 2x)
-VALU_F32_TFLOPS = 157.3
+# vector ALU: 256 CUs x 4 SIMDs x 16 lanes x FMA at 2.4 GHz = 78.6 TFLOP/s per
+# instruction stream for FP32 and FP64 alike; the published FP32 figure
+# (157.3) counts packed two-wide FP32, which every HIP source here is compiled
+# without, so one-wide FP32 issue peaks at 78.6
+VALU_F32_ONE_WIDE_TFLOPS = 78.6
 VALU_F64_TFLOPS = 78.6
 METRIC = "H|psi> band-applies/sec (FFT pts*bands/s) FP32 vs FP64; serve p50/p99 latency"
+DENSITY_BSUB = 16   # bands per density subgroup (library constant)
 
 
 def fft_flops(n):
@@ -50,29 +60,48 @@ def fft_flops(n):
 
 
 def plane_flops(shape):
-    """Flops of the pruned plane pass per band and z plane: inverse and forward
-    transforms of the N2 x rows and the x-extent y columns, and the real V(r)
-    multiply (2 flops per point)."""
+    """Flops of the pruned plane pass per transformed band and z plane: inverse
+    and forward transforms of the N2 x rows and the x-extent y columns, and the
+    real V(r) multiply (2 flops per point)."""
     n1, n2, ext = shape["n1"], shape["n2"], shape["ext"]
     return 2.0 * (n2 * fft_flops(n1) + ext * fft_flops(n2)) + 2.0 * n1 * n2
 
 
+def transforms(shape, nb):
+    """Complex 3D transforms per launch of nb bands (Gamma: one per band pair)."""
+    return (nb + 1) // 2 if shape.get("gamma") else nb
+
+
 def algorithmic(stage, shape, prec, nb):
-    """Algorithmic bytes (stick stages), flops (plane pass, GEMM stages) of one
-    launch of nb bands, with the resource that bounds it."""
+    """Algorithmic amount of one launch of nb bands with the resource that
+    bounds it: bytes for the stick passes, flops for the GEMMs.  The plane
+    pass (k2_plane) is priced by its HBM bytes; its transform flops are
+    reported beside them (plane_flops)."""
     npw, nst, nkb, n1, n2, n3 = (shape[k] for k in ("npw", "nst", "nkb", "n1", "n2", "n3"))
     c = 16 if prec == 0 else 8
     nfft = n1 * n2 * n3
-    if stage == "k1_scatter_zinv":   # read psi (complex128), write sticks (+ FP32 psi copy)
+    nt = transforms(shape, nb)
+    gam = bool(shape.get("gamma"))
+    npw_fft = 2 * npw - 1 if gam else npw
+    if stage == "k1_scatter_zinv":
+        # read psi (complex128) and the box map, write the sticks (+ the FP32
+        # psi copy the single-precision beta^H psi reads, complex k only)
+        if gam:
+            return "hbm", nb * 16 * npw + nt * (4 * npw_fft + c * nst * n3)
         return "hbm", nb * (16 * npw + c * nst * n3 + 4 * npw + (8 * npw if prec else 0))
-    if stage == "k2_plane":          # transform flops; its bytes: plane_bytes()
-        return "alu", nb * n3 * plane_flops(shape)
-    if stage == "k3_zfwd_gather":    # read sticks, psi, |k+G|^2, write H psi
+    if stage == "k2_plane":
+        return "hbm", plane_bytes(shape, prec, nb)
+    if stage == "k3_zfwd_gather":
+        if gam:
+            # K3 to the full-sphere pair buffer, then the unpack: read the buffer
+            # at G and -G, psi, |G|^2; write H psi
+            return "hbm", (nt * (c * nst * n3 + 4 * npw_fft + 2 * 16 * npw_fft) +
+                           nb * 2 * 16 * npw + 8 * npw)
         return "hbm", nb * (c * nst * n3 + 16 * npw + 16 * npw + 4 * npw) + 8 * npw
-    if stage == "calbec_gemm":
-        return "mfma", 8.0 * nb * nkb * npw
-    if stage == "addnl_gemm":
-        return "mfma", 8.0 * nb * nkb * npw
+    if stage in ("calbec_gemm", "addnl_gemm"):
+        # complex: 8 flops per complex multiply-add; Gamma: real products over
+        # the half sphere, 2 x (2 flops) per stored coefficient
+        return "mfma", (4.0 if gam else 8.0) * nb * nkb * npw
     if stage == "dscale":
         return "hbm", nb * nkb * c * 2
     ext = shape["ext"]
@@ -86,16 +115,14 @@ def algorithmic(stage, shape, prec, nb):
     raise KeyError(stage)
 
 
-DENSITY_BSUB = 16   # bands per density subgroup (library constant)
-
-
 def plane_bytes(shape, prec, nb):
     """K2 algorithmic HBM bytes: read + write the sticks, V once per launch."""
     c = 16 if prec == 0 else 8
-    return nb * 2 * c * shape["nst"] * shape["n3"] + (c // 2) * shape["n1"] * shape["n2"] * shape["n3"]
+    return (transforms(shape, nb) * 2 * c * shape["nst"] * shape["n3"] +
+            (c // 2) * shape["n1"] * shape["n2"] * shape["n3"])
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c2_hbm_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c5_gamma_hbm_traffic.json")
 
 
 def kernel_source_hash():
@@ -110,12 +137,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel, prec):
+def stored_traffic(kernel, prec, path=TRAFFIC_FILE):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE runs (scaled by the copy-kernel calibration), or None if absent
     or taken on other kernel sources."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("source_hash") != kernel_source_hash():
@@ -160,11 +187,14 @@ def time_projectors(q, torch, cell, reps=5):
     return out
 
 
-def time_apply(q, torch, cell, prec, nb, steps, warmup):
+def time_apply(q, torch, cell, prec, nb, steps, warmup, block=None, projgen=None):
     """Timed steps without instrumentation (the reported rate), then the same
     number of steps with per-stage HIP events (the kernel breakdown)."""
-    ctx = q.Context.from_cell(cell, precision=prec, block=nb)
-    psi = torch.from_numpy(__import__("cellgen").make_psi0(cell.npw, nb, seed=10502)).cuda()
+    import cellgen
+    ctx = q.Context.from_cell(cell, precision=prec, block=block or nb, projgen=projgen)
+    psi = torch.from_numpy(cellgen.make_psi0(cell.npw, nb, seed=10502)).cuda()
+    if getattr(cell, "gamma", False):
+        psi[:, 0].imag.zero_()   # real wavefunctions: psi(G = 0) real
     out = torch.empty_like(psi)
     for _ in range(warmup):
         ctx.apply_h(psi, out=out)
@@ -180,14 +210,37 @@ def time_apply(q, torch, cell, prec, nb, steps, warmup):
     stages = ctx.stage_times()
     ctx.profile(False)
     shape = ctx.info()
+    shape["gamma"] = bool(getattr(cell, "gamma", False))
     ctx.close()
+    del psi, out
+    torch.cuda.empty_cache()
     return dt, stages, shape
 
 
+def hpsi_leg(q, torch, cell, nb, steps, warmup, block=None, projgen=None, label=""):
+    """Both precision forms of H|psi> on one cell: rate, per-kernel rooflines."""
+    res = {}
+    for prec in (q.QEH_MIXED, q.QEH_FP64):
+        dt, stages, shape = time_apply(q, torch, cell, prec, nb, steps, warmup, block, projgen)
+        blk = shape["block"]
+        best, per = roofline_for(stages, shape, prec, blk)
+        name = "mixed" if prec else "fp64"
+        res[name] = dict(value=nb * steps / dt, unit="band-applies/s",
+                         ms_per_step=dt / steps * 1e3,
+                         fft_pts_bands_per_s=nb * steps / dt * cell.nfft,
+                         dominant_kernel=best, kernels=per)
+        print("# %s %s: %.3f ms/step, %.4g band-applies/s; kernels: %s" % (
+            label, name, dt / steps * 1e3, nb * steps / dt,
+            ", ".join("%s %.1f us (%.2f of %s peak)" % (k, v["avg_us"], v["frac"], v["bound"])
+                      for k, v in per.items())), file=sys.stderr, flush=True)
+    res["shape"] = shape
+    return res
+
+
 def time_gamma(q, torch, nb, steps, warmup):
-    """The benchmark's 64-atom cell moved to k = 0: H|psi> with complex
-    wavefunctions over the full sphere against the Gamma-point path (real
-    wavefunctions over half the sphere, two bands per complex FFT)."""
+    """The 64-atom cell moved to k = 0: H|psi> with complex wavefunctions over
+    the full sphere against the Gamma-point path (real wavefunctions over half
+    the sphere, two bands per complex FFT)."""
     import cellgen
     full = cellgen.make_cell("c2", kfrac=(0.0, 0.0, 0.0))
     half = cellgen.gamma_half(full)
@@ -205,37 +258,58 @@ def time_gamma(q, torch, nb, steps, warmup):
     return out
 
 
-def davidson_gamma(q, torch, name="c3"):
-    """Block Davidson on a Gamma-point cell on the Gamma path, projectors built
-    on the device: the 256-atom cell (135^3 box, 512 bands, H in blocks of 64)
-    or the 512-atom cell (160x160x168, 1024 bands in blocks of 128).  Time to
-    the converged eigenvalues in the mixed and FP64 forms, and their largest
-    difference."""
+def golden_eigs(name):
+    """Stored FP64 oracle eigenvalues of a named cell (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "%s_eigs.txt" % name)
+    if not os.path.exists(path):
+        return None
+    return np.loadtxt(path)
+
+
+def davidson_leg(q, torch, name):
+    """Block Davidson to converged eigenvalues on a named cell.  The 64-atom
+    cell runs at its k-point (complex, 128 bands, basis up to 512 vectors); the
+    256- and 512-atom Gamma cells run on the Gamma path with projectors built on
+    the device (512 bands in launches of 64; 1024 in launches of 128).  Forms:
+    mixed; FP64 to the mixed form's residual threshold (1e-5 Ry, equal
+    accuracy); FP64 to 1e-8 Ry.  Eigenvalues are held to the stored FP64 oracle
+    values (the lowest ones the oracle solved for)."""
     import cellgen
-    full = cellgen.make_cell(name, with_beta=False)
-    pg = cellgen.projgen_tables(full)
-    half = cellgen.gamma_half(full)
+    if name == "c2":
+        cell = cellgen.make_cell("c2")
+        pg, nvecx = None, 4 * cell.nbnd
+        full = cell
+    else:
+        full = cellgen.make_cell(name, with_beta=False)
+        pg = cellgen.projgen_tables(full)
+        cell, nvecx = cellgen.gamma_half(full), 0
     nb = full.nbnd
-    psi0 = cellgen.make_psi0(half.npw, nb, seed=10502)
-    res, eigs = {}, {}
-    for prec in (q.QEH_MIXED, q.QEH_FP64):
-        ctx = q.Context.from_cell(half, precision=prec, block=full.block, projgen=pg)
+    psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
+    gold = golden_eigs(name)
+    res = {}
+    for label, prec, rtol in (("mixed", q.QEH_MIXED, 1e-8), ("fp64_1e-5", q.QEH_FP64, 1e-5),
+                              ("fp64_1e-8", q.QEH_FP64, 1e-8)):
+        ctx = q.Context.from_cell(cell, precision=prec, block=full.block, projgen=pg)
         p = torch.from_numpy(psi0).cuda()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        eig, info = ctx.davidson(p, rtol=1e-8, allow_notconv=True)
+        eig, info = ctx.davidson(p, nvecx=nvecx, rtol=rtol, allow_notconv=True)
         torch.cuda.synchronize()
-        name = "mixed" if prec else "fp64"
-        eigs[name] = np.sort(eig)
-        res[name] = dict(seconds=time.perf_counter() - t0, status=info["status"],
-                         iters=info["iters"], band_applies=info["band_applies"],
-                         t_hpsi=info["t_hpsi"], t_subspace=info["t_subspace"],
-                         resid_max=info["resid_max"])
+        eig = np.sort(eig)
+        r = dict(seconds=time.perf_counter() - t0, status=info["status"], iters=info["iters"],
+                 band_applies=info["band_applies"], t_hpsi=info["t_hpsi"],
+                 t_subspace=info["t_subspace"], resid_max=info["resid_max"],
+                 eig_min=float(eig[0]), eig_max=float(eig[-1]))
+        if gold is not None:
+            m = min(len(gold), nb)
+            r["max_err_vs_oracle_Ry"] = float(np.abs(eig[:m] - gold[:m]).max())
+            r["oracle_bands_compared"] = m
+        res[label] = r
+        print("# davidson %s %s: %s" % (name, label, json.dumps(r)), file=sys.stderr, flush=True)
         ctx.close()
         del p
         torch.cuda.empty_cache()
-    res["max_eig_diff_mixed_vs_fp64_Ry"] = float(np.abs(eigs["mixed"] - eigs["fp64"]).max())
-    res["npw_stored"], res["bands"] = half.npw, nb
+    res["npw_stored"], res["bands"], res["gamma"] = cell.npw, nb, name != "c2"
     return res
 
 
@@ -268,6 +342,7 @@ def time_density(q, torch, cell, prec, nb, steps, warmup):
 
 
 def roofline_for(stages, shape, prec, nb):
+    """Per-kernel achieved rate against its bound's peak; nb = bands per launch."""
     best = None
     per = {}
     for name, (ms, n) in stages.items():
@@ -278,50 +353,72 @@ def roofline_for(stages, shape, prec, nb):
         if bound == "hbm":
             achieved = amount / avg_s / 1e9
             peak, unit = HBM_PEAK_GBS, "GB/s"
-        elif bound == "alu":
-            achieved = amount / avg_s / 1e12
-            peak, unit = (VALU_F64_TFLOPS if prec == 0 else VALU_F32_TFLOPS), "TFLOP/s"
         else:
             achieved = amount / avg_s / 1e12
             peak, unit = (MFMA_F64_TFLOPS if prec == 0 else MFMA_F32_TFLOPS), "TFLOP/s"
         per[name] = dict(avg_us=avg_s * 1e6, launches=n, bound=bound, achieved=achieved,
-                         peak=peak, unit=unit, frac=achieved / peak)
-        if name == "k2_plane":   # its HBM side, for the ridge between the two bounds
-            gbs = plane_bytes(shape, prec, nb) / avg_s / 1e9
-            per[name].update(hbm_GBs=gbs, hbm_frac=gbs / HBM_PEAK_GBS)
-            if prec != 0:
-                # the FP32 vector peak counts packed (two-wide) FP32 issue, which
-                # every HIP source here is compiled without; one-wide issue peaks
-                # at the FP64 figure
-                per[name].update(peak_one_wide_fp32=VALU_F64_TFLOPS,
-                                 frac_one_wide_fp32=achieved / VALU_F64_TFLOPS)
+                         peak=peak, unit=unit, frac=achieved / peak, amount_per_launch=amount)
+        if name == "k2_plane":
+            # the plane pass also does the transform arithmetic: its flops against
+            # the one-wide vector peak (packed FP32 is not emitted)
+            tf = transforms(shape, nb) * shape["n3"] * plane_flops(shape) / avg_s / 1e12
+            pk = VALU_F64_TFLOPS if prec == 0 else VALU_F32_ONE_WIDE_TFLOPS
+            per[name].update(alu_TFLOPs=tf, alu_peak_one_wide=pk, alu_frac=tf / pk)
         if best is None or ms > stages[best][0]:
             best = name
     return best, per
 
 
-def cpu_baseline(cell, budget_s=12.0):
+def host_cpu():
+    """Core counts and CPU model of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        r = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10)
+        for ln in r.stdout.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = os.cpu_count()
+    return dict(cpu_count=os.cpu_count(), affinity=aff, model=model)
+
+
+def cpu_baseline(cell, budget_s=15.0):
+    """The FP64 oracle's H|psi> on the full complex sphere of the headline cell,
+    one band at a time, until budget_s has passed (at least one band)."""
     import oracle
     import cellgen
-    psi = cellgen.make_psi0(cell.npw, 4, seed=10502)
-    oracle.apply_h(cell, psi[:1])          # warm the DFT matrix cache
+    hc = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", hc["affinity"]))
+    psi = cellgen.make_psi0(cell.npw, 8, seed=10502)
     done = 0
     t0 = time.perf_counter()
-    while True:
-        oracle.apply_h(cell, psi)
-        done += psi.shape[0]
+    while done < psi.shape[0]:
+        oracle.apply_h(cell, psi[done:done + 1])
+        done += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return dict(value=done / dt, unit="band-applies/s", cores=min(cores, threads),
-                kind="oracle",
-                sample="FP64 oracle apply_h (dense per-axis DFT) on %d bands of the same "
-                       "cell, %.1f s" % (done, dt))
+    return dict(value=done / dt, unit="band-applies/s", cores=min(hc["affinity"], threads),
+                kind="oracle", cpu_model=hc["model"], cpu_count=hc["cpu_count"],
+                affinity=hc["affinity"],
+                sample="FP64 oracle apply_h (dense per-axis DFT, host-built projectors) on "
+                       "%d band(s) of the 512-atom cell over its full complex sphere "
+                       "(%d plane waves), %.1f s; projector construction untimed"
+                       % (done, cell.npw, dt))
 
 
 def _make_request(r, device_beta=True):
@@ -348,8 +445,10 @@ def make_trace(duration, rate, seed=2104, device_beta=True):
     trace = [r for r in cellgen.served_trace(int(rate * duration * 2) + 10, rate=rate, seed=seed)
              if r["t_arrive"] <= duration]
     t_gen = time.perf_counter()
+    # fork: this process has not touched the GPU yet, and a fork pool leaves no
+    # resource-tracker process behind
     with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 4),
-                                mp_context=mp.get_context("spawn")) as ex:
+                                mp_context=mp.get_context("fork")) as ex:
         reqs = list(ex.map(functools.partial(_make_request, device_beta=device_beta), trace,
                            chunksize=4))
     return trace, reqs, time.perf_counter() - t_gen
@@ -452,20 +551,13 @@ def run_serve_child(child, timeout_s=300.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--davidson", action="store_true")
-    ap.add_argument("--davidson-c3", action="store_true",
-                    help="also run Davidson on the 256-atom Gamma cell (512 bands)")
-    ap.add_argument("--davidson-c5", action="store_true",
-                    help="also run Davidson on the 512-atom Gamma cell (1024 bands)")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-density", action="store_true",
-                    help="skip the charge density leg (128 bands, both forms)")
-    ap.add_argument("--no-gamma", action="store_true",
-                    help="skip the Gamma-point leg (the 64-atom cell at k = 0)")
-    ap.add_argument("--no-projectors", action="store_true",
-                    help="skip the projector-generation leg")
+    ap.add_argument("--no-davidson", action="store_true",
+                    help="skip the Davidson time-to-solution legs")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the complex-k = 0 and 64-atom legs (density, projectors, Gamma)")
     ap.add_argument("--serve", type=float, default=5.0,
                     help="seconds of the served Poisson trace to replay (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -486,15 +578,14 @@ def main():
         return
     # The served-trace leg runs in a child process, started here before this
     # process touches the GPU: it builds the trace on the host, then waits for
-    # the parent's go (after the timed H|psi> and density work) before it
-    # initialises its own device context.  A failure there cannot take down this
-    # benchmark line.
+    # the parent's go (after the timed work) before it initialises its own
+    # device context.  A failure there cannot take down this benchmark line.
     child = None
     if a.serve > 0:
         import subprocess
         env = dict(os.environ)
-        # one hardware queue per few job streams, so that a long dense eigensolve
-        # on one stream does not hold up the jobs sharing its queue (HIP reads
+        # one hardware queue per few job streams, so that one job's dense
+        # eigensolve does not hold up the jobs sharing its queue (HIP reads
         # this at initialisation; <= 32)
         env.setdefault("GPU_MAX_HW_QUEUES", "16")
         child = subprocess.Popen(
@@ -509,89 +600,80 @@ def main():
     import cellgen
     import paper_2104_10502_amd as q
 
-    cell = cellgen.make_cell("c2")
-    nb = 128
-    nfft = cell.nfft
-    res = {}
-    for prec in (q.QEH_MIXED, q.QEH_FP64):
-        dt, stages, shape = time_apply(q, torch, cell, prec, nb, a.steps, a.warmup)
-        ms = dt / a.steps * 1e3
-        rate = nb * a.steps / dt
-        best, per = roofline_for(stages, shape, prec, nb)
-        res[prec] = dict(ms=ms, rate=rate, best=best, per=per, shape=shape)
-        print("# precision %s: %.3f ms/step, %.4g band-applies/s; kernels: %s" % (
-            "mixed" if prec else "fp64", ms, rate,
-            ", ".join("%s %.1f us (%.2f of %s peak)" % (k, v["avg_us"], v["frac"], v["bound"])
-                      for k, v in per.items())), file=sys.stderr, flush=True)
-    mixed, f64 = res[q.QEH_MIXED], res[q.QEH_FP64]
-    b = mixed["per"][mixed["best"]]
+    # ---- headline: the 512-atom Gamma cell, 1024 bands in launches of 128
+    c5full = cellgen.make_cell("c5", with_beta=False)
+    pg5 = cellgen.projgen_tables(c5full)
+    c5 = cellgen.gamma_half(c5full)
+    nb = c5full.nbnd
+    head = hpsi_leg(q, torch, c5, nb, a.steps, a.warmup, block=c5full.block, projgen=pg5,
+                    label="512-atom Gamma")
+    mixed, f64 = head["mixed"], head["fp64"]
+    b = mixed["kernels"][mixed["dominant_kernel"]]
+    shape = head["shape"]
     out = {
         "metric": METRIC,
-        "value": mixed["rate"],
+        "value": mixed["value"],
         "unit": "band-applies/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": mixed["ms"],
+        "ms_per_step": mixed["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 (FFTs, V multiply, projector GEMMs) + f64 (psi, kinetic)",
         "data": "synthetic",
-        "config": {"workload": "64-atom diamond-like supercell a=20.52 bohr, k=(1/4,1/4,1/4), "
-                               "ecutwfc 30 Ry, 72^3 box, 23976 PW, 512 projectors, 128 bands",
-                   "bands_per_step": nb, "fft_points": nfft, "npw": cell.npw, "nkb": cell.nkb},
-        "fft_pts_bands_per_s": mixed["rate"] * nfft,
-        "fp64_form": {"value": f64["rate"], "unit": "band-applies/s", "ms_per_step": f64["ms"],
-                      "fft_pts_bands_per_s": f64["rate"] * nfft,
-                      "kernels": f64["per"]},
-        "kernels": mixed["per"],
-        "roofline": {"kernel": mixed["best"], "bound": b["bound"], "achieved": b["achieved"],
-                     "peak": b["peak"], "unit": b["unit"], "frac": b["frac"],
-                     "traffic": stored_traffic(mixed["best"], q.QEH_MIXED)},
+        "config": {"workload": "512-atom orthorhombic cell 40x40x42 bohr (diamond sites), "
+                               "Gamma point on the real-wavefunction path, ecutwfc 30 Ry, "
+                               "160x160x168 box, 6144 s/p/d projectors, 1024 bands per step "
+                               "in launches of 128",
+                   "bands_per_step": nb, "bands_per_launch": shape["block"],
+                   "fft_points": c5full.nfft, "npw_full_sphere": c5full.npw,
+                   "npw_stored": c5.npw, "nkb": c5full.nkb,
+                   "projectors": "built on the device from radial tables"},
+        "fft_pts_bands_per_s": mixed["fft_pts_bands_per_s"],
+        "fp64_form": {k: f64[k] for k in ("value", "unit", "ms_per_step", "fft_pts_bands_per_s",
+                                          "dominant_kernel", "kernels")},
+        "mixed_over_fp64": mixed["value"] / f64["value"],
+        "kernels": mixed["kernels"],
+        "roofline": {"kernel": mixed["dominant_kernel"], "bound": b["bound"],
+                     "achieved": b["achieved"], "peak": b["peak"], "unit": b["unit"],
+                     "frac": b["frac"],
+                     "traffic": stored_traffic(mixed["dominant_kernel"], q.QEH_MIXED)},
+        "roofline_fft_path": {k: {kk: mixed["kernels"][k][kk] for kk in
+                                  ("avg_us", "achieved", "peak", "unit", "frac")}
+                              for k in ("k1_scatter_zinv", "k2_plane", "k3_zfwd_gather")
+                              if k in mixed["kernels"]},
     }
-    if not a.no_density:
+    print("# headline: %s" % json.dumps({k: out[k] for k in ("value", "ms_per_step", "roofline")}),
+          file=sys.stderr, flush=True)
+    if not a.no_extras:
+        # the same cell as a general complex k = 0 (full sphere), fewer steps
+        ext = hpsi_leg(q, torch, c5full, nb, max(2, a.steps // 4), 1, block=c5full.block,
+                       projgen=pg5, label="512-atom complex k=0")
+        out["c5_complex_k0"] = {k: {kk: v[kk] for kk in ("value", "ms_per_step", "kernels")}
+                                for k, v in ext.items() if k in ("mixed", "fp64")}
+        out["c5_complex_k0"]["gamma_speedup_mixed"] = mixed["value"] / ext["mixed"]["value"]
+        # the 64-atom cell at its k-point
+        c2 = cellgen.make_cell("c2")
+        r2 = hpsi_leg(q, torch, c2, 128, 20, 3, label="64-atom")
+        out["c2"] = {k: {kk: v[kk] for kk in ("value", "ms_per_step", "fft_pts_bands_per_s",
+                                                "kernels")}
+                     for k, v in r2.items() if k in ("mixed", "fp64")}
         dens = {}
         for prec in (q.QEH_MIXED, q.QEH_FP64):
-            dt, stages, shape, integral = time_density(q, torch, cell, prec, nb, a.steps,
-                                                       a.warmup)
-            _, per = roofline_for(stages, shape, prec, nb)
+            dt, stages, shp, integral = time_density(q, torch, c2, prec, 128, 20, 3)
+            _, per = roofline_for(stages, shp, prec, 128)
             dens["mixed" if prec else "fp64"] = dict(
-                ms_per_call=dt / a.steps * 1e3, band_densities_per_s=nb * a.steps / dt,
-                integral=integral, occupation_sum=2.0 * nb, kernels=per)
-            print("# density %s: %.3f ms/call; kernels: %s" % (
-                "mixed" if prec else "fp64", dt / a.steps * 1e3,
-                ", ".join("%s %.1f us (%.2f of %s peak)" % (k, v["avg_us"], v["frac"],
-                                                            v["bound"])
-                          for k, v in per.items())), file=sys.stderr, flush=True)
-        out["density"] = dens
-    if not a.no_gamma:
-        out["gamma_point"] = time_gamma(q, torch, nb, a.steps, a.warmup)
-        print("# gamma point: %s" % json.dumps(out["gamma_point"]), file=sys.stderr, flush=True)
-    if not a.no_projectors:
-        out["projectors"] = time_projectors(q, torch, cell)
-        print("# projectors: %s" % json.dumps(out["projectors"]), file=sys.stderr, flush=True)
-    if a.davidson:
-        psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
-        dav = {}
-        for prec in (q.QEH_MIXED, q.QEH_FP64):
-            ctx = q.Context.from_cell(cell, precision=prec, block=nb)
-            p = torch.from_numpy(psi0).cuda()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            eig, info = ctx.davidson(p, nvecx=4 * nb, rtol=1e-8)
-            torch.cuda.synchronize()
-            dav["mixed" if prec else "fp64"] = dict(
-                seconds=time.perf_counter() - t0, iters=info["iters"],
-                band_applies=info["band_applies"], t_hpsi=info["t_hpsi"],
-                t_subspace=info["t_subspace"], resid_max=info["resid_max"],
-                eig_min=float(eig[0]), eig_max=float(eig[-1]))
-            ctx.close()
-        out["davidson"] = dav
-    for name in (["c3"] if a.davidson_c3 else []) + (["c5"] if a.davidson_c5 else []):
-        key = "davidson_%s_gamma" % name
-        out[key] = davidson_gamma(q, torch, name)
-        print("# %s: %s" % (key, json.dumps(out[key])), file=sys.stderr, flush=True)
+                ms_per_call=dt / 20 * 1e3, band_densities_per_s=128 * 20 / dt,
+                integral=integral, occupation_sum=2.0 * 128, kernels=per)
+        out["c2"]["density"] = dens
+        out["c2"]["gamma_point"] = time_gamma(q, torch, 128, 20, 3)
+        out["c2"]["projectors"] = time_projectors(q, torch, c2)
+        print("# 64-atom extras done", file=sys.stderr, flush=True)
+    if not a.no_davidson:
+        for name in ("c2", "c3", "c5"):
+            out["davidson_%s" % name] = davidson_leg(q, torch, name)
     if a.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -603,7 +685,9 @@ def main():
         out["serve"] = run_serve_child(child)
         print("# serve: %s" % json.dumps(out["serve"]), file=sys.stderr, flush=True)
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cell)
+        print("# cpu baseline: building the host projectors of the 512-atom cell",
+              file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cellgen.make_cell("c5"))
     print(json.dumps(out))
 
 

@@ -241,6 +241,12 @@ class Server:
     def submit(self, cells, psi0s, nb, precision=QEH_MIXED, block=None, nvecx=0, rtol=1e-8,
                maxiter=0):
         """cells: list of cell-like objects (one per k-point); psi0s: list of (nb, npw)."""
+        if len(psi0s) != len(cells):
+            raise ValueError("submit: %d cells but %d start-vector blocks" % (len(cells), len(psi0s)))
+        for k, (c, p) in enumerate(zip(cells, psi0s)):
+            if np.shape(p) != (int(nb), int(len(c.miller))):
+                raise ValueError("submit: k-point %d start vectors have shape %s, expected (%d, %d)"
+                                 % (k, np.shape(p), int(nb), len(c.miller)))
         keep = []
         arr = (QehCell * len(cells))()
         for i, c in enumerate(cells):

@@ -358,7 +358,14 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
     set_error("rocblas_create_handle failed");
     return QEH_ERR_DEVICE;
   }
-  rocblas_set_stream(rh_, c->stream);
+  // library reductions with atomics sum in an order that depends on timing:
+  // forbid them, so that a solve gives the same bits whatever else runs
+  if (rocblas_set_stream(rh_, c->stream) != rocblas_status_success ||
+      rocblas_set_atomics_mode(rh_, rocblas_atomics_not_allowed) != rocblas_status_success) {
+    release();
+    set_error("rocblas_set_stream / rocblas_set_atomics_mode failed");
+    return QEH_ERR_DEVICE;
+  }
   if (rocblas_set_workspace(rh_, w + L_.solver, std::max<size_t>(L_.solver_bytes, 256)) !=
       rocblas_status_success) {
     release();

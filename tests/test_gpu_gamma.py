@@ -229,5 +229,6 @@ def test_gamma_davidson_64_bands(prec, tol):
     p = torch.from_numpy(cellgen.make_psi0(h.npw, 64, seed=5)).cuda()
     eig, info = ctx.davidson(p, rtol=1e-8)
     assert info["status"] == 0
-    # the top of the window may cut a degenerate shell: compare below it
-    assert np.abs(np.sort(eig)[:56] - ref[:56]).max() < tol
+    # sorted eigenvalues are unique even where the window cuts a degenerate
+    # shell: all 64 are compared
+    assert np.abs(np.sort(eig) - ref).max() < tol
