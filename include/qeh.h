@@ -210,6 +210,24 @@ qeh_status qeh_beta_plan(const qeh_cell *cell, size_t *work_bytes);
 qeh_status qeh_beta_generate(const qeh_cell *cell, int precision, void *beta, long ldb,
                              void *work, size_t work_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * projectors as qeh_beta_generate (bitwise), with the generator's inputs
+ * staged in a static device array of QEH_BETA_STATIC_BYTES per GPU instead
+ * of a caller workspace.  The call allocates nothing (no hipMalloc, no
+ * library allocation); the array is created with the library's code object on
+ * each GPU it runs on and kept until the process ends.  The inputs it stages
+ * are 24 npw + 40 nat + 4 (nsp + 1 + channels) + 8 channels nq bytes, each
+ * field rounded up to 256 (qeh_beta_plan gives the figure): cells needing
+ * more get QEH_ERR_NOMEM and must use qeh_beta_generate.  beta (DEVICE),
+ * ldb, precision and hip_stream as for qeh_beta_generate (the array used is
+ * the one on the stream's device); returns after the work has finished.
+ * All calls on one GPU share its array: calls that overlap in time on the
+ * same GPU (two host threads) race and must be serialised by the caller. */
+#define QEH_BETA_STATIC_BYTES (8u << 20)
+qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *beta, long ldb,
+                                    void *hip_stream);
+
 /* Davidson options: nvecx = maximum basis size (>= 2 nb; 0 = 2 nb),
  * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
  * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single

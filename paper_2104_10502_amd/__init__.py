@@ -92,6 +92,8 @@ _SIGS = {
     "qeh_beta_plan": ([ctypes.POINTER(QehCell), _sz_p], ctypes.c_int),
     "qeh_beta_generate": ([ctypes.POINTER(QehCell), ctypes.c_int, _vp, ctypes.c_long, _vp,
                            ctypes.c_size_t, _vp], ctypes.c_int),
+    "qeh_beta_generate_static": ([ctypes.POINTER(QehCell), ctypes.c_int, _vp, ctypes.c_long,
+                                  _vp], ctypes.c_int),
     "qeh_density": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, _vp, _vp, ctypes.c_size_t],
                     ctypes.c_int),
     "qeh_ctx_profile": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -222,6 +224,35 @@ def generate_beta(lattice, kpt, miller, nproj, projgen, precision=QEH_FP64, devi
     _check(_lib.qeh_beta_generate(ctypes.byref(c), int(precision), _vp(out.data_ptr()), npw,
                                   _vp(work.data_ptr()), int(work.numel()), _stream_ptr(st)),
            "qeh_beta_generate")
+    return out
+
+
+BETA_STATIC_BYTES = 8 << 20   # QEH_BETA_STATIC_BYTES
+
+
+def generate_beta_static(lattice, kpt, miller, nproj, projgen, precision=QEH_FP64,
+                         out=None, device=None, stream=None):
+    """qeh_beta_generate_static: the projectors of ``projgen`` written into
+    ``out`` (an existing (nkb, >= npw) complex128 / complex64 CUDA tensor, or a
+    new one) with the library's static staging array instead of a workspace."""
+    torch = _torch()
+    dev = torch.device(device if device is not None else "cuda")
+    keep = []
+    miller = np.ascontiguousarray(miller, dtype=np.int32)
+    nproj = np.ascontiguousarray(nproj, dtype=np.int32)
+    c = _cell_struct(lattice, (1, 1, 1), kpt, miller, np.zeros(1), nproj, None,
+                     np.zeros(0, dtype=np.complex128), precision, 1, keep, projgen=projgen)
+    nkb, npw = int(nproj.sum()), int(miller.shape[0])
+    dt = torch.complex128 if precision == QEH_FP64 else torch.complex64
+    if out is None:
+        out = torch.empty((nkb, npw), dtype=dt, device=dev)
+    if out.dtype != dt or out.dim() != 2 or out.shape[0] != nkb or out.shape[1] < npw or \
+            out.stride(1) != 1:
+        raise ValueError("out must be (nkb, >= npw) %s with unit stride" % dt)
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(_lib.qeh_beta_generate_static(ctypes.byref(c), int(precision), _vp(out.data_ptr()),
+                                         out.stride(0), _stream_ptr(st)),
+           "qeh_beta_generate_static")
     return out
 
 

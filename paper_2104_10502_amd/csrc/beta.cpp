@@ -232,4 +232,28 @@ qeh_status qeh_beta_generate(const qeh_cell *cell, int precision, void *beta, lo
                      reinterpret_cast<hipStream_t>(hip_stream), nullptr, nullptr);
 }
 
+qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *beta, long ldb,
+                                    void *hip_stream) {
+  const qeh_status st = check_sphere(cell);
+  if (st != QEH_OK) return st;
+  if (precision != QEH_FP64 && precision != QEH_MIXED)
+    return bad("precision must be QEH_FP64 or QEH_MIXED");
+  if (!beta) return bad("beta is null");
+  if (ldb < cell->npw) return bad("ldb < npw");
+  const size_t need = projgen_layout(cell).total;
+  if (need > (size_t)QEH_BETA_STATIC_BYTES) {
+    set_error("qeh_beta_generate_static: the generator inputs need " + std::to_string(need) +
+              " bytes of staging, the static array holds " +
+              std::to_string((size_t)QEH_BETA_STATIC_BYTES) + " (use qeh_beta_generate)");
+    return QEH_ERR_NOMEM;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  char *work = nullptr;
+  const hipError_t e = beta_static_scratch(s, &work);
+  if (e != hipSuccess) return hip_fail(e, "static staging array address");
+  // every staged field is written before the generator reads it: nothing in
+  // the array needs clearing between calls
+  return projgen_run(cell, precision == QEH_FP64, beta, ldb, work, s, nullptr, nullptr);
+}
+
 }  // extern "C"

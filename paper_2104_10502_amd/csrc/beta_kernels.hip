@@ -13,6 +13,9 @@
 // computed in double; the single-precision form rounds at the store.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "qeh_internal.h"
 
 namespace qeh {
@@ -189,6 +192,38 @@ hipError_t launch_nl_diag(bool f64, const void *beta, long ldb, int npw, int nat
     hipLaunchKernelGGL(nl_diag_kernel<float2>, grid, dim3(64 * kDW), 0, s,
                        static_cast<const float2 *>(beta), ldb, npw, nat, atoms, dmat, hdiag);
   return hipGetLastError();
+}
+
+// Staging array of qeh_beta_generate_static (callers that cannot allocate):
+// one per GPU, alive until the process ends.  Host code never passes the name
+// itself to a kernel or a copy: it is a host-side stand-in, so each device's
+// address is looked up once (with that device current) and kept.
+static __device__ __align__(256) char scratch[QEH_BETA_STATIC_BYTES];
+
+hipError_t beta_static_scratch(hipStream_t s, char **out) {
+  static std::mutex mu;
+  static std::vector<char *> ptr;   // per device, from hipGetSymbolAddress
+  int dev = 0;
+  hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev >= (int)ptr.size()) ptr.resize(dev + 1, nullptr);
+  if (!ptr[dev]) {
+    int cur = 0;
+    e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<char *>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
 }
 
 }  // namespace qeh

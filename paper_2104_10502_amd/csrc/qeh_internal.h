@@ -201,6 +201,10 @@ hipError_t launch_beta_gen(bool f64, const double *q, int npw, int nat, const in
 hipError_t launch_nl_diag(bool f64, const void *beta, long ldb, int npw, int nat,
                           const int4 *atoms, const double2 *dmat, double *hdiag,
                           hipStream_t s);
+// Device address of the static staging array of qeh_beta_generate_static on
+// the device of stream s (the current device when s is null); looked up once
+// per device.
+hipError_t beta_static_scratch(hipStream_t s, char **out);
 
 // ---- complex GEMM launchers (gemm_kernels.hip) ----------------------------
 // C[m][n] (+)= sum_k opA(A[m][k]) opB(B(k,n)), complex, MFMA.
