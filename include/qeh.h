@@ -229,16 +229,37 @@ qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *b
                                     void *hip_stream);
 
 /* Davidson options: nvecx = maximum basis size (>= 2 nb; 0 = 2 nb),
- * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200).
- * In QEH_MIXED the residual threshold is max(rtol, 1e-5) since single
- * precision limits how small the residual can get; a band also counts as
- * converged there when its Ritz value moved by <= 1e-8 Ry in one iteration,
- * or when its residual has not dropped by 10% in 3 iterations while <= 10x
- * that threshold, or in 5 iterations while <= 100x it. */
+ * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200),
+ * subspace = solver of the reduced problem H_r y = eps S_r y:
+ *   QEH_SUBSPACE_AUTO (0): the library's own when nvecx <= 512, else rocSOLVER;
+ *   QEH_SUBSPACE_OWN (1): the library's own HIP solver (nvecx <= 512 only):
+ *     Cholesky, triangular solves, Householder tridiagonalisation, bisection
+ *     and inverse iteration, back-transformation; deterministic (fixed
+ *     summation orders), a few launches per iteration, no library calls;
+ *   QEH_SUBSPACE_ROCSOLVER (2): rocSOLVER potrf / trtri / heevd (syevd for
+ *     Gamma contexts) with the library's MFMA products around them.
+ * In QEH_MIXED the residual threshold is thr = max(rtol, 1e-5), since
+ * single precision limits how small the residual can get, and the solve runs
+ * in two phases when refine is set:
+ *   1. H applied in single precision (the context's form) until every band
+ *      has ||r|| <= thr or a residual that has not dropped by 10% in 3
+ *      iterations (the single-precision floor);
+ *   2. a restart from the Ritz vectors with H applied in FP64 through refine
+ *      (a QEH_FP64 context of the same cell: same Miller list, k, V,
+ *      projectors and D, on the same HIP stream, with the same npw, box,
+ *      projector count and Gamma flag) until every band has ||r|| <= thr,
+ *      that residual computed in FP64; the eigenvalue error is then the
+ *      FP64 form's at residual thr.
+ * Without refine the mixed form stops at phase 1's rules, with the floor
+ * accepted only while ||r|| <= 10 thr (3 iterations without a 10% drop) or
+ * <= 100 thr (5 iterations). */
+enum { QEH_SUBSPACE_AUTO = 0, QEH_SUBSPACE_OWN = 1, QEH_SUBSPACE_ROCSOLVER = 2 };
 typedef struct {
   int nvecx;
   double rtol;
   int maxiter;
+  int subspace;
+  qeh_ctx *refine;   /* QEH_MIXED solves only, may be NULL: see below */
 } qeh_dav_opts;
 
 typedef struct {
@@ -250,6 +271,8 @@ typedef struct {
   double t_total;         /* wall seconds                                    */
   double t_hpsi;          /* seconds in H application (device events)        */
   double t_subspace;      /* seconds in reductions + subspace eigensolve     */
+  int refine_iters;       /* of iters, those with H applied in FP64 through
+                             qeh_dav_opts.refine (QEH_MIXED)                  */
 } qeh_dav_info;
 
 /* Device workspace bytes for qeh_davidson with nb bands. */
@@ -264,6 +287,28 @@ qeh_status qeh_davidson_plan(const qeh_ctx *ctx, int nb, const qeh_dav_opts *opt
 qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
                         double *eig, const qeh_dav_opts *opts, void *work,
                         size_t work_bytes, qeh_dav_info *info);
+
+/* The dense solver of the Rayleigh-Ritz step on its own (the generalized
+ * Hermitian eigenproblem the paper solves with a dense GPU solver, section
+ * "Evolution of the GPU-enabled version"): the nb lowest eigenpairs of
+ * H y = eps S y, S positive definite, 1 <= nb <= n <= 512.  H, S: DEVICE
+ * complex n x n column-major with leading dimension ld >= n (Hermitian; only
+ * (X + X^H) / 2 is used).  eig: DEVICE, nb doubles, ascending.  Y: DEVICE
+ * complex n x nb column-major (ldy >= n), S-orthonormal eigenvectors
+ * (Y^H S Y = I).  work: DEVICE, qeh_subspace_plan bytes, 256-byte aligned.
+ * Runs on hip_stream (NULL = null stream) and returns after it finished.
+ * The kernels are qeh_davidson's own subspace path: Cholesky, two triangular
+ * solves for L^-1 H L^-H, Householder tridiagonalisation, bisection with
+ * twisted-factorisation eigenvectors (inverse iteration with Gram-Schmidt
+ * for numerically equal eigenvalues), back-transformation, a last triangular
+ * solve; fixed summation orders, so repeated calls give the same bits.
+ * Errors: QEH_ERR_INVALID (sizes, nulls), QEH_ERR_NOMEM (short or misaligned
+ * work), QEH_ERR_CHOLESKY (S not positive definite), QEH_ERR_NUMERIC
+ * (non-finite input). */
+qeh_status qeh_subspace_plan(int n, int nb, size_t *work_bytes);
+qeh_status qeh_subspace_eigh(int n, int nb, const double *H, const double *S, int ld,
+                             double *eig, double *Y, int ldy, void *work, size_t work_bytes,
+                             void *hip_stream);
 
 /* Diagonal of H over the context's plane waves (npw doubles, the cell's G
  * order): |k+G|^2 + the mean of V(r) + sum over atoms of

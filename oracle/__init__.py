@@ -16,7 +16,8 @@ exascale):
   GPU-ported kernels (section "Evolution of the GPU-enabled version").  The
   local part goes through the oracle's own dense per-axis DFT (``dft``), the
   exact definition of the operator that the pruned FFT path computes.
-* ``dense_h``: the same operator written out as a matrix for tiny cells.
+* ``dense_h``: the same operator written out as a matrix for tiny cells;
+  ``dense_eigs`` its lowest eigenvalues by LAPACK.
 * ``davidson``: the Davidson iterative diagonalisation (same section) with the
   Rayleigh-Ritz step solved as a Hermitian generalized eigenproblem, as the
   paper's dense-solver library does.
@@ -39,14 +40,14 @@ closed forms, invariants, brute force and library routines (see those files).
 """
 
 from .dft import dft_matrix, dft_axis, inv3, fwd3
-from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, vloc_coeffs,
-                          hdiag)
+from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, dense_eigs,
+                          vloc_coeffs, hdiag)
 from .davidson import davidson, rayleigh_ritz
 from .density import cell_volume, density, density_direct, psi_real_space
 from .beta import beta_projectors, radial_transform, real_harmonics, spherical_bessel
 from . import gamma
 
 __all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
-           "apply_h", "dense_h", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
+           "apply_h", "dense_h", "dense_eigs", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
            "cell_volume", "density", "density_direct", "psi_real_space", "beta_projectors",
            "radial_transform", "real_harmonics", "spherical_bessel", "gamma"]

@@ -104,6 +104,14 @@ def dense_h(cell) -> np.ndarray:
     return h
 
 
+def dense_eigs(cell, nb: int) -> np.ndarray:
+    """The nb lowest eigenvalues of the dense H of ``dense_h`` (ascending), by
+    LAPACK's Hermitian eigensolver (a library step: the definition written out
+    for cells small enough to hold H)."""
+    import scipy.linalg as sla
+    return sla.eigh(dense_h(cell), eigvals_only=True, subset_by_index=[0, nb - 1])
+
+
 def hdiag(cell) -> np.ndarray:
     """Diagonal of H (real): T_G + Vt[0] + sum_ij beta_i(G) D_ij conj(beta_j(G))."""
     v0 = float(np.mean(cell.vloc))

@@ -62,14 +62,15 @@ class QehCell(ctypes.Structure):
 
 
 class DavOpts(ctypes.Structure):
-    _fields_ = [("nvecx", ctypes.c_int), ("rtol", ctypes.c_double), ("maxiter", ctypes.c_int)]
+    _fields_ = [("nvecx", ctypes.c_int), ("rtol", ctypes.c_double), ("maxiter", ctypes.c_int),
+                ("subspace", ctypes.c_int), ("refine", ctypes.c_void_p)]
 
 
 class DavInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("notconv", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("band_applies", ctypes.c_long), ("resid_max", ctypes.c_double),
                 ("t_total", ctypes.c_double), ("t_hpsi", ctypes.c_double),
-                ("t_subspace", ctypes.c_double)]
+                ("t_subspace", ctypes.c_double), ("refine_iters", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -89,6 +90,9 @@ _SIGS = {
     "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
                       _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
     "qeh_density_plan": ([_vp, _sz_p], ctypes.c_int),
+    "qeh_subspace_plan": ([ctypes.c_int, ctypes.c_int, _sz_p], ctypes.c_int),
+    "qeh_subspace_eigh": ([ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp,
+                           ctypes.c_int, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
     "qeh_beta_plan": ([ctypes.POINTER(QehCell), _sz_p], ctypes.c_int),
     "qeh_beta_generate": ([ctypes.POINTER(QehCell), ctypes.c_int, _vp, ctypes.c_long, _vp,
                            ctypes.c_size_t, _vp], ctypes.c_int),
@@ -225,6 +229,35 @@ def generate_beta(lattice, kpt, miller, nproj, projgen, precision=QEH_FP64, devi
                                   _vp(work.data_ptr()), int(work.numel()), _stream_ptr(st)),
            "qeh_beta_generate")
     return out
+
+
+QEH_SUBSPACE_AUTO, QEH_SUBSPACE_OWN, QEH_SUBSPACE_ROCSOLVER = 0, 1, 2
+
+
+def subspace_eigh(h, s, nb, stream=None):
+    """qeh_subspace_eigh: the nb lowest eigenpairs of h y = eps s y for n x n
+    complex128 CUDA tensors (Hermitian h, positive definite s, n <= 512);
+    returns (eig float64 CUDA tensor (nb,), Y complex128 CUDA tensor (n, nb)),
+    Y column j the eigenvector of eig[j]."""
+    torch = _torch()
+    n = h.shape[0]
+    if h.shape != (n, n) or s.shape != (n, n) or h.dtype != torch.complex128 or \
+            s.dtype != torch.complex128 or h.device.type != "cuda" or s.device != h.device:
+        raise ValueError("h, s must be n x n complex128 CUDA tensors on one device")
+    # column-major storage: the transposes' rows are the matrices' columns
+    hc = h.t().contiguous()
+    sc = s.t().contiguous()
+    need = ctypes.c_size_t()
+    _check(_lib.qeh_subspace_plan(int(n), int(nb), ctypes.byref(need)), "qeh_subspace_plan")
+    work = torch.empty(max(int(need.value), 256), dtype=torch.uint8, device=h.device)
+    eig = torch.empty(nb, dtype=torch.float64, device=h.device)
+    yc = torch.empty((nb, n), dtype=torch.complex128, device=h.device)   # column-major n x nb
+    st = stream if stream is not None else torch.cuda.current_stream(h.device)
+    _check(_lib.qeh_subspace_eigh(int(n), int(nb), _vp(hc.data_ptr()), _vp(sc.data_ptr()), int(n),
+                                  _vp(eig.data_ptr()), _vp(yc.data_ptr()), int(n),
+                                  _vp(work.data_ptr()), int(work.numel()), _stream_ptr(st)),
+           "qeh_subspace_eigh")
+    return eig, yc.t()
 
 
 BETA_STATIC_BYTES = 8 << 20   # QEH_BETA_STATIC_BYTES
@@ -430,20 +463,25 @@ class Context:
         return out
 
     # ---------------------------------------------------------------- Davidson
-    def davidson_plan(self, nb, nvecx=0, rtol=1e-8, maxiter=0):
-        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
+    def davidson_plan(self, nb, nvecx=0, rtol=1e-8, maxiter=0, subspace=0):
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter), int(subspace))
         n = ctypes.c_size_t()
         _check(_lib.qeh_davidson_plan(self._h, int(nb), ctypes.byref(o), ctypes.byref(n)),
                "qeh_davidson_plan")
         return int(n.value)
 
-    def davidson(self, psi, nvecx=0, rtol=1e-8, maxiter=0, work=None, allow_notconv=False):
-        """In-place Davidson on psi (nb, npw) complex128; returns (eig ndarray, info dict)."""
+    def davidson(self, psi, nvecx=0, rtol=1e-8, maxiter=0, work=None, allow_notconv=False,
+                 subspace=0, refine=None):
+        """In-place Davidson on psi (nb, npw) complex128; returns (eig ndarray, info dict).
+        subspace: QEH_SUBSPACE_AUTO / _OWN / _ROCSOLVER (reduced-problem solver);
+        refine: an FP64 Context of the same cell on the same stream, for the
+        mixed form's FP64 refinement phase."""
         torch = _torch()
         psi = self._bands(psi)
         nb = psi.shape[0]
-        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
-        need = self.davidson_plan(nb, nvecx, rtol, maxiter)
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter), int(subspace),
+                    refine._h if refine is not None else None)
+        need = self.davidson_plan(nb, nvecx, rtol, maxiter, subspace)
         if work is None or work.numel() < need:
             work = torch.empty(max(need, 256), dtype=torch.uint8, device=psi.device)
         eig = np.zeros(nb, dtype=np.float64)

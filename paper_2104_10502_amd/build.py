@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libqeh.so")
 BUILD = os.path.join(ROOT, "_build")
 
-HIP_SOURCES = ["fft_kernels.hip", "gemm_kernels.hip", "dav_kernels.hip", "beta_kernels.hip"]
+HIP_SOURCES = ["fft_kernels.hip", "gemm_kernels.hip", "dav_kernels.hip", "beta_kernels.hip",
+               "eigh_kernels.hip"]
 CPP_SOURCES = ["ctx.cpp", "davidson.cpp", "server.cpp", "beta.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

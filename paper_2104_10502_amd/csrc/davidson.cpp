@@ -16,11 +16,13 @@
 //         full -> W_new = H t -> new columns of Hr, Sr.
 //
 // Everything runs on the context stream.  The reductions and rotations are
-// the library's MFMA complex GEMMs in FP64; the dense Hermitian generalized
-// eigensolve of the reduced pair uses rocSOLVER (the GPU counterpart of the
-// dense solver library the paper uses for this step), with its workspace
-// taken from the caller's work area so the library allocates no device
-// memory.  Small pinned host buffers hold the per-iteration readback.
+// the library's MFMA complex GEMMs in FP64.  The dense Hermitian generalized
+// eigensolve of the reduced pair (the paper's dense GPU solver step) runs on
+// the library's own kernels for bases up to 512 vectors (eigh_kernels.hip:
+// deterministic, about ten launches per iteration, no library handle) and on
+// rocSOLVER above that, with its workspace taken from the caller's work area
+// so the library allocates no device memory.  Small pinned host buffers hold
+// the per-iteration readback.
 #include "davidson.h"
 
 #include <rocsolver/rocsolver.h>
@@ -238,7 +240,7 @@ void EvPool::destroy() {
 }
 
 qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *nvecx,
-                          double *rtol, int *maxiter) {
+                          double *rtol, int *maxiter, bool *own) {
   if (!c) {
     set_error("ctx is null");
     return QEH_ERR_INVALID;
@@ -254,10 +256,32 @@ qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *
     set_error("nvecx must be in [2 nb, npw]");
     return QEH_ERR_INVALID;
   }
+  const int sub = o ? o->subspace : QEH_SUBSPACE_AUTO;
+  if (sub != QEH_SUBSPACE_AUTO && sub != QEH_SUBSPACE_OWN && sub != QEH_SUBSPACE_ROCSOLVER) {
+    set_error("subspace must be QEH_SUBSPACE_AUTO, _OWN or _ROCSOLVER");
+    return QEH_ERR_INVALID;
+  }
+  if (sub == QEH_SUBSPACE_OWN && *nvecx > kEigMaxN) {
+    set_error("the own subspace solver takes nvecx <= " + std::to_string(kEigMaxN));
+    return QEH_ERR_INVALID;
+  }
+  *own = sub == QEH_SUBSPACE_OWN || (sub == QEH_SUBSPACE_AUTO && *nvecx <= kEigMaxN);
+  if (o && o->refine) {
+    const qeh_ctx *r = o->refine;
+    if (c->prec != QEH_MIXED || r->prec != QEH_FP64) {
+      set_error("refine: a QEH_FP64 context for a QEH_MIXED solve");
+      return QEH_ERR_INVALID;
+    }
+    if (r->npw != c->npw || r->gamma != c->gamma || r->n1 != c->n1 || r->n2 != c->n2 ||
+        r->n3 != c->n3 || r->nkb != c->nkb || r->nat != c->nat) {
+      set_error("refine: context of a different cell (npw, box, projectors or Gamma flag)");
+      return QEH_ERR_INVALID;
+    }
+  }
   return QEH_OK;
 }
 
-qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
+qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, bool own, DavLayout *L) {
   size_t cur = 0;
   const size_t row = 16 * (size_t)c->npw;
   L->V = bump2(&cur, row * nvecx);
@@ -280,9 +304,19 @@ qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L) {
   L->idx = bump2(&cur, 4 * (size_t)nb);
   L->info = bump2(&cur, 16);
   L->flag = bump2(&cur, 4);
-  qeh_status st = solver_bytes(nvecx, c->gamma != 0, &L->solver_bytes);
-  if (st != QEH_OK) return st;
-  L->solver = bump2(&cur, std::max<size_t>(L->solver_bytes, 256));
+  L->own = own;
+  if (own) {
+    L->solver_bytes = 0;
+    L->solver = bump2(&cur, 0);
+    L->tri = bump2(&cur, 8 * 4 * (size_t)nvecx);
+    L->Zt = bump2(&cur, 8 * (size_t)nvecx * nb);
+    L->escr = bump2(&cur, 8 * eig_scratch_doubles(nvecx));
+  } else {
+    qeh_status st = solver_bytes(nvecx, c->gamma != 0, &L->solver_bytes);
+    if (st != QEH_OK) return st;
+    L->solver = bump2(&cur, std::max<size_t>(L->solver_bytes, 256));
+    L->tri = L->Zt = L->escr = bump2(&cur, 0);
+  }
   L->total = cur;
   return QEH_OK;
 }
@@ -291,7 +325,7 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
                         const qeh_dav_opts *o, void *work, size_t work_bytes) {
   t0_ = std::chrono::steady_clock::now();
   double rtol;
-  qeh_status st = dav_check_opts(c, nb, o, &nvecx_, &rtol, &maxiter_);
+  qeh_status st = dav_check_opts(c, nb, o, &nvecx_, &rtol, &maxiter_, &own_);
   if (st != QEH_OK) return st;
   if (!psi || !eig || !work) {
     set_error("psi_inout, eig and work must be non-null");
@@ -305,7 +339,7 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
     set_error("work not 256-byte aligned");
     return QEH_ERR_INVALID;
   }
-  st = dav_layout(c, nb, nvecx_, &L_);
+  st = dav_layout(c, nb, nvecx_, own_, &L_);
   if (st != QEH_OK) return st;
   if (work_bytes < L_.total) {
     set_error("work area has " + std::to_string(work_bytes) + " bytes, plan needs " +
@@ -319,6 +353,13 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   eig_ = eig;
   npw_ = c->npw;
   mixed_ = c->prec == QEH_MIXED;
+  c64_ = o ? o->refine : nullptr;
+  if (c64_ && c64_->stream != c->stream) {
+    set_error("refine: the FP64 context must use the same HIP stream");
+    return QEH_ERR_INVALID;
+  }
+  phase64_ = false;
+  it64_ = 0;
   thr_ = mixed_ ? std::max(rtol, 1e-5) : rtol;
   char *w = reinterpret_cast<char *>(work);
   V_ = reinterpret_cast<double2 *>(w + L_.V);
@@ -340,6 +381,9 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   idx_d_ = reinterpret_cast<int *>(w + L_.idx);
   info_d_ = reinterpret_cast<int *>(w + L_.info);
   flag_d_ = reinterpret_cast<int *>(w + L_.flag);
+  tri_ = reinterpret_cast<double *>(w + L_.tri);
+  Zt_ = reinterpret_cast<double *>(w + L_.Zt);
+  escr_ = reinterpret_cast<double *>(w + L_.escr);
   // pinned host readback: eps, norms (nb doubles each), idx (nb ints), 2 ints
   void *h = nullptr;
   const size_t hb = 16 * (size_t)nb + 4 * (size_t)nb + 32;
@@ -352,6 +396,10 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   eps_prev_.assign(nb, INFINITY);
   best_res_.assign(nb, INFINITY);
   stall_.assign(nb, 0);
+  phase_ = kStart;
+  notconv_ = nb;
+  resid_max_ = INFINITY;
+  if (own_) return QEH_OK;   // no library handle: the own solver needs none
   if (rocblas_create_handle(&rh_) != rocblas_status_success) {
     rh_ = nullptr;
     release();
@@ -389,11 +437,49 @@ void DavRun::release() {
 
 qeh_status DavRun::hpsi(const double2 *x, double2 *y, int n) {
   ev_h_.start(c_->stream);
-  qeh_status r = apply_h_impl(c_, 2, n, reinterpret_cast<const double *>(x), npw_,
-                              reinterpret_cast<double *>(y), npw_);
+  qeh_status r = apply_h_impl(phase64_ ? c64_ : c_, 2, n, reinterpret_cast<const double *>(x),
+                              npw_, reinterpret_cast<double *>(y), npw_);
   ev_h_.stop(c_->stream);
   band_applies_ += n;
   return r;
+}
+
+// Hr y = eps Sr y on the library's kernels: Sr = L L^H, A = L^-1 Hr L^-H by
+// two triangular solves (L^-1 Hr, then L^-1 of its adjoint), A = Q T Q^H,
+// the nb lowest eigenpairs of T, Z = Q Z_T, Y = L^-H Z.  Works in the
+// arena's n x n matrices: Sw (factor, then A before symmetrising), Lc / LcH
+// (L, L^H), X (L^-1 Hr, then Z), Hw (A, then its reflectors), Y.
+void DavRun::rr_own() {
+  hipStream_t s = c_->stream;
+  const int n = nbase_, nb = nb_, ld = nvecx_;
+  ok(launch_hermitise_copy(Hr_, ld, Hw_, ld, n, s));
+  ok(launch_hermitise_copy(Sr_, ld, Sw_, ld, n, s));
+  ok(launch_chol(Sw_, ld, n, info_d_ + 1, s));
+  ok(launch_tril_adjoint(Sw_, Lc_, LcH_, ld, n, s));
+  ok(launch_trsm(0, Lc_, ld, n, Hw_, ld, n, X_, ld, s));    // X = L^-1 Hr
+  ok(launch_trsm(1, Lc_, ld, n, X_, ld, n, Sw_, ld, s));    // Sw = L^-1 X^H = A
+  ok(launch_hermitise_copy(Sw_, ld, Hw_, ld, n, s));        // Hw = (A + A^H) / 2
+  ok(launch_tridiag(Hw_, ld, n, tri_, info_d_ + 1, s));
+  ok(launch_trieig(tri_, n, nb, eps_d_, Zt_, n, escr_, info_d_ + 3, info_d_ + 1, s));
+  ok(launch_backtr(Hw_, ld, n, tri_, Zt_, n, nb, X_, ld, info_d_ + 1, info_d_ + 3, s));
+  ok(launch_trsm(2, LcH_, ld, n, X_, ld, nb, Y_, ld, s));   // Y = L^-H Z
+}
+
+// Basis = the current Ritz vectors (orthonormal), W = H V through the active
+// context, reduced matrices rebuilt from them.
+void DavRun::restart_from_ritz() {
+  hipStream_t s = c_->stream;
+  ++restarts_;
+  ok(launch_copy_rows(P_, npw_, V_, npw_, npw_, nb_, s));
+  nbase_ = nb_;
+  if (phase64_) {
+    const qeh_status st = hpsi(V_, W_, nb_);
+    if (st != QEH_OK && result_ == QEH_OK) result_ = st;
+  } else {
+    ok(launch_copy_rows(Q_, npw_, W_, npw_, npw_, nb_, s));
+  }
+  ok(reduce_cols(c_, V_, nb_, W_, nb_, Hr_, nvecx_, part_));
+  ok(reduce_cols(c_, V_, nb_, V_, nb_, Sr_, nvecx_, part_));
 }
 
 bool DavRun::fail_device(const char *what) {
@@ -411,6 +497,7 @@ bool DavRun::advance() {
       case kStart: {
         // finiteness of psi0, V = psi0
         ok(launch_fill_int(flag_d_, 1, 0, s));
+        ok(launch_fill_int(info_d_, 4, 0, s));
         for (int b = 0; b < nb; ++b)
           ok(launch_check_finite(reinterpret_cast<const double *>(psi_ + (size_t)b * ldpsi_),
                                  2 * (long)npw, flag_d_, s));
@@ -445,6 +532,19 @@ bool DavRun::advance() {
         // products with the explicit inverse), A z = eps z (Hermitian
         // eigensolver), y = L^-H z (one more product).
         ++it_;
+        if (phase64_) ++it64_;
+        if (own_) {
+          // the whole reduced solve is enqueued at once: the kernels after
+          // the Cholesky skip their work when it failed, and the host reads
+          // all status words after one drain
+          ev_s_.start(s);
+          rr_own();
+          ev_s_.stop(s);
+          h_int_[1] = h_int_[2] = h_int_[3] = 0;
+          ok(hipMemcpyAsync(h_int_ + 1, info_d_ + 1, 12, hipMemcpyDeviceToHost, s));
+          phase_ = kRRCheck;
+          return false;
+        }
         ev_s_.start(s);
         const int n = nbase_;
         ok(launch_hermitise_copy(Hr_, nvecx, Hw_, nvecx, n, s));
@@ -536,12 +636,7 @@ bool DavRun::advance() {
           }
           // restart from the last Ritz vectors (orthonormal)
           chol_prev_ = true;
-          ++restarts_;
-          ok(launch_copy_rows(P_, npw, V_, npw, npw, nb, s));
-          ok(launch_copy_rows(Q_, npw, W_, npw, npw, nb, s));
-          nbase_ = nb;
-          ok(reduce_cols(c_, V_, nb, W_, nb, Hr_, nvecx, part_));
-          ok(reduce_cols(c_, V_, nb, V_, nb, Sr_, nvecx, part_));
+          restart_from_ritz();
           phase_ = kRR;
           break;
         }
@@ -574,14 +669,17 @@ bool DavRun::advance() {
           } else {
             ++stall_[b];
           }
-          // mixed form: the single-precision floor stops the residual; accept a
-          // band whose Ritz value has settled, whose small residual has not
-          // improved by 10% in 3 iterations, or whose residual below 100x the
-          // threshold has not improved by 10% in 5 (the floor grows with the
-          // cutoff and the number of projectors)
-          if (mixed_ && std::fabs(h_eps_[b] - eps_prev_[b]) <= 1e-8) conv = true;
-          if (mixed_ && stall_[b] >= 3 && r <= 10.0 * thr_) conv = true;
-          if (mixed_ && stall_[b] >= 5 && r <= 100.0 * thr_) conv = true;
+          // mixed form, single-precision phase: the floor stops the residual.
+          // With a refinement context a band is handed over once its residual
+          // has not dropped by 10% in 3 iterations; without one it is
+          // accepted at the floor while that floor is <= 10x the threshold
+          // (3 iterations) or <= 100x (5: the floor grows with the cutoff and
+          // the number of projectors)
+          if (mixed_ && !phase64_) {
+            if (c64_ && stall_[b] >= 3) conv = true;
+            if (!c64_ && stall_[b] >= 3 && r <= 10.0 * thr_) conv = true;
+            if (!c64_ && stall_[b] >= 5 && r <= 100.0 * thr_) conv = true;
+          }
           if (!conv) h_idx_[nc++] = b;
         }
         for (int b = 0; b < nb; ++b) eps_prev_[b] = h_eps_[b];
@@ -592,6 +690,22 @@ bool DavRun::advance() {
         } else if (nc > 0 && it_ >= maxiter_) {
           set_error("Davidson reached maxiter");
           result_ = QEH_ERR_NOT_CONVERGED;
+        }
+        if (nc == 0 && result_ == QEH_OK && c64_ && !phase64_) {
+          // single precision has done what it can: continue with H in FP64
+          // from the current Ritz vectors until the FP64 residuals meet thr
+          phase64_ = true;
+          for (int b = 0; b < nb; ++b) {
+            best_res_[b] = INFINITY;
+            stall_[b] = 0;
+          }
+          restart_from_ritz();
+          if (result_ != QEH_OK) {
+            phase_ = kDone;
+            return true;
+          }
+          phase_ = kRR;
+          break;
         }
         if (nc == 0 || result_ != QEH_OK) {
           ok(launch_copy_rows(P_, npw, psi_, ldpsi_, npw, nb, s));
@@ -650,6 +764,7 @@ void DavRun::fill_info(qeh_dav_info *info) const {
   info->resid_max = resid_max_;
   info->t_hpsi = ev_h_.acc;
   info->t_subspace = ev_s_.acc;
+  info->refine_iters = it64_;
   info->t_total = t_total_ > 0.0 ? t_total_
                                  : std::chrono::duration<double>(
                                        std::chrono::steady_clock::now() - t0_).count();
@@ -669,10 +784,11 @@ qeh_status qeh_davidson_plan(const qeh_ctx *c, int nb, const qeh_dav_opts *o,
   }
   int nvecx, maxiter;
   double rtol;
-  qeh_status st = dav_check_opts(c, nb, o, &nvecx, &rtol, &maxiter);
+  bool own = false;
+  qeh_status st = dav_check_opts(c, nb, o, &nvecx, &rtol, &maxiter, &own);
   if (st != QEH_OK) return st;
   DavLayout L;
-  st = dav_layout(c, nb, nvecx, &L);
+  st = dav_layout(c, nb, nvecx, own, &L);
   if (st != QEH_OK) return st;
   *work_bytes = L.total;
   return QEH_OK;
@@ -696,6 +812,97 @@ qeh_status qeh_davidson(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double
   const qeh_status r = run.result();
   run.release();
   return r;
+}
+
+namespace {
+struct EighLayout {
+  size_t Sw, Lc, LcH, X, Hw, tri, Zt, escr, info, total;
+};
+EighLayout eigh_layout(int n, int nb) {
+  EighLayout L{};
+  size_t cur = 0;
+  const size_t mat = 16 * (size_t)n * n;
+  L.Sw = bump2(&cur, mat);
+  L.Lc = bump2(&cur, mat);
+  L.LcH = bump2(&cur, mat);
+  L.X = bump2(&cur, mat);
+  L.Hw = bump2(&cur, mat);
+  L.tri = bump2(&cur, 8 * 4 * (size_t)n);
+  L.Zt = bump2(&cur, 8 * (size_t)n * nb);
+  L.escr = bump2(&cur, 8 * eig_scratch_doubles(n));
+  L.info = bump2(&cur, 16);
+  L.total = cur;
+  return L;
+}
+}  // namespace
+
+qeh_status qeh_subspace_plan(int n, int nb, size_t *work_bytes) {
+  if (!work_bytes) {
+    set_error("work_bytes is null");
+    return QEH_ERR_INVALID;
+  }
+  if (n < 1 || n > kEigMaxN || nb < 1 || nb > n) {
+    set_error("need 1 <= nb <= n <= " + std::to_string(kEigMaxN));
+    return QEH_ERR_INVALID;
+  }
+  *work_bytes = eigh_layout(n, nb).total;
+  return QEH_OK;
+}
+
+qeh_status qeh_subspace_eigh(int n, int nb, const double *H, const double *S, int ld, double *eig,
+                             double *Y, int ldy, void *work, size_t work_bytes,
+                             void *hip_stream) {
+  size_t need = 0;
+  qeh_status st = qeh_subspace_plan(n, nb, &need);
+  if (st != QEH_OK) return st;
+  if (!H || !S || !eig || !Y || !work) {
+    set_error("H, S, eig, Y and work must be non-null");
+    return QEH_ERR_INVALID;
+  }
+  if (ld < n || ldy < n) {
+    set_error("ld and ldy must be >= n");
+    return QEH_ERR_INVALID;
+  }
+  if (reinterpret_cast<uintptr_t>(work) % kAlign || work_bytes < need) {
+    set_error("work must be 256-byte aligned with qeh_subspace_plan bytes");
+    return QEH_ERR_NOMEM;
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const EighLayout L = eigh_layout(n, nb);
+  char *w = static_cast<char *>(work);
+  auto M = [&](size_t off) { return reinterpret_cast<double2 *>(w + off); };
+  double *tri = reinterpret_cast<double *>(w + L.tri), *zt = reinterpret_cast<double *>(w + L.Zt),
+         *escr = reinterpret_cast<double *>(w + L.escr);
+  int *info = reinterpret_cast<int *>(w + L.info);
+  const double2 *h = reinterpret_cast<const double2 *>(H), *sm = reinterpret_cast<const double2 *>(S);
+  hipError_t e = launch_fill_int(info, 4, 0, s);
+  auto run = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  run(launch_hermitise_copy(h, ld, M(L.Hw), n, n, s));
+  run(launch_hermitise_copy(sm, ld, M(L.Sw), n, n, s));
+  run(launch_chol(M(L.Sw), n, n, info, s));
+  run(launch_tril_adjoint(M(L.Sw), M(L.Lc), M(L.LcH), n, n, s));
+  run(launch_trsm(0, M(L.Lc), n, n, M(L.Hw), n, n, M(L.X), n, s));
+  run(launch_trsm(1, M(L.Lc), n, n, M(L.X), n, n, M(L.Sw), n, s));
+  run(launch_hermitise_copy(M(L.Sw), n, M(L.Hw), n, n, s));
+  run(launch_tridiag(M(L.Hw), n, n, tri, info, s));
+  run(launch_trieig(tri, n, nb, eig, zt, n, escr, info + 2, info, s));
+  run(launch_backtr(M(L.Hw), n, n, tri, zt, n, nb, M(L.X), n, info, info + 2, s));
+  run(launch_trsm(2, M(L.LcH), n, n, M(L.X), n, nb, reinterpret_cast<double2 *>(Y), ldy, s));
+  int hinfo[4] = {0, 0, 0, 0};
+  run(hipMemcpyAsync(hinfo, info, 16, hipMemcpyDeviceToHost, s));
+  run(hipStreamSynchronize(s));
+  if (e != hipSuccess) return hip_fail(e, "qeh_subspace_eigh");
+  if (hinfo[0] != 0) {
+    set_error("S is not positive definite (leading minor " + std::to_string(hinfo[0]) + ")");
+    return QEH_ERR_CHOLESKY;
+  }
+  if (hinfo[2] != 0) {
+    set_error("tridiagonal eigensolver failed (status " + std::to_string(hinfo[2]) + ")");
+    return QEH_ERR_NUMERIC;
+  }
+  return QEH_OK;
 }
 
 }  // extern "C"

@@ -16,8 +16,9 @@ namespace qeh {
 
 struct DavLayout {
   size_t V, W, P, Q, Hr, Sr, Hw, Sw, X, Lc, LcH, Y, part, eps, E, norms, idx, info, flag,
-      solver;
+      solver, tri, Zt, escr;
   size_t solver_bytes;
+  bool own;   // the library's own subspace solver (else rocSOLVER)
   size_t total;
 };
 
@@ -34,8 +35,8 @@ struct EvPool {
 };
 
 qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *nvecx,
-                          double *rtol, int *maxiter);
-qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, DavLayout *L);
+                          double *rtol, int *maxiter, bool *own);
+qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, bool own, DavLayout *L);
 
 class DavRun {
  public:
@@ -50,6 +51,8 @@ class DavRun {
 
  private:
   enum Phase { kStart, kCheckInput, kRR, kRRSolve, kRRCheck, kConverge, kFinish, kDone };
+  void rr_own();   // enqueue the whole Rayleigh-Ritz solve on the own kernels
+  void restart_from_ritz();   // V = P, W = H P, reduced matrices rebuilt
   qeh_status hpsi(const double2 *x, double2 *y, int n);
   void ok(hipError_t e) {
     if (err_ == hipSuccess) err_ = e;
@@ -66,6 +69,11 @@ class DavRun {
   double2 *V_ = nullptr, *W_ = nullptr, *P_ = nullptr, *Q_ = nullptr;
   double2 *Hr_ = nullptr, *Sr_ = nullptr, *Hw_ = nullptr, *Sw_ = nullptr, *part_ = nullptr;
   double2 *X_ = nullptr, *Lc_ = nullptr, *LcH_ = nullptr, *Y_ = nullptr;
+  double *tri_ = nullptr, *Zt_ = nullptr, *escr_ = nullptr;   // own subspace solver
+  bool own_ = false;
+  qeh_ctx *c64_ = nullptr;   // mixed form: FP64 context of the refinement phase
+  bool phase64_ = false;     // H applied through c64_
+  int it64_ = 0;             // iterations of the refinement phase
   double *eps_d_ = nullptr, *E_d_ = nullptr, *norms_d_ = nullptr;
   int *idx_d_ = nullptr, *info_d_ = nullptr, *flag_d_ = nullptr;
   // pinned host mirrors of the per-iteration readback

@@ -1,0 +1,855 @@
+// Dense Hermitian solver of the Davidson Rayleigh-Ritz step, written for the
+// small reduced problems of block Davidson (n <= 512): the paper solves this
+// "relatively small" generalized eigenproblem with a dense GPU solver (section
+// "Evolution of the GPU-enabled version").  H y = eps S y for the lowest nb
+// pairs, in five deterministic kernels (fixed summation orders, no atomics on
+// floating-point data), each problem a handful of launches instead of the
+// hundreds of a library eigensolver:
+//
+//   chol_kernel     one workgroup: S = L L^H, right-looking, lower triangle
+//   trsm_kernel     one wave per column, many workgroups: L X = B (forward),
+//                   with B given or as the adjoint of a matrix, or L^H X = B
+//                   (backward with the explicit L^H); A = L^-1 H L^-H by two
+//                   of them, Y = L^-H Z by a third
+//   tridiag_kernel  one workgroup: Householder reduction A = Q T Q^H, T real
+//                   symmetric tridiagonal (d, e), reflectors kept in A
+//   trieig_kernel   one workgroup: the nb lowest eigenpairs of T.  T is split
+//                   where |e_k| <= eps ||T||; the global nb-th eigenvalue is
+//                   bracketed by multisection of Sturm counts; every block's
+//                   eigenvalues below it are found by bisection (one thread
+//                   each) and sorted; eigenvectors come from twisted
+//                   factorizations of T_b - lambda I (one thread each), except
+//                   for groups of numerically equal eigenvalues of one block
+//                   (gap <= 1e-12 ||T||, as exact multiplets of A leave them:
+//                   Householder does not split T there), which get inverse
+//                   iteration from distinct start vectors through one pivoted
+//                   LU of T_b - sigma I with Gram-Schmidt between the two
+//                   sweeps; vectors of close eigenvalues of one block
+//                   (gap <= 1e-5 ||T||) are re-orthogonalised in index order
+//   backtr_kernel   one wave per column, many workgroups: Z = Q Z_T through
+//                   the stored reflectors
+//
+// Storage: column-major double2 matrices with leading dimension ld.  A real
+// symmetric pair (Gamma point) goes through the same kernels with zero
+// imaginary parts, which stay zero.
+#include <hip/hip_runtime.h>
+
+#include "cplx.h"
+#include "qeh_internal.h"
+
+namespace qeh {
+namespace {
+
+constexpr int kET = 1024;            // threads of the one-workgroup kernels
+constexpr int kEW = kET / 64;        // their waves
+constexpr int kEMaxN = kEigMaxN;     // largest problem (rows held 8 per lane)
+constexpr int kSlots = kEMaxN / 64;  // register slots per lane in the column kernels
+constexpr double kEps = 2.220446049250313e-16;
+constexpr double kTiny = 2.2250738585072014e-308;
+constexpr double kDegRel = 1e-12;    // numerically equal eigenvalues (relative to ||T||)
+constexpr double kCloseRel = 1e-5;   // close eigenvalues, re-orthogonalised
+constexpr int kTU = 6;               // independent loads in flight per thread
+
+__device__ __forceinline__ double wave_sum(double v) {
+  // fixed butterfly; lane 0's result is what callers use
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return __shfl(v, 0);
+}
+
+// Sum over the workgroup, identical in every thread and from run to run.
+__device__ double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < kEW; ++i) s += red[i];
+  return s;
+}
+
+__device__ double block_max(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = red[0];
+  for (int i = 1; i < kEW; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+__device__ double block_min(double v, double *red) {
+  return -block_max(-v, red);
+}
+
+// ---------------------------------------------------------------- Cholesky
+// S (n x n, lower triangle read) = L L^H in place (lower).  info = 0, or
+// j + 1 if the leading (j+1) x (j+1) minor is not positive definite (or not
+// finite); L is then incomplete.
+__global__ __launch_bounds__(kET) void chol_kernel(double2 *S, long ld, int n, int *info) {
+  __shared__ double2 col[kEMaxN];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < n; ++j) {
+    const double ajj = S[j + (long)j * ld].x;
+    if (!(ajj > 0.0) || !isfinite(ajj)) {   // same value in every thread
+      if (tid == 0) *info = j + 1;
+      return;
+    }
+    const double ljj = sqrt(ajj), rinv = 1.0 / ljj;
+    for (int i = j + 1 + tid; i < n; i += kET) {
+      const double2 v = cscale(S[i + (long)j * ld], rinv);
+      S[i + (long)j * ld] = v;
+      col[i] = v;
+    }
+    if (tid == 0) S[j + (long)j * ld] = make_double2(ljj, 0.0);
+    __syncthreads();
+    const int m = n - j - 1;
+    if (m > 0) {
+      // trailing update of the lower triangle, S -= c c^H: thread (row r,
+      // column group grp) takes columns kk = grp, grp + g, ... <= r, eight
+      // loads in flight
+      const int g = kET / m;
+      if (tid < g * m) {
+        const int r = tid % m, grp = tid / m;
+        double2 *t = S + (long)(j + 1) * ld + (j + 1);
+        const double2 cr = col[j + 1 + r];
+        int kk = grp;
+        for (; kk + (kTU - 1) * g <= r; kk += kTU * g) {
+          double2 a[kTU];
+#pragma unroll
+          for (int u = 0; u < kTU; ++u) a[u] = t[r + (long)(kk + u * g) * ld];
+#pragma unroll
+          for (int u = 0; u < kTU; ++u)
+            t[r + (long)(kk + u * g) * ld] = csub(a[u], cmulc(cr, col[j + 1 + kk + u * g]));
+        }
+        for (; kk <= r; kk += g) {
+          double2 *p = t + r + (long)kk * ld;
+          *p = csub(*p, cmulc(cr, col[j + 1 + kk]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *info = 0;
+}
+
+// ---------------------------------------------------------------- triangular solves
+// One wave per right-hand side column j; the column's n <= 512 entries sit in
+// registers (row s * 64 + lane in slot s).
+//   MODE 0: L x = b,   L lower (T), b = B(:, j)
+//   MODE 1: L x = b,   b = conj(M(j, :)) with M = B (column j of M^H)
+//   MODE 2: U x = b,   U upper (T), b = B(:, j)   (backward)
+// The diagonal of T is real (a Cholesky factor).
+template <int MODE>
+__global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T, long ldt, int n,
+                                                   const double2 *__restrict__ B, long ldb,
+                                                   int ncol, double2 *__restrict__ X, long ldx) {
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= ncol) return;   // whole waves only: no workgroup barrier below
+  double2 x[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = s * 64 + lane;
+    double2 v = make_double2(0.0, 0.0);
+    if (i < n) {
+      if (MODE == 1) {
+        const double2 m = B[j + (long)i * ldb];
+        v = make_double2(m.x, -m.y);
+      } else {
+        v = B[i + (long)j * ldb];
+      }
+    }
+    x[s] = v;
+  }
+  if (MODE != 2) {
+#pragma unroll
+    for (int sb = 0; sb < kSlots; ++sb) {
+      for (int l = 0; l < 64; ++l) {
+        const int k = sb * 64 + l;
+        if (k >= n) break;
+        const double rinv = 1.0 / T[k + (long)k * ldt].x;
+        double2 xk = make_double2(__shfl(x[sb].x, l), __shfl(x[sb].y, l));
+        xk = cscale(xk, rinv);
+        if (lane == l) x[sb] = xk;
+#pragma unroll
+        for (int s = sb; s < kSlots; ++s) {
+          const int i = s * 64 + lane;
+          if (i > k && i < n) x[s] = csub(x[s], cmul(T[i + (long)k * ldt], xk));
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int sb = kSlots - 1; sb >= 0; --sb) {
+      for (int l = 63; l >= 0; --l) {
+        const int k = sb * 64 + l;
+        if (k >= n) continue;
+        const double rinv = 1.0 / T[k + (long)k * ldt].x;
+        double2 xk = make_double2(__shfl(x[sb].x, l), __shfl(x[sb].y, l));
+        xk = cscale(xk, rinv);
+        if (lane == l) x[sb] = xk;
+#pragma unroll
+        for (int s = 0; s <= sb; ++s) {
+          const int i = s * 64 + lane;
+          if (i < k) x[s] = csub(x[s], cmul(T[i + (long)k * ldt], xk));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = s * 64 + lane;
+    if (i < n) X[i + (long)j * ldx] = x[s];
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonalisation
+// A (n x n Hermitian, full storage) = Q T Q^H, Q = H_0 ... H_{n-2},
+// H_k = I - tau_k v_k v_k^H acting on rows k+1..n-1.  On return column k of A
+// holds v_k in rows k+1..n-1 (v_k[k+1] = 1); tri = d[n] | e[n] | tau (double2)[n].
+//
+// Step k needs p = A22 v_k (A22 = rows / columns k+1..); the rank-2 update of
+// step k and the product of step k+1 share one pass over the trailing matrix:
+// column k+1 is updated first (it defines v_{k+1}), then every other element
+// is read once, updated, written back and multiplied into p for step k+1.
+// Threads cover rows i (fastest, coalesced) x column groups; eight columns'
+// loads are in flight per thread.
+// Householder vector of the column col[0..m) (col[0] the subdiagonal entry):
+// tau, beta, and v written to col (v[0] = 1) and to vs.  Uniform in all threads.
+__device__ void householder(double2 *col, int m, double2 *vs, double *red, double2 *t_out,
+                            double *beta_out) {
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int i = 1 + tid; i < m; i += kET) {
+    const double2 v = col[i];
+    s += v.x * v.x + v.y * v.y;
+  }
+  const double xn2 = block_sum(s, red);
+  const double2 alpha = col[0];
+  double beta;
+  double2 t = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+  if (xn2 == 0.0 && alpha.y == 0.0) {
+    beta = alpha.x;
+  } else {
+    beta = -copysign(sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2), alpha.x);
+    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double2 ab = make_double2(alpha.x - beta, alpha.y);
+    const double den = ab.x * ab.x + ab.y * ab.y;
+    scale = make_double2(ab.x / den, -ab.y / den);   // 1 / (alpha - beta)
+  }
+  const bool refl = t.x != 0.0 || t.y != 0.0;
+  for (int i = tid; i < m; i += kET) {
+    const double2 v = i == 0 ? make_double2(1.0, 0.0) : (refl ? cmul(col[i], scale) : col[i]);
+    vs[i] = v;
+    col[i] = v;
+  }
+  *t_out = t;
+  *beta_out = beta;
+}
+
+// One pass over the m x m block U (columns 1..m-1, rows 1..m-1 of the
+// trailing matrix of step k; element (i, j) at U[i + j*lda]):
+//   if upd:  U(i, j) -= v_i conj(w_j) + w_i conj(v_j)   (stored back)
+//   if vn:   part[grp * mm + (i - 1)] = sum over the thread's columns of U(i, j) vn_{j-1}
+// Rows and columns 0 (column 0 was done separately) are skipped.
+__device__ void fused_pass(double2 *U, long lda, int m, bool upd, const double2 *vs,
+                           const double2 *ws, bool mv, const double2 *vn, double2 *part) {
+  const int tid = threadIdx.x;
+  const int mm = m - 1;
+  if (mm <= 0) return;
+  const int g = kET / mm;   // >= 2 (mm <= 510)
+  if (tid >= g * mm) return;
+  const int r = tid % mm, grp = tid / mm;
+  const int i = r + 1;
+  const double2 vi = vs[i], wi = ws[i];
+  double2 acc = make_double2(0.0, 0.0);
+  int j = 1 + grp;
+  for (; j + (kTU - 1) * g < m; j += kTU * g) {
+    double2 a[kTU];
+#pragma unroll
+    for (int u = 0; u < kTU; ++u) a[u] = U[i + (long)(j + u * g) * lda];
+#pragma unroll
+    for (int u = 0; u < kTU; ++u) {
+      const int jj = j + u * g;
+      if (upd) {
+        a[u] = csub(a[u], cadd(cmulc(vi, ws[jj]), cmulc(wi, vs[jj])));
+        U[i + (long)jj * lda] = a[u];
+      }
+      if (mv) acc = cadd(acc, cmul(a[u], vn[jj - 1]));
+    }
+  }
+  for (; j < m; j += g) {
+    double2 a = U[i + (long)j * lda];
+    if (upd) {
+      a = csub(a, cadd(cmulc(vi, ws[j]), cmulc(wi, vs[j])));
+      U[i + (long)j * lda] = a;
+    }
+    if (mv) acc = cadd(acc, cmul(a, vn[j - 1]));
+  }
+  if (mv) part[grp * mm + r] = acc;
+}
+
+__global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int n, double *tri,
+                                                      const int *info_chol) {
+  if (*info_chol != 0) return;
+  __shared__ double2 vbuf[2][kEMaxN];   // v_k and v_{k+1}
+  __shared__ double2 ps[kEMaxN];        // A22 v_k, then p, then w
+  __shared__ double2 part[kET];
+  __shared__ double red[kEW];
+  double *d = tri, *e = tri + n;
+  double2 *tau = reinterpret_cast<double2 *>(tri + 2 * n);
+  const int tid = threadIdx.x;
+  if (n == 1) {
+    if (tid == 0) d[0] = A[0].x;
+    return;
+  }
+  // step 0's reflector and its product A22 v_0 (a plain pass: no update)
+  double2 t;
+  double beta;
+  householder(A + 1, n - 1, vbuf[0], red, &t, &beta);
+  if (tid == 0) {
+    d[0] = A[0].x;
+    e[0] = beta;
+    tau[0] = t;
+  }
+  __syncthreads();
+  {
+    // the pass skips row / column 0 of its block: hand it the whole A22 by
+    // starting one row and column earlier (A11 corner of A)
+    const int m = n - 1;
+    // rows 0..m-1 of A22 times v: do row 0 and column 0 here too
+    const double2 *a22 = A + lda + 1;
+    const int g = kET / m;
+    if (tid < g * m) {
+      const int i = tid % m, grp = tid / m;
+      double2 acc = make_double2(0.0, 0.0);
+      int jj = grp;
+      for (; jj + (kTU - 1) * g < m; jj += kTU * g) {
+        double2 a[kTU];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) a[u] = a22[i + (long)(jj + u * g) * lda];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) acc = cadd(acc, cmul(a[u], vbuf[0][jj + u * g]));
+      }
+      for (; jj < m; jj += g) acc = cadd(acc, cmul(a22[i + (long)jj * lda], vbuf[0][jj]));
+      part[tid] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kET) {
+      double2 acc = part[i];
+      for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * m + i]);
+      ps[i] = acc;
+    }
+    __syncthreads();
+  }
+  int cur = 0;
+  for (int k = 0; k + 1 < n; ++k) {
+    const int m = n - k - 1;   // order of A22 of step k
+    double2 *u = A + (long)(k + 1) * lda + (k + 1);   // A22 of step k, (0, 0) corner
+    const double2 *vs = vbuf[cur];
+    const bool refl = t.x != 0.0 || t.y != 0.0;
+    if (refl) {
+      // p = t A22 v, alpha2 = -1/2 t (p^H v), w = p + alpha2 v (in ps)
+      double dr = 0.0, di = 0.0;
+      for (int i = tid; i < m; i += kET) {
+        const double2 p = cmul(t, ps[i]), v = vs[i];
+        dr += p.x * v.x + p.y * v.y;
+        di += p.x * v.y - p.y * v.x;
+      }
+      dr = block_sum(dr, red);
+      di = block_sum(di, red);
+      const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
+      for (int i = tid; i < m; i += kET) ps[i] = cadd(cmul(t, ps[i]), cmul(a2, vs[i]));
+      __syncthreads();
+      // column 0 of A22 (column k+1 of A), rows 0..m-1
+      for (int i = tid; i < m; i += kET)
+        u[i] = csub(u[i], cadd(cmulc(vs[i], ps[0]), cmulc(ps[i], vs[0])));
+      __syncthreads();
+    }
+    if (m == 1) {
+      if (tid == 0) d[k + 1] = u[0].x;
+      break;
+    }
+    // reflector of step k+1 from column k+1 below the diagonal
+    double2 t1;
+    double beta1;
+    householder(u + 1, m - 1, vbuf[cur ^ 1], red, &t1, &beta1);
+    if (tid == 0) {
+      d[k + 1] = u[0].x;
+      e[k + 1] = beta1;
+      tau[k + 1] = t1;
+    }
+    __syncthreads();
+    const bool refl1 = t1.x != 0.0 || t1.y != 0.0;
+    // rest of step k's update fused with step k+1's product (rows / columns
+    // 1..m-1 of this A22 are A22 of step k+1)
+    fused_pass(u, lda, m, refl, vs, ps, refl1, vbuf[cur ^ 1], part);
+    __syncthreads();
+    if (refl1) {
+      const int mm = m - 1, g = kET / mm;
+      for (int i = tid; i < mm; i += kET) {
+        double2 acc = part[i];
+        for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * mm + i]);
+        ps[i] = acc;
+      }
+    }
+    __syncthreads();
+    t = t1;
+    cur ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonal eigenpairs
+// Number of eigenvalues of the block [s, t) of T (split e) below x.
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int s, int t, double x,
+                                           double pivmin) {
+  int c = 0;
+  double q = d[s] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += q < 0.0;
+  for (int i = s + 1; i < t; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  }
+  return c;
+}
+
+__device__ __forceinline__ double guard(double q, double pivmin) {
+  return fabs(q) < pivmin ? -pivmin : q;
+}
+
+// deterministic start vector entry in [-1, 1) for row i of group member r
+__device__ __forceinline__ double start_entry(int i, int r) {
+  unsigned long long z = (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull ^
+                         (unsigned long long)(r + 1) * 0xC2B2AE3D27D4EB4Full;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// Solve (T_b - sigma I) x = x in place with the pivoted LU (dl, dd, du, du2,
+// piv) of length m; tiny pivots replaced by +-tiny.
+__device__ void lu_solve(const double *dl, const double *dd, const double *du, const double *du2,
+                         const double *piv, int m, double tiny, double *x) {
+  for (int i = 0; i + 1 < m; ++i) {
+    if (piv[i] != 0.0) {
+      const double a = x[i], b = x[i + 1];
+      x[i] = b;
+      x[i + 1] = a - dl[i] * b;
+    } else {
+      x[i + 1] -= dl[i] * x[i];
+    }
+  }
+  auto piv_d = [&](int i) {
+    const double v = dd[i];
+    return fabs(v) < tiny ? copysign(tiny, v) : v;
+  };
+  x[m - 1] /= piv_d(m - 1);
+  if (m > 1) x[m - 2] = (x[m - 2] - du[m - 2] * x[m - 1]) / piv_d(m - 2);
+  for (int i = m - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / piv_d(i);
+}
+
+// Gram-Schmidt of the columns of one group (tasks g0 .. g0+cnt-1 in block
+// order, Z columns zc[task]) by one wave: each column against the earlier
+// ones, then normalised.
+__device__ void wave_mgs(double *Z, int ldz, const int *zc, int g0, int cnt, int s, int t) {
+  const int lane = threadIdx.x & 63;
+  for (int r = 0; r < cnt; ++r) {
+    double *zr = Z + (long)zc[g0 + r] * ldz;
+    for (int rr = 0; rr < r; ++rr) {
+      const double *zq = Z + (long)zc[g0 + rr] * ldz;
+      double dp = 0.0;
+      for (int i = s + lane; i < t; i += 64) dp += zq[i] * zr[i];
+      dp = wave_sum(dp);
+      for (int i = s + lane; i < t; i += 64) zr[i] -= dp * zq[i];
+    }
+    double nn = 0.0;
+    for (int i = s + lane; i < t; i += 64) nn += zr[i] * zr[i];
+    nn = wave_sum(nn);
+    const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = s + lane; i < t; i += 64) zr[i] *= inv;
+  }
+}
+
+// The nb lowest eigenpairs of T (tri = d | e).  w[j] ascending, Z(:, j)
+// (column-major, ldz >= n, real) orthonormal eigenvectors.  scr: 7 n kEMaxN
+// doubles.  info: 0, 1 (T not finite), 2 (fewer than nb eigenvalues found).
+__global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, int nb, double *w,
+                                                     double *Z, int ldz, double *scr, int *info,
+                                                     const int *info_chol) {
+  if (*info_chol != 0) return;
+  __shared__ double sd[kEMaxN], se[kEMaxN], se2[kEMaxN];
+  __shared__ int bst[kEMaxN + 1];    // block starts
+  __shared__ int bof[kEMaxN + 1];    // first task of each block
+  __shared__ double tlam[kEMaxN];    // task eigenvalue
+  __shared__ int tblk[kEMaxN], tpos[kEMaxN];   // task block, sorted position
+  __shared__ int gdeg[kEMaxN], gclo[kEMaxN];   // first task of the task's degenerate / close group
+  __shared__ double key[kET];
+  __shared__ int kid[kET];
+  __shared__ double red[kEW];
+  __shared__ int sh_i[4];            // nblk, ntask, first qualifying multisection point
+  __shared__ double sh_d[2];         // multisection bracket
+  const int tid = threadIdx.x;
+  const int wid = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < n; i += kET) {
+    sd[i] = tri[i];
+    se[i] = i + 1 < n ? tri[n + i] : 0.0;
+  }
+  __syncthreads();
+  double md = 0.0, me = 0.0;
+  for (int i = tid; i < n; i += kET) {
+    md = fmax(md, fabs(sd[i]));
+    me = fmax(me, fabs(se[i]));
+  }
+  md = block_max(md, red);
+  me = block_max(me, red);
+  const double tnorm = md + 2.0 * me;
+  if (!isfinite(tnorm) || nb < 1 || nb > n) {
+    if (tid == 0) *info = 1;
+    return;
+  }
+  // split where |e| is negligible
+  double e2max = 0.0;
+  for (int i = tid; i < n; i += kET) {
+    if (fabs(se[i]) <= kEps * tnorm) se[i] = 0.0;
+    se2[i] = se[i] * se[i];
+    e2max = fmax(e2max, se2[i]);
+  }
+  e2max = block_max(e2max, red);
+  const double pivmin = kTiny * fmax(1.0, e2max);
+  double lo = 1e300, hi = -1e300;
+  for (int i = tid; i < n; i += kET) {
+    const double r = fabs(se[i]) + (i > 0 ? fabs(se[i - 1]) : 0.0);
+    lo = fmin(lo, sd[i] - r);
+    hi = fmax(hi, sd[i] + r);
+  }
+  const double gl = block_min(lo, red) - 2.0 * kEps * tnorm - pivmin;
+  const double gu = block_max(hi, red) + 2.0 * kEps * tnorm + pivmin;
+  if (tid == 0) {
+    int nbk = 0;
+    bst[nbk++] = 0;
+    for (int i = 0; i + 1 < n; ++i)
+      if (se[i] == 0.0) bst[nbk++] = i + 1;
+    bst[nbk] = n;
+    sh_i[0] = nbk;
+  }
+  __syncthreads();
+  const int nblk = sh_i[0];
+  // bracket the nb-th eigenvalue: count(lo) <= nb - 1 < count(hi)
+  if (tid == 0) {
+    sh_d[0] = gl;
+    sh_d[1] = gu;
+  }
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const double a = sh_d[0], b = sh_d[1];
+    if (b - a <= 2.0 * kEps * fmax(fabs(a), fabs(b)) + pivmin) break;   // uniform
+    const double x = a + (b - a) * (double)(tid + 1) / (double)(kET + 1);
+    const int c = sturm_count(sd, se2, 0, n, x, pivmin);
+    if (tid == 0) sh_i[2] = kET;
+    __syncthreads();
+    if (c > nb - 1) atomicMin(&sh_i[2], tid);   // first point above: order-free minimum
+    __syncthreads();
+    const int f = sh_i[2];
+    __syncthreads();
+    if (tid == 0) {
+      const double xf = f < kET ? a + (b - a) * (double)(f + 1) / (double)(kET + 1) : b;
+      const double xl = f > 0 ? a + (b - a) * (double)f / (double)(kET + 1) : a;
+      sh_d[0] = xl;
+      sh_d[1] = xf;
+    }
+    __syncthreads();
+  }
+  const double xcut = sh_d[1] + 4.0 * kEps * tnorm + pivmin;
+  // eigenvalues of each block below the cut -> tasks
+  for (int b = tid; b < nblk; b += kET) bof[b] = sturm_count(sd, se2, bst[b], bst[b + 1], xcut, pivmin);
+  __syncthreads();
+  if (tid == 0) {
+    int acc = 0;
+    for (int b = 0; b < nblk; ++b) {
+      const int c = bof[b];
+      bof[b] = acc;
+      acc += c;
+    }
+    bof[nblk] = acc;
+    sh_i[1] = acc;
+  }
+  __syncthreads();
+  const int ntask = sh_i[1];
+  if (ntask < nb || ntask > kEMaxN) {
+    if (tid == 0) *info = 2;
+    return;
+  }
+  for (int b = tid; b < nblk; b += kET)
+    for (int t = bof[b]; t < bof[b + 1]; ++t) tblk[t] = b;
+  __syncthreads();
+  // bisection, one thread per task (local index t - bof[b] of block b)
+  if (tid < ntask) {
+    const int b = tblk[tid], s = bst[b], t = bst[b + 1], loc = tid - bof[b];
+    double a = gl, c = xcut;
+    for (int it = 0; it < 160; ++it) {
+      if (c - a <= 2.0 * kEps * fmax(fabs(a), fabs(c)) + pivmin) break;
+      const double mid = 0.5 * (a + c);
+      if (!(mid > a && mid < c)) break;
+      if (sturm_count(sd, se2, s, t, mid, pivmin) > loc) c = mid;
+      else a = mid;
+    }
+    tlam[tid] = 0.5 * (a + c);
+  }
+  // sort (value, task) pairs by value, task index breaking ties (bitonic, 1024 keys)
+  key[tid] = tid < ntask ? tlam[tid] : INFINITY;
+  kid[tid] = tid;
+  if (tid < kEMaxN) tpos[tid] = nb;   // not selected unless sorted below nb
+  __syncthreads();
+  for (int size = 2; size <= kET; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const int p = tid ^ stride;
+      if (p > tid) {
+        const bool up = (tid & size) == 0;
+        const double ka = key[tid], kb = key[p];
+        const int ia = kid[tid], ib = kid[p];
+        const bool gt = ka > kb || (ka == kb && ia > ib);
+        if (gt == up) {
+          key[tid] = kb;
+          key[p] = ka;
+          kid[tid] = ib;
+          kid[p] = ia;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid < ntask && kid[tid] < ntask) tpos[kid[tid]] = tid;
+  __syncthreads();
+  // groups within a block among the selected tasks (tasks of one block are
+  // consecutive and ascending)
+  if (tid < ntask && tpos[tid] < nb) {
+    int g = tid;
+    while (g > bof[tblk[tid]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kDegRel * tnorm) --g;
+    gdeg[tid] = g;
+    g = tid;
+    while (g > bof[tblk[tid]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kCloseRel * tnorm)
+      --g;
+    gclo[tid] = g;
+  }
+  __syncthreads();
+  const long ls = n;   // per-task scratch stride
+  double *twp = scr;                    // [task][n] D+ (top-down pivots)
+  double *twm = scr + ls * kEMaxN;      // [task][n] D- (bottom-up pivots)
+  double *lu = scr + 2 * ls * kEMaxN;   // [task][5 n] pivoted LU (group leaders)
+  const double dtiny = kEps * tnorm;
+  auto in_group = [&](int t) {   // selected task t is in a degenerate group of >= 2
+    return gdeg[t] != t || (t + 1 < bof[tblk[t] + 1] && tpos[t + 1] < nb && gdeg[t + 1] == t);
+  };
+  // pass 1: twisted vectors (singletons); LU of the degenerate groups (leaders)
+  if (tid < ntask && tpos[tid] < nb) {
+    const int b = tblk[tid], s = bst[b], t = bst[b + 1], m = t - s;
+    double *z = Z + (long)tpos[tid] * ldz;
+    for (int i = 0; i < n; ++i)
+      if (i < s || i >= t) z[i] = 0.0;
+    const double lam = tlam[tid];
+    if (!in_group(tid)) {
+      if (m == 1) {
+        z[s] = 1.0;
+      } else {
+        double *dp = twp + (long)tid * ls, *dm = twm + (long)tid * ls;
+        dp[0] = sd[s] - lam;
+        for (int i = 1; i < m; ++i) dp[i] = sd[s + i] - lam - se2[s + i - 1] / guard(dp[i - 1], pivmin);
+        dm[m - 1] = sd[t - 1] - lam;
+        for (int i = m - 2; i >= 0; --i) dm[i] = sd[s + i] - lam - se2[s + i] / guard(dm[i + 1], pivmin);
+        int r = 0;
+        double best = INFINITY;
+#pragma unroll 8
+        for (int i = 0; i < m; ++i) {
+          const double gm = fabs(dp[i] + dm[i] - (sd[s + i] - lam));
+          if (gm < best) {
+            best = gm;
+            r = i;
+          }
+        }
+        z[s + r] = 1.0;
+        double nn = 1.0;
+#pragma unroll 8
+        for (int i = r - 1; i >= 0; --i) {
+          z[s + i] = -se[s + i] / guard(dp[i], pivmin) * z[s + i + 1];
+          nn += z[s + i] * z[s + i];
+        }
+#pragma unroll 8
+        for (int i = r; i + 1 < m; ++i) {
+          z[s + i + 1] = -se[s + i] / guard(dm[i + 1], pivmin) * z[s + i];
+          nn += z[s + i + 1] * z[s + i + 1];
+        }
+        const double inv = 1.0 / sqrt(nn);
+#pragma unroll 8
+        for (int i = s; i < t; ++i) z[i] *= inv;
+      }
+    } else if (gdeg[tid] == tid) {
+      // pivoted LU of T_b - lam I (LAPACK gttrf order)
+      double *dl = lu + (long)tid * 5 * ls, *dd = dl + ls, *du = dd + ls, *du2 = du + ls,
+             *pv = du2 + ls;
+      for (int i = 0; i < m; ++i) dd[i] = sd[s + i] - lam;
+      for (int i = 0; i + 1 < m; ++i) {
+        dl[i] = se[s + i];
+        du[i] = se[s + i];
+        pv[i] = 0.0;
+      }
+      for (int i = 0; i + 2 < m; ++i) du2[i] = 0.0;
+      for (int i = 0; i + 1 < m; ++i) {
+        if (fabs(dd[i]) >= fabs(dl[i])) {
+          const double f = dd[i] != 0.0 ? dl[i] / dd[i] : 0.0;
+          dl[i] = f;
+          dd[i + 1] -= f * du[i];
+        } else {
+          const double f = dd[i] / dl[i];
+          dd[i] = dl[i];
+          dl[i] = f;
+          const double tmp = du[i];
+          du[i] = dd[i + 1];
+          dd[i + 1] = tmp - f * dd[i + 1];
+          if (i + 2 < m) {
+            du2[i] = du[i + 1];
+            du[i + 1] = -f * du[i + 1];
+          }
+          pv[i] = 1.0;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // passes 2-5: two sweeps of inverse iteration for the degenerate groups,
+  // each followed by Gram-Schmidt within the group (one wave per group)
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    if (tid < ntask && tpos[tid] < nb && in_group(tid)) {
+      const int b = tblk[tid], s = bst[b], t = bst[b + 1], m = t - s;
+      const int ld0 = gdeg[tid];
+      const double *dl = lu + (long)ld0 * 5 * ls, *dd = dl + ls, *du = dd + ls, *du2 = du + ls,
+                   *pv = du2 + ls;
+      double *z = Z + (long)tpos[tid] * ldz + s;
+      if (sweep == 0)
+        for (int i = 0; i < m; ++i) z[i] = start_entry(i, tid - ld0);
+      lu_solve(dl, dd, du, du2, pv, m, dtiny, z);
+      double nn = 0.0;
+      for (int i = 0; i < m; ++i) nn += z[i] * z[i];
+      const double inv = nn > 0.0 && isfinite(nn) ? 1.0 / sqrt(nn) : 0.0;
+      for (int i = 0; i < m; ++i) z[i] *= inv;
+    }
+    __syncthreads();
+    // group leaders, dealt to waves in task order
+    for (int t0 = 0; t0 < ntask; ++t0) {
+      if (t0 % kEW != wid || tpos[t0] >= nb || gdeg[t0] != t0 || !in_group(t0)) continue;
+      int cnt = 1;
+      while (t0 + cnt < bof[tblk[t0] + 1] && tpos[t0 + cnt] < nb && gdeg[t0 + cnt] == t0) ++cnt;
+      wave_mgs(Z, ldz, tpos, t0, cnt, bst[tblk[t0]], bst[tblk[t0] + 1]);
+    }
+    __syncthreads();
+  }
+  // close groups: Gram-Schmidt in block order (one wave per group)
+  for (int t0 = 0; t0 < ntask; ++t0) {
+    if (t0 % kEW != wid || tpos[t0] >= nb || gclo[t0] != t0) continue;
+    int cnt = 1;
+    while (t0 + cnt < bof[tblk[t0] + 1] && tpos[t0 + cnt] < nb && gclo[t0 + cnt] == t0) ++cnt;
+    if (cnt > 1) wave_mgs(Z, ldz, tpos, t0, cnt, bst[tblk[t0]], bst[tblk[t0] + 1]);
+  }
+  if (tid < ntask && tpos[tid] < nb) w[tpos[tid]] = tlam[tid];
+  (void)lane;
+  if (tid == 0) *info = 0;
+}
+
+// ---------------------------------------------------------------- back-transformation
+// Zc(:, j) = Q Zt(:, j) = H_0 (H_1 ( ... H_{n-2} Zt(:, j))), one wave per column.
+__global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__ A, long lda, int n,
+                                                     const double *__restrict__ tri,
+                                                     const double *__restrict__ Zt, int ldz,
+                                                     int nb, double2 *__restrict__ Zc, long ldc,
+                                                     const int *info_chol, const int *info_eig) {
+  if (*info_chol != 0 || *info_eig != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= nb) return;
+  const double2 *tau = reinterpret_cast<const double2 *>(tri + 2 * n);
+  double2 z[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = s * 64 + lane;
+    z[s] = make_double2(i < n ? Zt[i + (long)j * ldz] : 0.0, 0.0);
+  }
+  for (int k = n - 2; k >= 0; --k) {
+    const double2 t = tau[k];
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    const double2 *v = A + (long)k * lda;
+    double dr = 0.0, di = 0.0;   // v^H z
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int i = s * 64 + lane;
+      if (i > k && i < n) {
+        const double2 vi = v[i];
+        dr += vi.x * z[s].x + vi.y * z[s].y;
+        di += vi.x * z[s].y - vi.y * z[s].x;
+      }
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double2 c = cmul(t, make_double2(dr, di));
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int i = s * 64 + lane;
+      if (i > k && i < n) z[s] = csub(z[s], cmul(c, v[i]));
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = s * 64 + lane;
+    if (i < n) Zc[i + (long)j * ldc] = z[s];
+  }
+}
+
+}  // namespace
+
+size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN; }
+
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, hipStream_t s) {
+  if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kET), 0, s, S, ld, n, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double2 *B, long ldb,
+                       int ncol, double2 *X, long ldx, hipStream_t s) {
+  if (n < 1 || n > kEMaxN || ncol < 1) return hipErrorInvalidValue;
+  const dim3 grid((ncol + 3) / 4);
+  if (mode == 0)
+    hipLaunchKernelGGL(trsm_kernel<0>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
+  else if (mode == 1)
+    hipLaunchKernelGGL(trsm_kernel<1>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
+  else
+    hipLaunchKernelGGL(trsm_kernel<2>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
+  return hipGetLastError();
+}
+
+hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, const int *info_chol,
+                          hipStream_t s) {
+  if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A, lda, n, tri, info_chol);
+  return hipGetLastError();
+}
+
+hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z, int ldz,
+                         double *scr, int *info, const int *info_chol, hipStream_t s) {
+  if (n < 1 || n > kEMaxN || nb < 1 || nb > n || ldz < n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(trieig_kernel, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
+                     info_chol);
+  return hipGetLastError();
+}
+
+hipError_t launch_backtr(const double2 *A, long lda, int n, const double *tri, const double *Zt,
+                         int ldz, int nb, double2 *Zc, long ldc, const int *info_chol,
+                         const int *info_eig, hipStream_t s) {
+  if (n < 1 || n > kEMaxN || nb < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(backtr_kernel, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri, Zt, ldz,
+                     nb, Zc, ldc, info_chol, info_eig);
+  return hipGetLastError();
+}
+
+}  // namespace qeh

@@ -237,6 +237,28 @@ hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nspli
 // the real full-sphere projection (ignored otherwise).
 hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi);
 
+// ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
+// Reduced problems up to kEigMaxN; column-major double2 matrices.
+constexpr int kEigMaxN = 512;
+// S = L L^H in place (lower), one workgroup; info = 0 or the failing column + 1.
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, hipStream_t s);
+// X = L^-1 B (mode 0, T = L lower), X = L^-1 M^H with B = M (mode 1), or
+// X = U^-1 B (mode 2, T = U upper, backward); ncol columns, one wave each.
+hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double2 *B, long ldb,
+                       int ncol, double2 *X, long ldx, hipStream_t s);
+// A = Q T Q^H (Householder, in place); tri = d[n] | e[n] | tau (double2)[n].
+hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, const int *info_chol,
+                          hipStream_t s);
+// nb lowest eigenpairs of T: w[nb] ascending, Z (real, n x nb, ldz); scr holds
+// eig_scratch_doubles(n) doubles; info 0 / nonzero on failure.
+size_t eig_scratch_doubles(int n);
+hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z, int ldz,
+                         double *scr, int *info, const int *info_chol, hipStream_t s);
+// Zc = Q Zt (n x nb) through the reflectors stored in A by launch_tridiag.
+hipError_t launch_backtr(const double2 *A, long lda, int n, const double *tri, const double *Zt,
+                         int ldz, int nb, double2 *Zc, long ldc, const int *info_chol,
+                         const int *info_eig, hipStream_t s);
+
 // ---- Davidson helpers (dav_kernels.hip) ----------------------------------
 // norms[b] = || Q_b - eps_b P_b ||^2 over npw (double), one launch; gamma = 1:
 // half-sphere vectors, every G != 0 counted twice (G and -G).

@@ -78,10 +78,12 @@ struct Job {
   Request *req = nullptr;
   int k = 0;
   HostCell hc;
-  size_t ctx_bytes = 0, dav_bytes = 0, psi_bytes = 0, total = 0;
+  size_t ctx_bytes = 0, ctx64_bytes = 0, dav_bytes = 0, psi_bytes = 0, total = 0;
   size_t off = 0;
   int slot = -1;
   qeh_ctx *ctx = nullptr;
+  qeh_ctx *ctx64 = nullptr;   // mixed-form requests: FP64 context of the refinement phase
+  qeh_dav_opts opts{};
   std::unique_ptr<DavRun> run;
   bool started = false, finished = false, reaped = false;
   std::thread th;
@@ -208,7 +210,20 @@ bool start_job(qeh_server *s, Job *j) {
     j->st = rc;
     return false;
   }
-  double2 *psi = reinterpret_cast<double2 *>(base + j->ctx_bytes);
+  j->opts = j->req->opts;
+  j->opts.refine = nullptr;
+  if (j->ctx64_bytes) {
+    qeh_cell c64 = j->hc.cell;
+    c64.precision = QEH_FP64;
+    rc = qeh_ctx_create(&c64, base + j->ctx_bytes, j->ctx64_bytes, st, &j->ctx64);
+    if (rc != QEH_OK) {
+      j->st = rc;
+      return false;
+    }
+    j->opts.refine = j->ctx64;
+  }
+  char *after = base + j->ctx_bytes + j->ctx64_bytes;
+  double2 *psi = reinterpret_cast<double2 *>(after);
   // exactly the host copy's bytes (psi_bytes is that size rounded up to the
   // arena alignment; reading that far would run past the end of the vector)
   hipError_t e = hipMemcpyAsync(psi, j->hc.psi0.data(), sizeof(double) * j->hc.psi0.size(),
@@ -219,8 +234,8 @@ bool start_job(qeh_server *s, Job *j) {
   }
   j->eig.assign(j->req->nb, 0.0);
   j->run.reset(new DavRun());
-  rc = j->run->init(j->ctx, j->req->nb, psi, j->hc.cell.npw, j->eig.data(), &j->req->opts,
-                    base + j->ctx_bytes + j->psi_bytes, j->dav_bytes);
+  rc = j->run->init(j->ctx, j->req->nb, psi, j->hc.cell.npw, j->eig.data(), &j->opts,
+                    after + j->psi_bytes, j->dav_bytes);
   if (rc != QEH_OK) {
     j->st = rc;
     return false;
@@ -237,6 +252,8 @@ void finish_job(qeh_server *s, Job *j) {
   j->run.reset();
   if (j->ctx) qeh_ctx_destroy(j->ctx);
   j->ctx = nullptr;
+  if (j->ctx64) qeh_ctx_destroy(j->ctx64);
+  j->ctx64 = nullptr;
   std::lock_guard<std::mutex> lk(s->mu);
   free_range(s, j->off, j->total);
   s->slot_free[j->slot] = 1;
@@ -339,21 +356,31 @@ void server_loop(qeh_server *s) {
 qeh_status plan_job(const qeh_cell *cell, int nb, const qeh_dav_opts *o, Job *j) {
   qeh_status st = qeh_ctx_plan(cell, &j->ctx_bytes);
   if (st != QEH_OK) return st;
+  j->ctx64_bytes = 0;
+  if (cell->precision == QEH_MIXED) {
+    // mixed-form solves finish with H in FP64 (refinement phase)
+    qeh_cell c64 = *cell;
+    c64.precision = QEH_FP64;
+    st = qeh_ctx_plan(&c64, &j->ctx64_bytes);
+    if (st != QEH_OK) return st;
+    j->ctx64_bytes = align_up(j->ctx64_bytes);
+  }
   // the Davidson plan needs only npw and the Gamma flag from a context
   qeh_ctx probe;
   probe.npw = cell->npw;
   probe.gamma = cell->gamma ? 1 : 0;
   int nvecx, maxiter;
   double rtol;
-  st = dav_check_opts(&probe, nb, o, &nvecx, &rtol, &maxiter);
+  bool own = false;
+  st = dav_check_opts(&probe, nb, o, &nvecx, &rtol, &maxiter, &own);
   if (st != QEH_OK) return st;
   DavLayout L;
-  st = dav_layout(&probe, nb, nvecx, &L);
+  st = dav_layout(&probe, nb, nvecx, own, &L);
   if (st != QEH_OK) return st;
   j->ctx_bytes = align_up(j->ctx_bytes);
   j->psi_bytes = align_up(16 * (size_t)nb * cell->npw);
   j->dav_bytes = align_up(L.total);
-  j->total = j->ctx_bytes + j->psi_bytes + j->dav_bytes;
+  j->total = j->ctx_bytes + j->ctx64_bytes + j->psi_bytes + j->dav_bytes;
   return QEH_OK;
 }
 
@@ -438,6 +465,7 @@ qeh_status qeh_submit(qeh_server *s, const qeh_cell *cells, int nk, int nb, cons
   r->nk = nk;
   r->nb = nb;
   if (opts) r->opts = *opts;
+  r->opts.refine = nullptr;   // the server attaches its own FP64 context per job
   r->t[0] = now_s(s->t0);
   size_t off = 0;
   for (int k = 0; k < nk; ++k) {

@@ -1,7 +1,7 @@
 """Write the stored expected values under tests/golden/ from the FP64 oracle.
 
 Calls only ``oracle`` and the seeded generator ``cellgen``; nothing from the
-HIP library.  Usage: python tests/golden/make_golden.py [c2] [c3] [c5]
+HIP library.  Usage: python tests/golden/make_golden.py [c2] [c3] [c5] [served]
 
 The 256- and 512-atom cells are solved for their lowest 64 and 32 bands only
 (an oracle H application there takes seconds per band); the GPU solves all
@@ -65,10 +65,39 @@ def low_eigs(name: str, nb: int, header: str):
     print("wrote", path, info["iters"], info["band_applies"], "%.0f s" % dt, flush=True)
 
 
+# Served requests whose eigenvalues the serving test checks: (atoms, ecutwfc,
+# k-points, cell seed), cells from the served-trace generator with host-built
+# projectors (the s+p Gaussian form), nb = 2 atoms.
+SERVED = [(128, 30.0, 1, 501), (64, 30.0, 2, 502), (96, 25.0, 2, 503), (40, 30.0, 3, 504),
+          (16, 20.0, 4, 505)]
+
+
+def served_eigs():
+    import json
+    out = []
+    t = time.time()
+    for nat, ecut, nk, seed in SERVED:
+        ks = []
+        for k in range(nk):
+            cell = cellgen.random_served_cell(nat, ecut, k, seed)
+            ks.append([float(x) for x in oracle.dense_eigs(cell, cell.nbnd)])
+            print("served", nat, ecut, k, cell.npw, "%.0f s" % (time.time() - t), flush=True)
+        out.append(dict(nat=nat, ecutwfc=ecut, nk=nk, seed=seed, eigs=ks))
+    path = os.path.join(HERE, "served_eigs.json")
+    with open(path, "w") as f:
+        json.dump(dict(source="LAPACK eigenvalues of the FP64 oracle's dense H "
+                              "(oracle.dense_eigs) of each k-point cell of "
+                              "cellgen.random_served_cell(nat, ecutwfc, k, seed), host projectors",
+                       requests=out), f, indent=1)
+    print("wrote", path, "%.0f s" % (time.time() - t))
+
+
 if __name__ == "__main__":
     which = sys.argv[1:] or ["c2"]
     if "c2" in which:
         c2_eigs()
+    if "served" in which:
+        served_eigs()
     if "c3" in which:
         low_eigs("c3", 64, "# 256-atom cell (cubic a=32.6 bohr, jittered FCC sites, k = 0, ecutwfc 40 Ry,\n"
                  "# box 135^3, 2048 projectors, seed 2104):\n")

@@ -96,6 +96,14 @@ def test_p1_free_electron_gamma_c1():
     assert np.abs(eps - ref).max() < 1e-10
 
 
+def test_p1_dense_eigs_free_electron_shells():
+    # the dense route at V = 0, no projectors: the lowest |k+G|^2 shells of C1
+    cell = _c1(vzero=True, nobeta=True)
+    s = 0.39478417604357434
+    ref = np.array([0.0] + [s] * 6 + [2 * s] * 9)
+    assert np.abs(oracle.dense_eigs(cell, 16) - ref).max() < 1e-12
+
+
 def test_p1_free_electron_kpoint_c2_shells():
     # k = (1/4,1/4,1/4) 2pi/a, a = 20.52: |f+m|^2 = 3/16, 11/16 (x3), 19/16 (x3),
     # 27/16 (x1), 35/16 (x3) ... in units of (2 pi / a)^2.
