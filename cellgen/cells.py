@@ -18,6 +18,10 @@ wave exp(i q.r) has kinetic energy |q|^2):
   shape (N3, N2, N1) with x fastest.
 * ``beta`` is (nkb, npw) complex128, plane-wave index fastest, and already
   contains 1/sqrt(Omega) and the structure phase exp(-i (k+G).tau).
+* ``qmat`` (optional, ``overlap=True``) holds per-atom q blocks of the overlap
+  S = 1 + sum_ij |beta_i> q_ij <beta_j| in the layout of ``dmat``, one
+  U[0.05, 0.5] value per (atom, channel) shared across m, drawn from the
+  stream seeded with seed + 1 (q >= 0, so S is positive definite).
 * ``dmat`` holds the per-atom Hermitian D blocks (nproj_a x nproj_a each,
   row-major) concatenated in atom order, complex128, in Ry.
 """
@@ -67,6 +71,9 @@ class Cell:
     projgen: dict = None
     # True: a k = 0 cell stored over the half sphere (see ``gamma_half``)
     gamma: bool = False
+    # per-atom Hermitian q blocks of the overlap S = 1 + sum |beta> q <beta|
+    # (same layout as dmat); None: S = 1 (norm-conserving)
+    qmat: np.ndarray = None
 
     @property
     def npw(self) -> int:
@@ -341,7 +348,8 @@ def _spec(name: str) -> dict:
 
 def make_cell(name: str, *, seed: int = 2104, with_beta: bool = True, **override) -> Cell:
     """Build a named cell.  ``override`` may replace any spec entry (e.g. fft,
-    ecutwfc, nbnd, block, kfrac, lattice, frac, proj, vzero=True, nobeta=True)."""
+    ecutwfc, nbnd, block, kfrac, lattice, frac, proj, vzero=True, nobeta=True,
+    overlap=True for the q blocks of a non-identity overlap)."""
     spec = _spec(name) if name in ("c1", "c2", "c3", "c5") else {}
     spec.update(override)
     lattice = np.asarray(spec["lattice"], dtype=np.float64)
@@ -380,11 +388,15 @@ def make_cell(name: str, *, seed: int = 2104, with_beta: bool = True, **override
         nproj = np.full(nat, per_atom, dtype=np.int32)
         beta = beta_matrix(lattice, kpt, miller, pos, proj) if with_beta else None
         dmat = _dmat_blocks(nat, proj, dvals)
+    qmat = None
+    if spec.get("overlap") and not spec.get("nobeta"):
+        qvals = np.random.default_rng(seed + 1).uniform(0.05, 0.5, size=(nat, nchan))
+        qmat = _dmat_blocks(nat, proj, qvals)
     return Cell(name=name, lattice=lattice, fft=fft, kpt=kpt,
                 ecutwfc=float(spec["ecutwfc"]), ecutrho=float(ecutrho), positions=pos,
                 miller=miller, vloc=vloc, nproj=nproj, beta=beta, dmat=dmat,
                 nbnd=int(spec["nbnd"]), block=int(spec.get("block", spec["nbnd"])),
-                proj_set=proj, meta=dict(seed=seed))
+                proj_set=proj, meta=dict(seed=seed), qmat=qmat)
 
 
 def make_psi0(npw: int, nb: int, seed: int = 10502) -> np.ndarray:

@@ -111,7 +111,18 @@ typedef struct {
                              device from these tables (and diag(H) with it);
                              ignored when beta is given                        */
   int gamma;              /* 1: real wavefunctions at k = 0 (see below); 0: general k */
+  const double *qmat;     /* optional, complex, layout of dmat: per-atom
+                             Hermitian q blocks of the overlap
+                             S = 1 + sum_ij |beta_i> q_ij <beta_j|; NULL: S = 1 */
 } qeh_cell;
+
+/* The overlap operator (listed among the GPU-ported kernels, section
+ * "Evolution of the GPU-enabled version"; ultrasoft / PAW form): with qmat
+ * set, a context applies S with qeh_apply_s, and qeh_davidson solves the
+ * generalized problem H psi = eps S psi (basis V, H V and S V; reduced pair
+ * V^H H V, V^H S V; residuals H psi - eps S psi; S-orthonormal Ritz vectors,
+ * psi^H S psi = I).  S must be positive definite (q >= 0 suffices); Gamma
+ * cells need real q blocks. */
 
 /* Gamma-point cells (gamma = 1): the real-wavefunction case ("k = 0 only
  * sampling" of section "Evolution of the GPU-enabled version").  With
@@ -157,6 +168,13 @@ qeh_status qeh_ctx_destroy(qeh_ctx *ctx);
  * without waiting.  Result is independent of how bands are grouped. */
 qeh_status qeh_apply_h(qeh_ctx *ctx, int nb, const double *psi, int ldpsi,
                        double *hpsi, int ldh);
+
+/* S psi for nb bands (same layout rules as qeh_apply_h): spsi = psi +
+ * beta q beta^H psi, with beta^H psi and the product in the context's
+ * precision (single precision in QEH_MIXED, accumulated onto the FP64 psi).
+ * A context without qmat copies psi.  Enqueued on the context stream. */
+qeh_status qeh_apply_s(qeh_ctx *ctx, int nb, const double *psi, int ldpsi, double *spsi,
+                       int ldsp);
 
 /* The three parts of H separately (same layout rules as qeh_apply_h):
  * part 0 = kinetic + local (the FFT path), part 1 = nonlocal only. */
@@ -242,9 +260,11 @@ qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *b
  * single precision limits how small the residual can get, and the solve runs
  * in two phases when refine is set:
  *   1. H applied in single precision (the context's form) until every band
- *      has ||r|| <= thr or a residual that has not dropped by 10% in 3
- *      iterations (the single-precision floor);
- *   2. a restart from the Ritz vectors with H applied in FP64 through refine
+ *      has ||r|| <= thr, or a residual that has not dropped by 10% in 3
+ *      iterations, or a Ritz value that moved by <= 1e-8 Ry in one (the
+ *      single-precision floor);
+ *   2. the same basis with H V recomputed, and H applied from then on, in
+ *      FP64 through refine
  *      (a QEH_FP64 context of the same cell: same Miller list, k, V,
  *      projectors and D, on the same HIP stream, with the same npw, box,
  *      projector count and Gamma flag) until every band has ||r|| <= thr,
@@ -252,7 +272,8 @@ qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *b
  *      FP64 form's at residual thr.
  * Without refine the mixed form stops at phase 1's rules, with the floor
  * accepted only while ||r|| <= 10 thr (3 iterations without a 10% drop) or
- * <= 100 thr (5 iterations). */
+ * <= 100 thr (5 iterations, or a settled Ritz value); its eigenvalue error is
+ * then bounded by ||r||^2 / gap with ||r|| up to 100 thr. */
 enum { QEH_SUBSPACE_AUTO = 0, QEH_SUBSPACE_OWN = 1, QEH_SUBSPACE_ROCSOLVER = 2 };
 typedef struct {
   int nvecx;

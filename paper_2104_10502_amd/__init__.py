@@ -58,7 +58,8 @@ class QehCell(ctypes.Structure):
                 ("miller", _c_int_p), ("vloc", _c_dbl_p), ("nat", ctypes.c_int),
                 ("nproj", _c_int_p), ("beta", _c_dbl_p), ("dmat", _c_dbl_p),
                 ("precision", ctypes.c_int), ("block", ctypes.c_int),
-                ("projgen", ctypes.POINTER(QehProjgen)), ("gamma", ctypes.c_int)]
+                ("projgen", ctypes.POINTER(QehProjgen)), ("gamma", ctypes.c_int),
+                ("qmat", _c_dbl_p)]
 
 
 class DavOpts(ctypes.Structure):
@@ -84,6 +85,7 @@ _SIGS = {
                         ctypes.POINTER(_vp)], ctypes.c_int),
     "qeh_ctx_destroy": ([_vp], ctypes.c_int),
     "qeh_apply_h": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int], ctypes.c_int),
+    "qeh_apply_s": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _vp, ctypes.c_int], ctypes.c_int),
     "qeh_apply_h_part": ([_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp,
                           ctypes.c_int], ctypes.c_int),
     "qeh_davidson_plan": ([_vp, ctypes.c_int, ctypes.POINTER(DavOpts), _sz_p], ctypes.c_int),
@@ -179,7 +181,7 @@ def _projgen_struct(pg, keep):
 
 
 def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block, keep,
-                 projgen=None, gamma=False):
+                 projgen=None, gamma=False, qmat=None):
     """Fill a QehCell from host arrays; ``keep`` collects the arrays it points to.
     With beta None and a projgen dict, the library builds beta on the device."""
     k = dict(miller=np.ascontiguousarray(miller, dtype=np.int32),
@@ -204,6 +206,9 @@ def _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, 
     if beta is None and projgen is not None:
         c.projgen = ctypes.pointer(_projgen_struct(projgen, keep))
     c.gamma = 1 if gamma else 0
+    if qmat is not None:
+        k["qmat"] = np.ascontiguousarray(qmat, dtype=np.complex128)
+        c.qmat = k["qmat"].ctypes.data_as(_c_dbl_p)
     return c
 
 
@@ -318,7 +323,8 @@ class Server:
             arr[i] = _cell_struct(c.lattice, c.fft, c.kpt, c.miller, c.vloc, c.nproj,
                                   None if pg is not None else c.beta, c.dmat, precision,
                                   block or nb, keep, projgen=pg,
-                                  gamma=getattr(c, "gamma", False))
+                                  gamma=getattr(c, "gamma", False),
+                                  qmat=getattr(c, "qmat", None))
         psi = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).ravel()
                                                    for p in psi0s]))
         o = DavOpts(int(nvecx), float(rtol), int(maxiter))
@@ -369,7 +375,8 @@ class Context:
 
     Inputs are plain host arrays: lattice (3,3) rows a_i, fft (N1,N2,N3), kpt (3,),
     miller (npw,3) int, vloc (N3,N2,N1) float64, nproj (nat,) int,
-    beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128.  With beta None,
+    beta (nkb,npw) complex128, dmat (sum nproj^2,) complex128, optional qmat (same
+    layout as dmat: the overlap's q blocks, S != 1).  With beta None,
     ``projgen`` (a dict: tau, ityp, nchan, lchan, dq, tab) describes the radial
     tables from which the library builds beta on the device.  ``gamma=True``:
     real wavefunctions at k = 0, miller (and psi, beta) over the half sphere.
@@ -377,12 +384,12 @@ class Context:
 
     def __init__(self, lattice, fft, kpt, miller, vloc, nproj, beta, dmat, *,
                  precision=QEH_FP64, block=64, device=None, stream=None, projgen=None,
-                 gamma=False):
+                 gamma=False, qmat=None):
         torch = _torch()
         self.device = torch.device(device if device is not None else "cuda")
         keep = []
         c = _cell_struct(lattice, fft, kpt, miller, vloc, nproj, beta, dmat, precision, block,
-                         keep, projgen=projgen, gamma=gamma)
+                         keep, projgen=projgen, gamma=gamma, qmat=qmat)
         self._keep = keep
         self._cell = c
         nbytes = ctypes.c_size_t()
@@ -407,6 +414,7 @@ class Context:
     def from_cell(cls, cell, **kw):
         pg = kw.get("projgen")
         kw.setdefault("gamma", getattr(cell, "gamma", False))
+        kw.setdefault("qmat", getattr(cell, "qmat", None))
         return cls(cell.lattice, cell.fft, cell.kpt, cell.miller, cell.vloc, cell.nproj,
                    None if pg is not None else cell.beta, cell.dmat, **kw)
 
@@ -418,6 +426,17 @@ class Context:
         if psi.dim() != 2 or psi.shape[1] < self.npw or psi.stride(1) != 1:
             raise ValueError("psi must be (nb, >= npw) with unit stride along G")
         return psi
+
+    def apply_s(self, psi, out=None):
+        """S psi (the overlap; a copy of psi without q blocks)."""
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        if out is None:
+            out = torch.empty((nb, self.npw), dtype=torch.complex128, device=psi.device)
+        _check(_lib.qeh_apply_s(self._h, nb, _vp(psi.data_ptr()), psi.stride(0),
+                                _vp(out.data_ptr()), out.stride(0)), "qeh_apply_s")
+        return out
 
     def apply_h(self, psi, out=None, part=None):
         torch = _torch()

@@ -67,5 +67,49 @@ def build(verbose: bool = False) -> str:
     return OUT
 
 
+def build_host_sanitized(verbose: bool = False) -> str:
+    """A copy of the library whose host C++ (validation, planning, maps,
+    request copies, the Davidson state machine) is built with AddressSanitizer
+    and UndefinedBehaviorSanitizer, linked with the regular device objects:
+    _build/asan/libqeh_asan.so, for CPU tests of the host code.  The device
+    code is not instrumented."""
+    out_dir = os.path.join(BUILD, "asan")
+    os.makedirs(out_dir, exist_ok=True)
+    hip_objs = []
+    for src in HIP_SOURCES:
+        o = os.path.join(BUILD, src + ".o")
+        if not os.path.exists(o):
+            o = _compile(src)
+        hip_objs.append(o)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-g"]
+
+    def comp(src):
+        obj = os.path.join(out_dir, src + ".o")
+        cmd = [_hipcc()] + COMMON + ["--offload-arch=gfx950", "-D__HIP_PLATFORM_AMD__"] + san + \
+            ["-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr))
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=len(CPP_SOURCES)) as ex:
+        host_objs = list(ex.map(comp, CPP_SOURCES))
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    out = os.path.join(out_dir, "libqeh_asan.so")
+    # linked by the LLVM driver (not hipcc) so that the shared sanitizer
+    # runtime of the compiler that instrumented the objects is used
+    cmd = [os.path.join(rocm, "llvm", "bin", "clang++"), "-shared", "-fPIC",
+           "-fsanitize=address,undefined", "-shared-libsan", "-o", out] + host_objs + hip_objs + \
+        ["-L" + os.path.join(rocm, "lib"), "-lrocsolver", "-lrocblas", "-lamdhip64",
+         "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr))
+    if verbose:
+        print("built", out)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)

@@ -225,6 +225,17 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
       set_error("dmat has a non-finite value");
       return QEH_ERR_NUMERIC;
     }
+  if (c->qmat) {
+    if (nkb == 0) return invalid("qmat given without projectors");
+    for (long i = 0; i < 2 * nd; ++i)
+      if (!std::isfinite(c->qmat[i])) {
+        set_error("qmat has a non-finite value");
+        return QEH_ERR_NUMERIC;
+      }
+    if (c->gamma)
+      for (long i = 0; i < nd; ++i)
+        if (c->qmat[2 * i + 1] != 0.0) return invalid("gamma cells need a real q");
+  }
   if (c->gamma) {
     // real projectors: beta_i(G = 0) real, D real symmetric
     for (long i = 0; i < nd; ++i)
@@ -240,7 +251,7 @@ qeh_status validate(const qeh_cell *c, HostMaps *hm) {
 // Arena layout, shared by plan and create.
 struct Layout {
   size_t off_stick_off, off_gmap, off_tidx, off_tidx_dit, off_xin, off_kin, off_hdiag, off_vs,
-      off_tw, off_beta, off_dmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part,
+      off_tw, off_beta, off_dmat, off_qmat, off_pj0, off_pnb, off_pdoff, off_chunk, off_sbuf, off_part,
       off_ps, off_big, off_colstart, off_psi32, off_pgen, off_gbuf;
   size_t total;
 };
@@ -416,6 +427,7 @@ Layout layout(const qeh_cell *c, const HostMaps &hm, const Geometry &g) {
   L.off_tw = bump(&cur, cs * (size_t)(c->fft[0] + c->fft[1] + c->fft[2]));
   L.off_beta = bump(&cur, cs * (size_t)g.nkb * c->npw);
   L.off_dmat = bump(&cur, 16 * (size_t)g.nd);
+  L.off_qmat = bump(&cur, c->qmat ? 16 * (size_t)g.nd : 0);
   L.off_pj0 = bump(&cur, 4 * (size_t)g.nkb);
   L.off_pnb = bump(&cur, 4 * (size_t)g.nkb);
   L.off_pdoff = bump(&cur, 4 * (size_t)g.nkb);
@@ -550,6 +562,8 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->d.tw = A + L.off_tw;
   c->d.beta = A + L.off_beta;
   c->d.dmat = reinterpret_cast<double2 *>(A + L.off_dmat);
+  c->has_q = cell->qmat ? 1 : 0;
+  c->d.qmat = cell->qmat ? reinterpret_cast<double2 *>(A + L.off_qmat) : nullptr;
   c->d.pj0 = reinterpret_cast<int *>(A + L.off_pj0);
   c->d.pnb = reinterpret_cast<int *>(A + L.off_pnb);
   c->d.pdoff = reinterpret_cast<int *>(A + L.off_pdoff);
@@ -674,6 +688,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   up(c->d.pdoff, pdoff.data(), 4 * pdoff.size());
   up(c->d.chunk, chunk.data(), 4 * chunk.size());
   up(c->d.dmat, cell->dmat, 16 * (size_t)g.nd);
+  if (cell->qmat) up(c->d.qmat, cell->qmat, 16 * (size_t)g.nd);
   std::vector<float> f32;
   if (f64) {
     up(c->d.vs, vs64.data(), 8 * nfft);
@@ -886,6 +901,74 @@ qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldp
   return QEH_OK;
 }
 
+// S psi = psi + beta q beta^H psi, per block of the context's block size:
+// copy psi, beta^H psi (split-K), q scaling (the D-scaling kernel with the q
+// blocks), beta qs accumulated onto the copy.
+qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double *spsi,
+                        int ldsp) {
+  if (!c) return invalid("ctx is null");
+  if (nb < 0) return invalid("nb < 0");
+  if (nb == 0) return QEH_OK;
+  if (!psi || !spsi) return invalid("psi / spsi null");
+  if (ldpsi < c->npw || ldsp < c->npw) return invalid("leading dimension < npw");
+  if (psi == spsi) return invalid("psi and spsi must not overlap");
+  const double2 *p = reinterpret_cast<const double2 *>(psi);
+  double2 *o = reinterpret_cast<double2 *>(spsi);
+  hipError_t e = launch_copy_rows(p, ldpsi, o, ldsp, c->npw, nb, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "S psi copy");
+  if (!c->has_q || c->nkb == 0) return QEH_OK;
+  const bool f64 = c->prec == QEH_FP64;
+  for (int b0 = 0; b0 < nb; b0 += c->block) {
+    const int nbk = std::min(c->block, nb - b0);
+    const double2 *pb = p + (size_t)b0 * ldpsi;
+    GemmDesc g1{};
+    g1.A = pb;
+    g1.lda = ldpsi;
+    g1.ta = T_D2;
+    g1.B = c->d.beta;
+    g1.ldb = c->npw;
+    g1.tb = f64 ? T_D2 : T_F2;
+    g1.bmode = 0;
+    g1.C = c->d.part;
+    g1.ldc = c->nkb;
+    g1.tc = f64 ? T_D2 : T_F2;
+    g1.M = nbk;
+    g1.N = c->nkb;
+    g1.K = c->npw;
+    g1.conjB = 1;
+    g1.nsplit = c->nsplit;
+    g1.kchunk = c->kchunk;
+    g1.split_stride = (long)c->block * c->nkb;
+    g1.prec = f64 ? G_F64 : G_F32;
+    g1.rmode = c->gamma ? 1 : 0;
+    e = launch_cgemm(g1, c->stream);
+    if (e == hipSuccess) e = launch_dscale(c, nbk, pb, ldpsi, c->d.qmat);
+    if (e != hipSuccess) return hip_fail(e, "S psi projections");
+    GemmDesc g3{};
+    g3.A = c->d.ps;
+    g3.lda = c->nkb;
+    g3.ta = f64 ? T_D2 : T_F2;
+    g3.B = c->d.beta;
+    g3.ldb = c->npw;
+    g3.tb = f64 ? T_D2 : T_F2;
+    g3.bmode = 1;
+    g3.C = o + (size_t)b0 * ldsp;
+    g3.ldc = ldsp;
+    g3.tc = T_D2;
+    g3.M = nbk;
+    g3.N = c->npw;
+    g3.K = c->nkb;
+    g3.accumulate = 1;
+    g3.nsplit = 1;
+    g3.kchunk = c->nkb;
+    g3.prec = f64 ? G_F64 : G_F32;
+    g3.rmode = c->gamma ? 2 : 0;
+    e = launch_cgemm(g3, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "S psi product");
+  }
+  return QEH_OK;
+}
+
 // ---- charge density (charge density generation among the ported kernels,
 // section "Evolution of the GPU-enabled version")
 struct DensityWork {
@@ -1005,6 +1088,11 @@ extern "C" {
 qeh_status qeh_apply_h(qeh_ctx *c, int nb, const double *psi, int ldpsi, double *hpsi,
                        int ldh) {
   return apply_h_impl(c, 2, nb, psi, ldpsi, hpsi, ldh);
+}
+
+qeh_status qeh_apply_s(qeh_ctx *c, int nb, const double *psi, int ldpsi, double *spsi,
+                       int ldsp) {
+  return apply_s_impl(c, nb, psi, ldpsi, spsi, ldsp);
 }
 
 qeh_status qeh_apply_h_part(qeh_ctx *c, int part, int nb, const double *psi, int ldpsi,

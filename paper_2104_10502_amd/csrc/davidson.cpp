@@ -36,6 +36,8 @@
 namespace qeh {
 qeh_status apply_h_impl(qeh_ctx *c, int part, int nb, const double *psi, int ldpsi,
                         double *hpsi, int ldh);
+qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double *spsi,
+                        int ldsp);
 
 namespace {
 
@@ -273,7 +275,7 @@ qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *
       return QEH_ERR_INVALID;
     }
     if (r->npw != c->npw || r->gamma != c->gamma || r->n1 != c->n1 || r->n2 != c->n2 ||
-        r->n3 != c->n3 || r->nkb != c->nkb || r->nat != c->nat) {
+        r->n3 != c->n3 || r->nkb != c->nkb || r->nat != c->nat || r->has_q != c->has_q) {
       set_error("refine: context of a different cell (npw, box, projectors or Gamma flag)");
       return QEH_ERR_INVALID;
     }
@@ -304,6 +306,9 @@ qeh_status dav_layout(const qeh_ctx *c, int nb, int nvecx, bool own, DavLayout *
   L->idx = bump2(&cur, 4 * (size_t)nb);
   L->info = bump2(&cur, 16);
   L->flag = bump2(&cur, 4);
+  // generalized problem: S V and S P beside V and P
+  L->U = bump2(&cur, c->has_q ? row * nvecx : 0);
+  L->SP = bump2(&cur, c->has_q ? row * nb : 0);
   L->own = own;
   if (own) {
     L->solver_bytes = 0;
@@ -381,6 +386,9 @@ qeh_status DavRun::init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig
   idx_d_ = reinterpret_cast<int *>(w + L_.idx);
   info_d_ = reinterpret_cast<int *>(w + L_.info);
   flag_d_ = reinterpret_cast<int *>(w + L_.flag);
+  gen_ = c->has_q != 0;
+  U_ = gen_ ? reinterpret_cast<double2 *>(w + L_.U) : nullptr;
+  SP_ = gen_ ? reinterpret_cast<double2 *>(w + L_.SP) : nullptr;
   tri_ = reinterpret_cast<double *>(w + L_.tri);
   Zt_ = reinterpret_cast<double *>(w + L_.Zt);
   escr_ = reinterpret_cast<double *>(w + L_.escr);
@@ -473,13 +481,23 @@ void DavRun::restart_from_ritz() {
   ok(launch_copy_rows(P_, npw_, V_, npw_, npw_, nb_, s));
   nbase_ = nb_;
   if (phase64_) {
-    const qeh_status st = hpsi(V_, W_, nb_);
+    qeh_status st = hpsi(V_, W_, nb_);
+    if (st == QEH_OK && gen_) st = spsi(V_, U_, nb_);
     if (st != QEH_OK && result_ == QEH_OK) result_ = st;
   } else {
     ok(launch_copy_rows(Q_, npw_, W_, npw_, npw_, nb_, s));
+    if (gen_) ok(launch_copy_rows(SP_, npw_, U_, npw_, npw_, nb_, s));
   }
   ok(reduce_cols(c_, V_, nb_, W_, nb_, Hr_, nvecx_, part_));
-  ok(reduce_cols(c_, V_, nb_, V_, nb_, Sr_, nvecx_, part_));
+  ok(reduce_cols(c_, V_, nb_, gen_ ? U_ : V_, nb_, Sr_, nvecx_, part_));
+}
+
+qeh_status DavRun::spsi(const double2 *x, double2 *y, int n) {
+  ev_h_.start(c_->stream);
+  qeh_status r = apply_s_impl(phase64_ ? c64_ : c_, n, reinterpret_cast<const double *>(x), npw_,
+                              reinterpret_cast<double *>(y), npw_);
+  ev_h_.stop(c_->stream);
+  return r;
 }
 
 bool DavRun::fail_device(const char *what) {
@@ -515,13 +533,14 @@ bool DavRun::advance() {
           return true;
         }
         qeh_status st = hpsi(V_, W_, nb);
+        if (st == QEH_OK && gen_) st = spsi(V_, U_, nb);
         if (st != QEH_OK) {
           result_ = st;
           phase_ = kDone;
           return true;
         }
         ok(reduce_cols(c_, V_, nb, W_, nb, Hr_, nvecx, part_));
-        ok(reduce_cols(c_, V_, nb, V_, nb, Sr_, nvecx, part_));
+        ok(reduce_cols(c_, V_, nb, gen_ ? U_ : V_, nb, Sr_, nvecx, part_));
         nbase_ = nb;
         phase_ = kRR;
         break;
@@ -644,7 +663,9 @@ bool DavRun::advance() {
         ev_s_.start(s);
         ok(rotate(c_, Y_, nvecx, nbase_, nb, V_, P_));
         ok(rotate(c_, Y_, nvecx, nbase_, nb, W_, Q_));
-        ok(launch_resid_norms(P_, Q_, npw, npw, nb, eps_d_, norms_d_, c_->gamma, s));
+        if (gen_) ok(rotate(c_, Y_, nvecx, nbase_, nb, U_, SP_));
+        // residuals H psi - eps S psi (S psi = psi for S = 1)
+        ok(launch_resid_norms(gen_ ? SP_ : P_, Q_, npw, npw, nb, eps_d_, norms_d_, c_->gamma, s));
         ev_s_.stop(s);
         have_ritz_ = true;
         ok(hipMemcpyAsync(h_eps_, eps_d_, 8 * (size_t)nb, hipMemcpyDeviceToHost, s));
@@ -669,16 +690,19 @@ bool DavRun::advance() {
           } else {
             ++stall_[b];
           }
-          // mixed form, single-precision phase: the floor stops the residual.
-          // With a refinement context a band is handed over once its residual
-          // has not dropped by 10% in 3 iterations; without one it is
-          // accepted at the floor while that floor is <= 10x the threshold
-          // (3 iterations) or <= 100x (5: the floor grows with the cutoff and
-          // the number of projectors)
+          // mixed form, single-precision phase: the floor stops the residual
+          // (noise at the floor can keep resetting the stall count, so a Ritz
+          // value that has settled to 1e-8 Ry counts as stalled too).  With a
+          // refinement context a stalled band is handed over to the FP64
+          // phase, whatever its residual; without one it is accepted at the
+          // floor only while that floor is <= 10x the threshold (3 iterations)
+          // or <= 100x (5 iterations, or a settled Ritz value): the floor
+          // grows with the cutoff and the number of projectors
           if (mixed_ && !phase64_) {
-            if (c64_ && stall_[b] >= 3) conv = true;
+            const bool settled = std::fabs(h_eps_[b] - eps_prev_[b]) <= 1e-8;
+            if (c64_ && (stall_[b] >= 3 || settled)) conv = true;
             if (!c64_ && stall_[b] >= 3 && r <= 10.0 * thr_) conv = true;
-            if (!c64_ && stall_[b] >= 5 && r <= 100.0 * thr_) conv = true;
+            if (!c64_ && (stall_[b] >= 5 || settled) && r <= 100.0 * thr_) conv = true;
           }
           if (!conv) h_idx_[nc++] = b;
         }
@@ -692,18 +716,25 @@ bool DavRun::advance() {
           result_ = QEH_ERR_NOT_CONVERGED;
         }
         if (nc == 0 && result_ == QEH_OK && c64_ && !phase64_) {
-          // single precision has done what it can: continue with H in FP64
-          // from the current Ritz vectors until the FP64 residuals meet thr
+          // single precision has done what it can: continue on the same basis
+          // with H (and S) applied in FP64 until the FP64 residuals meet thr.
+          // W = H V is recomputed for every basis vector (the subspace is
+          // kept, only the operator's rounding changes); Sr = V^H V stands
+          // unless S != 1, whose S V is recomputed as well
           phase64_ = true;
           for (int b = 0; b < nb; ++b) {
             best_res_[b] = INFINITY;
             stall_[b] = 0;
           }
-          restart_from_ritz();
-          if (result_ != QEH_OK) {
+          qeh_status st = hpsi(V_, W_, nbase_);
+          if (st == QEH_OK && gen_) st = spsi(V_, U_, nbase_);
+          if (st != QEH_OK) {
+            result_ = st;
             phase_ = kDone;
             return true;
           }
+          ok(reduce_cols(c_, V_, nbase_, W_, nbase_, Hr_, nvecx, part_));
+          if (gen_) ok(reduce_cols(c_, V_, nbase_, U_, nbase_, Sr_, nvecx, part_));
           phase_ = kRR;
           break;
         }
@@ -717,13 +748,16 @@ bool DavRun::advance() {
           ++restarts_;
           ok(launch_copy_rows(P_, npw, V_, npw, npw, nb, s));
           ok(launch_copy_rows(Q_, npw, W_, npw, npw, nb, s));
+          if (gen_) ok(launch_copy_rows(SP_, npw, U_, npw, npw, nb, s));
           ok(launch_set_diag(Hr_, nvecx, nb, eps_d_, s));
           ok(launch_set_diag(Sr_, nvecx, nb, nullptr, s));
           nbase_ = nb;
         }
-        ok(launch_precond(P_, Q_, npw, npw, idx_d_, nc, eps_d_, c_->d.hdiag,
+        ok(launch_precond(gen_ ? SP_ : P_, Q_, npw, npw, idx_d_, nc, eps_d_, c_->d.hdiag,
                           V_ + (size_t)nbase_ * npw, npw, c_->gamma, s));
         qeh_status st = hpsi(V_ + (size_t)nbase_ * npw, W_ + (size_t)nbase_ * npw, nc);
+        if (st == QEH_OK && gen_)
+          st = spsi(V_ + (size_t)nbase_ * npw, U_ + (size_t)nbase_ * npw, nc);
         if (st != QEH_OK) {
           result_ = st;
           phase_ = kDone;
@@ -732,7 +766,7 @@ bool DavRun::advance() {
         ev_s_.start(s);
         ok(reduce_cols(c_, V_, nbase_ + nc, W_ + (size_t)nbase_ * npw, nc,
                        Hr_ + (size_t)nbase_ * nvecx, nvecx, part_));
-        ok(reduce_cols(c_, V_, nbase_ + nc, V_ + (size_t)nbase_ * npw, nc,
+        ok(reduce_cols(c_, V_, nbase_ + nc, (gen_ ? U_ : V_) + (size_t)nbase_ * npw, nc,
                        Sr_ + (size_t)nbase_ * nvecx, nvecx, part_));
         ok(launch_herm_fill(Hr_, nvecx, nbase_, nbase_ + nc, s));
         ok(launch_herm_fill(Sr_, nvecx, nbase_, nbase_ + nc, s));

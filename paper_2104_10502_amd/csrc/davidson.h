@@ -16,7 +16,7 @@ namespace qeh {
 
 struct DavLayout {
   size_t V, W, P, Q, Hr, Sr, Hw, Sw, X, Lc, LcH, Y, part, eps, E, norms, idx, info, flag,
-      solver, tri, Zt, escr;
+      solver, tri, Zt, escr, U, SP;
   size_t solver_bytes;
   bool own;   // the library's own subspace solver (else rocSOLVER)
   size_t total;
@@ -54,6 +54,7 @@ class DavRun {
   void rr_own();   // enqueue the whole Rayleigh-Ritz solve on the own kernels
   void restart_from_ritz();   // V = P, W = H P, reduced matrices rebuilt
   qeh_status hpsi(const double2 *x, double2 *y, int n);
+  qeh_status spsi(const double2 *x, double2 *y, int n);   // S x (generalized problem)
   void ok(hipError_t e) {
     if (err_ == hipSuccess) err_ = e;
   }
@@ -71,6 +72,8 @@ class DavRun {
   double2 *X_ = nullptr, *Lc_ = nullptr, *LcH_ = nullptr, *Y_ = nullptr;
   double *tri_ = nullptr, *Zt_ = nullptr, *escr_ = nullptr;   // own subspace solver
   bool own_ = false;
+  double2 *U_ = nullptr, *SP_ = nullptr;   // S V and S P (overlap S != 1)
+  bool gen_ = false;                       // generalized problem H psi = eps S psi
   qeh_ctx *c64_ = nullptr;   // mixed form: FP64 context of the refinement phase
   bool phase64_ = false;     // H applied through c64_
   int it64_ = 0;             // iterations of the refinement phase

@@ -85,45 +85,61 @@ __device__ double block_min(double v, double *red) {
 // S (n x n, lower triangle read) = L L^H in place (lower).  info = 0, or
 // j + 1 if the leading (j+1) x (j+1) minor is not positive definite (or not
 // finite); L is then incomplete.
+//
+// Right-looking by panels of kCB columns: the panel (rows jb..n-1) is
+// factored in LDS, written back, and the trailing lower triangle gets one
+// rank-kCB update, each element read and written once per panel (the row's
+// panel entries in registers, the column's broadcast from LDS).
+constexpr int kCB = 16;
+constexpr int kCBP = kCB + 1;   // padded LDS row stride (bank spread)
+
 __global__ __launch_bounds__(kET) void chol_kernel(double2 *S, long ld, int n, int *info) {
-  __shared__ double2 col[kEMaxN];
+  __shared__ double2 P[kEMaxN * kCBP];
   const int tid = threadIdx.x;
-  for (int j = 0; j < n; ++j) {
-    const double ajj = S[j + (long)j * ld].x;
-    if (!(ajj > 0.0) || !isfinite(ajj)) {   // same value in every thread
-      if (tid == 0) *info = j + 1;
-      return;
+  for (int jb = 0; jb < n; jb += kCB) {
+    const int b = min(kCB, n - jb), m = n - jb;
+    for (int idx = tid; idx < m * kCB; idx += kET) {
+      const int r = idx % m, c = idx / m;
+      P[r * kCBP + c] = (c < b && r >= c) ? S[(jb + r) + (long)(jb + c) * ld] : make_double2(0.0, 0.0);
     }
-    const double ljj = sqrt(ajj), rinv = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < n; i += kET) {
-      const double2 v = cscale(S[i + (long)j * ld], rinv);
-      S[i + (long)j * ld] = v;
-      col[i] = v;
-    }
-    if (tid == 0) S[j + (long)j * ld] = make_double2(ljj, 0.0);
     __syncthreads();
-    const int m = n - j - 1;
-    if (m > 0) {
-      // trailing update of the lower triangle, S -= c c^H: thread (row r,
-      // column group grp) takes columns kk = grp, grp + g, ... <= r, eight
-      // loads in flight
-      const int g = kET / m;
-      if (tid < g * m) {
-        const int r = tid % m, grp = tid / m;
-        double2 *t = S + (long)(j + 1) * ld + (j + 1);
-        const double2 cr = col[j + 1 + r];
-        int kk = grp;
-        for (; kk + (kTU - 1) * g <= r; kk += kTU * g) {
-          double2 a[kTU];
+    for (int c = 0; c < b; ++c) {
+      const double ajj = P[c * kCBP + c].x;
+      if (!(ajj > 0.0) || !isfinite(ajj)) {   // same value in every thread
+        if (tid == 0) *info = jb + c + 1;
+        return;
+      }
+      const double ljj = sqrt(ajj), rinv = 1.0 / ljj;
+      __syncthreads();
+      for (int r = c + tid; r < m; r += kET)
+        P[r * kCBP + c] = r == c ? make_double2(ljj, 0.0) : cscale(P[r * kCBP + c], rinv);
+      __syncthreads();
+      const int w = b - c - 1;
+      for (int idx = tid; idx < m * w; idx += kET) {
+        const int r = idx % m, c2 = c + 1 + idx / m;
+        if (r >= c2) P[r * kCBP + c2] = csub(P[r * kCBP + c2], cmulc(P[r * kCBP + c], P[c2 * kCBP + c]));
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < m * b; idx += kET) {
+      const int r = idx % m, c = idx / m;
+      if (r >= c) S[(jb + r) + (long)(jb + c) * ld] = P[r * kCBP + c];
+    }
+    const int mt = n - jb - b;
+    if (mt > 0) {
+      const int g = kET / mt;   // >= 2
+      if (tid < g * mt) {
+        const int r = tid % mt, grp = tid / mt;
+        double2 pr[kCB];
 #pragma unroll
-          for (int u = 0; u < kTU; ++u) a[u] = t[r + (long)(kk + u * g) * ld];
+        for (int c = 0; c < kCB; ++c) pr[c] = P[(b + r) * kCBP + c];
+        double2 *row = S + (jb + b + r) + (long)(jb + b) * ld;
+        for (int kk = grp; kk <= r; kk += g) {
+          const double2 *pk = P + (b + kk) * kCBP;
+          double2 acc = row[(long)kk * ld];
 #pragma unroll
-          for (int u = 0; u < kTU; ++u)
-            t[r + (long)(kk + u * g) * ld] = csub(a[u], cmulc(cr, col[j + 1 + kk + u * g]));
-        }
-        for (; kk <= r; kk += g) {
-          double2 *p = t + r + (long)kk * ld;
-          *p = csub(*p, cmulc(cr, col[j + 1 + kk]));
+          for (int c = 0; c < kCB; ++c) acc = csub(acc, cmulc(pr[c], pk[c]));
+          row[(long)kk * ld] = acc;
         }
       }
     }
@@ -401,6 +417,17 @@ __global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int 
 
 // ---------------------------------------------------------------- tridiagonal eigenpairs
 // Number of eigenvalues of the block [s, t) of T (split e) below x.
+// 1/q from the hardware reciprocal estimate and two Newton steps (full
+// double precision for |q| >= pivmin; the quotient e^2/q then stays below
+// 1/DBL_MIN because pivmin >= DBL_MIN max(1, e^2))
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int s, int t, double x,
                                            double pivmin) {
   int c = 0;
@@ -408,7 +435,7 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
   if (fabs(q) < pivmin) q = -pivmin;
   c += q < 0.0;
   for (int i = s + 1; i < t; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    q = d[i] - x - e2[i - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
   }
@@ -545,7 +572,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   __syncthreads();
   for (int round = 0; round < 8; ++round) {
     const double a = sh_d[0], b = sh_d[1];
-    if (b - a <= 2.0 * kEps * fmax(fabs(a), fabs(b)) + pivmin) break;   // uniform
+    if (b - a <= 2.0 * kEps * tnorm) break;   // uniform: absolute accuracy eps ||T||
     const double x = a + (b - a) * (double)(tid + 1) / (double)(kET + 1);
     const int c = sturm_count(sd, se2, 0, n, x, pivmin);
     if (tid == 0) sh_i[2] = kET;
@@ -590,7 +617,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     const int b = tblk[tid], s = bst[b], t = bst[b + 1], loc = tid - bof[b];
     double a = gl, c = xcut;
     for (int it = 0; it < 160; ++it) {
-      if (c - a <= 2.0 * kEps * fmax(fabs(a), fabs(c)) + pivmin) break;
+      if (c - a <= 2.0 * kEps * tnorm) break;
       const double mid = 0.5 * (a + c);
       if (!(mid > a && mid < c)) break;
       if (sturm_count(sd, se2, s, t, mid, pivmin) > loc) c = mid;

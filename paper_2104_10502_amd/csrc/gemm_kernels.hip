@@ -433,21 +433,23 @@ hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nspli
   return hipGetLastError();
 }
 
-hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi) {
+hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi,
+                         const double2 *mat) {
   if (c->nkb == 0) return hipSuccess;
+  if (!mat) mat = c->d.dmat;
   dim3 grid(c->nchunk, nbk);
   const long ss = (long)c->block * c->nkb;
   const double2 *gpsi = c->gamma ? psi : nullptr;
   if (c->prec == QEH_FP64) {
     hipLaunchKernelGGL((dscale_kernel<double2, double2>), grid, dim3(256), 0, c->stream,
                        reinterpret_cast<const double2 *>(c->d.part), ss, c->nsplit, c->nkb,
-                       reinterpret_cast<double2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
+                       reinterpret_cast<double2 *>(c->d.ps), mat, c->d.pj0, c->d.pnb,
                        c->d.pdoff, c->d.chunk, gpsi, ldpsi,
                        reinterpret_cast<const double2 *>(c->d.beta), (long)c->npw);
   } else {
     hipLaunchKernelGGL((dscale_kernel<float2, float2>), grid, dim3(256), 0, c->stream,
                        reinterpret_cast<const float2 *>(c->d.part), ss, c->nsplit, c->nkb,
-                       reinterpret_cast<float2 *>(c->d.ps), c->d.dmat, c->d.pj0, c->d.pnb,
+                       reinterpret_cast<float2 *>(c->d.ps), mat, c->d.pj0, c->d.pnb,
                        c->d.pdoff, c->d.chunk, gpsi, ldpsi,
                        reinterpret_cast<const float2 *>(c->d.beta), (long)c->npw);
   }

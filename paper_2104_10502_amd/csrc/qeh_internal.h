@@ -82,6 +82,7 @@ struct DevMaps {
   void *tw;          // twiddles x | y | z (double2 or float2)
   void *beta;        // [nkb][npw] (double2 or float2)
   double2 *dmat;     // concatenated blocks
+  double2 *qmat;     // overlap q blocks (same layout), or null
   int *pj0;          // [nkb] first projector of the atom block of i
   int *pnb;          // [nkb] size of that block
   int *pdoff;        // [nkb] offset of row i of its block in dmat
@@ -101,6 +102,7 @@ struct qeh_ctx {
   int npw = 0, nst = 0, nkb = 0, nat = 0;
   int npw_fft = 0;      // G-vectors of the FFT sphere (2 npw - 1 for Gamma cells, else npw)
   int gamma = 0;        // 1: real wavefunctions at k = 0, half sphere stored
+  int has_q = 0;        // 1: overlap q blocks present (S != 1)
   int n1 = 0, n2 = 0, n3 = 0, ext = 0, hmin = 0;
   int block = 0, prec = 0;
   int plane_path = 0;   // 0 fused plane kernel, 1 split through HBM, 2 lane-pair kernel,
@@ -235,7 +237,9 @@ hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nspli
 // apply the block-diagonal D: ps[b][i] = sum_j D_ij sum_s part[s][b][j].
 // Gamma contexts: psi (ldpsi) are the block's bands, whose G = 0 values enter
 // the real full-sphere projection (ignored otherwise).
-hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi);
+// mat: the block-diagonal matrix applied (D, or the overlap's q; null = D).
+hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldpsi,
+                         const double2 *mat = nullptr);
 
 // ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
 // Reduced problems up to kEigMaxN; column-major double2 matrices.

@@ -47,7 +47,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct HostCell {
   qeh_cell cell{};
   std::vector<int> miller, nproj;
-  std::vector<double> vloc, beta, dmat, psi0;
+  std::vector<double> vloc, beta, dmat, qmat, psi0;
   // radial-table description when beta is built on the device
   bool has_pg = false;
   qeh_projgen pg{};
@@ -59,6 +59,7 @@ struct HostCell {
     cell.nproj = nproj.empty() ? nullptr : nproj.data();
     cell.beta = beta.empty() ? nullptr : beta.data();
     cell.dmat = dmat.empty() ? nullptr : dmat.data();
+    cell.qmat = qmat.empty() ? nullptr : qmat.data();
     if (has_pg) {
       pg.tau = tau.data();
       pg.ityp = ityp.data();
@@ -365,10 +366,11 @@ qeh_status plan_job(const qeh_cell *cell, int nb, const qeh_dav_opts *o, Job *j)
     if (st != QEH_OK) return st;
     j->ctx64_bytes = align_up(j->ctx64_bytes);
   }
-  // the Davidson plan needs only npw and the Gamma flag from a context
+  // the Davidson plan needs only npw, the Gamma flag and whether S != 1
   qeh_ctx probe;
   probe.npw = cell->npw;
   probe.gamma = cell->gamma ? 1 : 0;
+  probe.has_q = cell->qmat ? 1 : 0;   // S != 1: the plan holds S V and S P too
   int nvecx, maxiter;
   double rtol;
   bool own = false;
@@ -413,6 +415,7 @@ void copy_cell(const qeh_cell *c, const double *psi0, int nb, HostCell *h) {
     h->tab.assign(p->tab, p->tab + (size_t)nch * p->nq);
   }
   if (nd) h->dmat.assign(c->dmat, c->dmat + 2 * nd);
+  if (nd && c->qmat) h->qmat.assign(c->qmat, c->qmat + 2 * nd);
   h->psi0.assign(psi0, psi0 + 2 * (size_t)nb * npw);
   h->bind();
 }

@@ -122,8 +122,10 @@ def test_gamma_davidson_c1_vs_lapack(prec, tol):
     h = cellgen.gamma_half(c)
     ref = sla.eigh(oracle.dense_h(c), eigvals_only=True, subset_by_index=[0, c.nbnd - 1])
     ctx = q.Context.from_cell(h, precision=prec, block=c.nbnd)
+    # the mixed form finishes with FP64 H applications on an FP64 Gamma context
+    c64 = q.Context.from_cell(h, precision=0, block=c.nbnd) if prec == 1 else None
     p = torch.from_numpy(cellgen.make_psi0(h.npw, c.nbnd)).cuda()   # Im psi(0) != 0: zeroed
-    eig, info = ctx.davidson(p, rtol=1e-8)
+    eig, info = ctx.davidson(p, rtol=1e-8, refine=c64)
     assert info["status"] == 0
     assert np.abs(np.sort(eig) - ref).max() < tol, np.abs(np.sort(eig) - ref).max()
     # Ritz vectors: real functions, orthonormal in the full-sphere product,
@@ -226,8 +228,9 @@ def test_gamma_davidson_64_bands(prec, tol):
     h = cellgen.gamma_half(c)
     ref = sla.eigh(oracle.dense_h(c), eigvals_only=True, subset_by_index=[0, 63])
     ctx = q.Context.from_cell(h, precision=prec, block=32)
+    c64 = q.Context.from_cell(h, precision=0, block=32) if prec == 1 else None
     p = torch.from_numpy(cellgen.make_psi0(h.npw, 64, seed=5)).cuda()
-    eig, info = ctx.davidson(p, rtol=1e-8)
+    eig, info = ctx.davidson(p, rtol=1e-8, refine=c64)
     assert info["status"] == 0
     # sorted eigenvalues are unique even where the window cuts a degenerate
     # shell: all 64 are compared
