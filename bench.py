@@ -566,6 +566,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-davidson", action="store_true",
                     help="skip the Davidson time-to-solution legs")
+    ap.add_argument("--davidson-cells", default="c2,c3,c5",
+                    help="comma-separated cells of the Davidson legs (c2, c3, c5)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the complex-k = 0 and 64-atom legs (density, projectors, Gamma)")
     ap.add_argument("--serve", type=float, default=5.0,
@@ -682,7 +684,7 @@ def main():
         out["c2"]["projectors"] = time_projectors(q, torch, c2)
         print("# 64-atom extras done", file=sys.stderr, flush=True)
     if not a.no_davidson:
-        for name in ("c2", "c3", "c5"):
+        for name in [x for x in a.davidson_cells.split(",") if x in ("c2", "c3", "c5")]:
             out["davidson_%s" % name] = davidson_leg(q, torch, name)
     if a.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

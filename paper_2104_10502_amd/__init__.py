@@ -308,7 +308,7 @@ class Server:
         self._nk = {}
 
     def submit(self, cells, psi0s, nb, precision=QEH_MIXED, block=None, nvecx=0, rtol=1e-8,
-               maxiter=0):
+               maxiter=0, subspace=0):
         """cells: list of cell-like objects (one per k-point); psi0s: list of (nb, npw)."""
         if len(psi0s) != len(cells):
             raise ValueError("submit: %d cells but %d start-vector blocks" % (len(cells), len(psi0s)))
@@ -327,7 +327,7 @@ class Server:
                                   qmat=getattr(c, "qmat", None))
         psi = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.complex128).ravel()
                                                    for p in psi0s]))
-        o = DavOpts(int(nvecx), float(rtol), int(maxiter))
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter), int(subspace))
         t = ctypes.c_uint64()
         _check(_lib.qeh_submit(self._h, arr, len(cells), int(nb), psi.ctypes.data_as(_c_dbl_p),
                                ctypes.byref(o), ctypes.byref(t)), "qeh_submit")

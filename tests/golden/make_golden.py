@@ -42,14 +42,39 @@ def c2_eigs():
     print("wrote", path, info["iters"], info["band_applies"], "%.0f s" % dt)
 
 
-def low_eigs(name: str, nb: int, header: str):
+_CELL = None
+
+
+def _vloc_band(x):
+    return oracle.vloc_psi(_CELL, x[None, :])[0]
+
+
+def _parallel_apply_h(cell, nproc):
+    """oracle.apply_h with the local-potential term of each band computed in a
+    separate forked worker (each band's transform is independent; the
+    arithmetic per band is exactly apply_h's)."""
+    import multiprocessing as mp
+    global _CELL
+    _CELL = cell
+    pool = mp.get_context("fork").Pool(nproc)
+    kin = oracle.kinetic(cell)
+
+    def apply(x):
+        x = np.atleast_2d(x)
+        loc = np.array(pool.map(_vloc_band, list(x)))
+        return kin[None, :] * x + loc + oracle.vnl_psi(cell, x)
+    return apply, pool
+
+
+def low_eigs(name: str, nb: int, header: str, nproc: int = 6):
     """Lowest nb eigenvalues of a Gamma cell, solved on the full complex sphere."""
     cell = cellgen.make_cell(name)
     psi0 = cellgen.make_psi0(cell.npw, nb, seed=10502)
     t = time.time()
     hd = oracle.hdiag(cell)
-    eps, psi, info = oracle.davidson(lambda x: oracle.apply_h(cell, x), psi0, hd,
-                                     rtol=1e-9, nvecx=4 * nb, maxiter=400)
+    apply, pool = _parallel_apply_h(cell, nproc)
+    eps, psi, info = oracle.davidson(apply, psi0, hd, rtol=1e-9, nvecx=4 * nb, maxiter=400)
+    pool.close()
     dt = time.time() - t
     assert info["converged"], info
     path = os.path.join(HERE, "%s_eigs.txt" % name)
