@@ -45,7 +45,8 @@ enum {
   QEH_ERR_NOT_CONVERGED = -5,  /* Davidson hit maxiter (results still written)  */
   QEH_ERR_REJECTED = -6,       /* served request can never fit the budget       */
   QEH_ERR_DEVICE = -7,         /* a HIP call failed                             */
-  QEH_ERR_BUSY = -8            /* served request not finished yet               */
+  QEH_ERR_BUSY = -8,           /* served request not finished yet               */
+  QEH_RCI_APPLY_H = 1          /* qeh_dav_rci_step: apply H to the request      */
 };
 
 enum { QEH_FP64 = 0, QEH_MIXED = 1 };
@@ -308,6 +309,48 @@ qeh_status qeh_davidson_plan(const qeh_ctx *ctx, int nb, const qeh_dav_opts *opt
 qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
                         double *eig, const qeh_dav_opts *opts, void *work,
                         size_t work_bytes, qeh_dav_info *info);
+
+/* Reverse-communication Davidson: the solver hands every H|psi> product to
+ * the caller, who computes it with a Hamiltonian builder of its own and
+ * passes the result back (the solver library's reverse communication
+ * interface, section "Domain-specific mathematical libraries").  The same
+ * solve as qeh_davidson, driven one step at a time:
+ *   qeh_dav_rci_create binds the solve (arguments as qeh_davidson's; work is
+ *     qeh_davidson_plan bytes; opts->refine must be NULL) and enqueues nothing;
+ *   qeh_dav_rci_step enqueues work on the context's stream up to the next H
+ *     product and returns QEH_RCI_APPLY_H with req filled: x (DEVICE, n bands
+ *     of npw complex coefficients, interleaved re/im, leading dimension ld =
+ *     npw, inside work: read only) and y (DEVICE, same layout, inside work:
+ *     write only).  The caller writes H x into y, enqueued on the context's
+ *     stream or finished before the next qeh_dav_rci_step (x is ready on that
+ *     stream, not necessarily on the host), and calls qeh_dav_rci_step
+ *     again.  It returns QEH_OK when the solve has converged (psi_inout, eig
+ *     written), a negative status on failure (QEH_ERR_NOT_CONVERGED with the
+ *     results written at maxiter); once ended, every further call returns
+ *     that same status.  It blocks only where qeh_davidson waits for the
+ *     stream (the per-iteration residual readback);
+ *   qeh_dav_rci_destroy waits for the context's stream, fills info (may be
+ *     NULL; t_hpsi = 0, the H time being the caller's) and frees the handle.
+ * The context supplies the plane-wave set, the Gamma flag, diag(H) for the
+ * preconditioner and, with q blocks set, the overlap S; its precision sets
+ * the stop rule only (QEH_MIXED: qeh_davidson's single-precision rules
+ * without refine).  A caller that serves each request with qeh_apply_h on the
+ * same context gets qeh_davidson's results bit for bit.  One thread drives a
+ * handle.  Errors: QEH_ERR_INVALID (nulls, refine set, and qeh_davidson's
+ * argument checks), QEH_ERR_NOMEM (short work or no host memory for the
+ * handle), QEH_ERR_DEVICE. */
+typedef struct qeh_dav_rci qeh_dav_rci;
+typedef struct {
+  const double *x;
+  double *y;
+  int n;
+  int ld;
+} qeh_rci_request;
+qeh_status qeh_dav_rci_create(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
+                              double *eig, const qeh_dav_opts *opts, void *work,
+                              size_t work_bytes, qeh_dav_rci **out);
+qeh_status qeh_dav_rci_step(qeh_dav_rci *rci, qeh_rci_request *req);
+qeh_status qeh_dav_rci_destroy(qeh_dav_rci *rci, qeh_dav_info *info);
 
 /* The dense solver of the Rayleigh-Ritz step on its own (the generalized
  * Hermitian eigenproblem the paper solves with a dense GPU solver, section

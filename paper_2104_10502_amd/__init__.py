@@ -26,6 +26,7 @@ QEH_ERR_NOT_CONVERGED = -5
 QEH_ERR_REJECTED = -6
 QEH_ERR_DEVICE = -7
 QEH_ERR_BUSY = -8
+QEH_RCI_APPLY_H = 1
 QEH_FP64 = 0
 QEH_MIXED = 1
 NSTAGES = 9
@@ -67,6 +68,11 @@ class DavOpts(ctypes.Structure):
                 ("subspace", ctypes.c_int), ("refine", ctypes.c_void_p)]
 
 
+class RciRequest(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int),
+                ("ld", ctypes.c_int)]
+
+
 class DavInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("notconv", ctypes.c_int), ("restarts", ctypes.c_int),
                 ("band_applies", ctypes.c_long), ("resid_max", ctypes.c_double),
@@ -91,6 +97,11 @@ _SIGS = {
     "qeh_davidson_plan": ([_vp, ctypes.c_int, ctypes.POINTER(DavOpts), _sz_p], ctypes.c_int),
     "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
                       _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
+    "qeh_dav_rci_create": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p,
+                            ctypes.POINTER(DavOpts), _vp, ctypes.c_size_t, ctypes.POINTER(_vp)],
+                           ctypes.c_int),
+    "qeh_dav_rci_step": ([_vp, ctypes.POINTER(RciRequest)], ctypes.c_int),
+    "qeh_dav_rci_destroy": ([_vp, ctypes.POINTER(DavInfo)], ctypes.c_int),
     "qeh_density_plan": ([_vp, _sz_p], ctypes.c_int),
     "qeh_subspace_plan": ([ctypes.c_int, ctypes.c_int, _sz_p], ctypes.c_int),
     "qeh_subspace_eigh": ([ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp,
@@ -509,6 +520,50 @@ class Context:
                                eig.ctypes.data_as(_c_dbl_p), ctypes.byref(o),
                                _vp(work.data_ptr()), int(work.numel()), ctypes.byref(info))
         _check(st, "qeh_davidson", allow=(QEH_ERR_NOT_CONVERGED,) if allow_notconv else ())
+        d = info.as_dict()
+        d["status"] = st
+        return eig, d
+
+    def davidson_rci(self, psi, apply, nvecx=0, rtol=1e-8, maxiter=0, work=None,
+                     allow_notconv=False, subspace=0):
+        """Davidson with H supplied by the caller (reverse communication).
+        apply(x, y) receives two complex128 (n, npw) views of the solver's work
+        area and must write H x into y on this context's stream.  Returns
+        (eig ndarray, info dict) like davidson()."""
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        o = DavOpts(int(nvecx), float(rtol), int(maxiter), int(subspace), None)
+        need = self.davidson_plan(nb, nvecx, rtol, maxiter, subspace)
+        if work is None or work.numel() < need:
+            work = torch.empty(max(need, 256), dtype=torch.uint8, device=psi.device)
+        eig = np.zeros(nb, dtype=np.float64)
+        h = _vp()
+        _check(_lib.qeh_dav_rci_create(self._h, nb, _vp(psi.data_ptr()), psi.stride(0),
+                                       eig.ctypes.data_as(_c_dbl_p), ctypes.byref(o),
+                                       _vp(work.data_ptr()), int(work.numel()),
+                                       ctypes.byref(h)), "qeh_dav_rci_create")
+        base, size = work.data_ptr(), work.numel()
+
+        def view(ptr, n, ld):
+            off = ptr - base
+            nbytes = 16 * n * ld
+            if off < 0 or off % 16 or off + nbytes > size:
+                raise RuntimeError("request outside the work area")
+            return work[off:off + nbytes].view(torch.complex128).view(n, ld)
+
+        req = RciRequest()
+        info = DavInfo()
+        try:
+            while True:
+                st = _lib.qeh_dav_rci_step(h, ctypes.byref(req))
+                if st != QEH_RCI_APPLY_H:
+                    break
+                apply(view(req.x, req.n, req.ld), view(req.y, req.n, req.ld))
+        finally:
+            dst = _lib.qeh_dav_rci_destroy(h, ctypes.byref(info))
+        _check(st, "qeh_dav_rci_step", allow=(QEH_ERR_NOT_CONVERGED,) if allow_notconv else ())
+        _check(dst, "qeh_dav_rci_destroy")
         d = info.as_dict()
         d["status"] = st
         return eig, d

@@ -484,6 +484,7 @@ const char *qeh_status_str(qeh_status s) {
     case QEH_ERR_REJECTED: return "request rejected";
     case QEH_ERR_DEVICE: return "device error";
     case QEH_ERR_BUSY: return "busy";
+    case QEH_RCI_APPLY_H: return "apply H to the request";
     default: return "unknown status";
   }
 }

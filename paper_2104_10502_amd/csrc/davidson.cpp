@@ -25,6 +25,8 @@
 // the per-iteration readback.
 #include "davidson.h"
 
+#include <new>
+
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -444,12 +446,28 @@ void DavRun::release() {
 }
 
 qeh_status DavRun::hpsi(const double2 *x, double2 *y, int n) {
+  band_applies_ += n;
+  if (rci_) {   // the caller applies H before the next advance()
+    req_x_ = x;
+    req_y_ = y;
+    req_n_ = n;
+    pending_ = true;
+    return QEH_OK;
+  }
   ev_h_.start(c_->stream);
   qeh_status r = apply_h_impl(phase64_ ? c64_ : c_, 2, n, reinterpret_cast<const double *>(x),
                               npw_, reinterpret_cast<double *>(y), npw_);
   ev_h_.stop(c_->stream);
-  band_applies_ += n;
   return r;
+}
+
+bool DavRun::take_request(const double2 **x, double2 **y, int *n) {
+  if (!pending_) return false;
+  pending_ = false;
+  *x = req_x_;
+  *y = req_y_;
+  *n = req_n_;
+  return true;
 }
 
 // Hr y = eps Sr y on the library's kernels: Sr = L L^H, A = L^-1 Hr L^-H by
@@ -493,10 +511,12 @@ void DavRun::restart_from_ritz() {
 }
 
 qeh_status DavRun::spsi(const double2 *x, double2 *y, int n) {
-  ev_h_.start(c_->stream);
+  // timed with H (t_hpsi), except under reverse communication, where that
+  // figure is left to the caller
+  if (!rci_) ev_h_.start(c_->stream);
   qeh_status r = apply_s_impl(phase64_ ? c64_ : c_, n, reinterpret_cast<const double *>(x), npw_,
                               reinterpret_cast<double *>(y), npw_);
-  ev_h_.stop(c_->stream);
+  if (!rci_) ev_h_.stop(c_->stream);
   return r;
 }
 
@@ -533,7 +553,17 @@ bool DavRun::advance() {
           return true;
         }
         qeh_status st = hpsi(V_, W_, nb);
-        if (st == QEH_OK && gen_) st = spsi(V_, U_, nb);
+        if (st != QEH_OK) {
+          result_ = st;
+          phase_ = kDone;
+          return true;
+        }
+        phase_ = kCheckInputPost;
+        if (rci_) return false;
+        break;
+      }
+      case kCheckInputPost: {
+        qeh_status st = gen_ ? spsi(V_, U_, nb) : QEH_OK;
         if (st != QEH_OK) {
           result_ = st;
           phase_ = kDone;
@@ -756,8 +786,20 @@ bool DavRun::advance() {
         ok(launch_precond(gen_ ? SP_ : P_, Q_, npw, npw, idx_d_, nc, eps_d_, c_->d.hdiag,
                           V_ + (size_t)nbase_ * npw, npw, c_->gamma, s));
         qeh_status st = hpsi(V_ + (size_t)nbase_ * npw, W_ + (size_t)nbase_ * npw, nc);
-        if (st == QEH_OK && gen_)
-          st = spsi(V_ + (size_t)nbase_ * npw, U_ + (size_t)nbase_ * npw, nc);
+        if (st != QEH_OK) {
+          result_ = st;
+          phase_ = kDone;
+          return true;
+        }
+        nc_ = nc;
+        phase_ = kConvergePost;
+        if (rci_) return false;
+        break;
+      }
+      case kConvergePost: {
+        const int nc = nc_;
+        qeh_status st =
+            gen_ ? spsi(V_ + (size_t)nbase_ * npw, U_ + (size_t)nbase_ * npw, nc) : QEH_OK;
         if (st != QEH_OK) {
           result_ = st;
           phase_ = kDone;
@@ -846,6 +888,92 @@ qeh_status qeh_davidson(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double
   const qeh_status r = run.result();
   run.release();
   return r;
+}
+
+}  // extern "C"
+
+struct qeh_dav_rci {
+  qeh::DavRun run;
+  qeh_ctx *ctx = nullptr;
+  bool ended = false;
+  qeh_status final_status = QEH_OK;
+};
+
+extern "C" {
+
+qeh_status qeh_dav_rci_create(qeh_ctx *c, int nb, double *psi_inout, int ldpsi, double *eig,
+                              const qeh_dav_opts *o, void *work, size_t work_bytes,
+                              qeh_dav_rci **out) {
+  if (!out) {
+    set_error("out is null");
+    return QEH_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (o && o->refine) {
+    set_error("reverse communication: the caller applies H, opts->refine must be NULL");
+    return QEH_ERR_INVALID;
+  }
+  qeh_dav_rci *r = new (std::nothrow) qeh_dav_rci;
+  if (!r) {
+    set_error("no host memory for the reverse-communication handle");
+    return QEH_ERR_NOMEM;
+  }
+  qeh_status st = r->run.init(c, nb, reinterpret_cast<double2 *>(psi_inout), ldpsi, eig, o,
+                              work, work_bytes);
+  if (st != QEH_OK) {
+    delete r;
+    return st;
+  }
+  r->run.set_rci();
+  r->ctx = c;
+  *out = r;
+  return QEH_OK;
+}
+
+qeh_status qeh_dav_rci_step(qeh_dav_rci *r, qeh_rci_request *req) {
+  if (!r || !req) {
+    set_error("rci and req must be non-null");
+    return QEH_ERR_INVALID;
+  }
+  req->x = nullptr;
+  req->y = nullptr;
+  req->n = 0;
+  req->ld = 0;
+  if (r->ended) return r->final_status;
+  while (!r->run.advance()) {
+    const double2 *x;
+    double2 *y;
+    int n;
+    if (r->run.take_request(&x, &y, &n)) {
+      req->x = reinterpret_cast<const double *>(x);
+      req->y = reinterpret_cast<double *>(y);
+      req->n = n;
+      req->ld = r->ctx->npw;
+      return QEH_RCI_APPLY_H;
+    }
+    hipError_t e = hipStreamSynchronize(r->ctx->stream);
+    if (e != hipSuccess) {
+      r->ended = true;
+      r->final_status = hip_fail(e, "davidson sync");
+      return r->final_status;
+    }
+  }
+  r->ended = true;
+  r->final_status = r->run.result();
+  return r->final_status;
+}
+
+qeh_status qeh_dav_rci_destroy(qeh_dav_rci *r, qeh_dav_info *info) {
+  if (!r) {
+    set_error("rci is null");
+    return QEH_ERR_INVALID;
+  }
+  // work still enqueued (an abandoned solve) reads the handle's pinned buffers
+  hipError_t e = hipStreamSynchronize(r->ctx->stream);
+  r->run.fill_info(info);
+  r->run.release();
+  delete r;
+  return e == hipSuccess ? QEH_OK : hip_fail(e, "davidson rci destroy");
 }
 
 namespace {

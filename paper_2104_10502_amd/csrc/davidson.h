@@ -2,7 +2,11 @@
 // the context stream up to the next point where the host needs device
 // results, and returns false; after the stream has drained the caller calls
 // advance() again.  It returns true once the run is finished.  The blocking
-// qeh_davidson() and the request server both drive this one state machine.
+// qeh_davidson(), the request server and the reverse-communication handle all
+// drive this one state machine.  In reverse-communication mode every H
+// application becomes a request (take_request) that the caller serves before
+// the next advance(); the work enqueued before and after it is the same as
+// when the run applies H itself.
 #pragma once
 
 #include <rocblas/rocblas.h>
@@ -44,13 +48,29 @@ class DavRun {
   qeh_status init(qeh_ctx *c, int nb, double2 *psi, int ldpsi, double *eig,
                   const qeh_dav_opts *o, void *work, size_t work_bytes);
   bool advance();
+  // reverse communication: H is applied by the caller (set before the first
+  // advance); after advance() returns false, take_request reports whether it
+  // stopped for an H application rather than for a stream drain
+  void set_rci() { rci_ = true; }
+  bool take_request(const double2 **x, double2 **y, int *n);
   qeh_status result() const { return result_; }
   void fill_info(qeh_dav_info *info) const;
   void release();
   ~DavRun() { release(); }
 
  private:
-  enum Phase { kStart, kCheckInput, kRR, kRRSolve, kRRCheck, kConverge, kFinish, kDone };
+  enum Phase {
+    kStart,
+    kCheckInput,
+    kCheckInputPost,   // after H V of the starting block
+    kRR,
+    kRRSolve,
+    kRRCheck,
+    kConverge,
+    kConvergePost,     // after H of the new correction vectors
+    kFinish,
+    kDone
+  };
   void rr_own();   // enqueue the whole Rayleigh-Ritz solve on the own kernels
   void restart_from_ritz();   // V = P, W = H P, reduced matrices rebuilt
   qeh_status hpsi(const double2 *x, double2 *y, int n);
@@ -87,7 +107,11 @@ class DavRun {
   rocblas_handle rh_ = nullptr;
   EvPool ev_h_, ev_s_;
   Phase phase_ = kStart;
-  int it_ = 0, restarts_ = 0, notconv_ = 0, nbase_ = 0;
+  int it_ = 0, restarts_ = 0, notconv_ = 0, nbase_ = 0, nc_ = 0;
+  bool rci_ = false, pending_ = false;   // reverse communication
+  const double2 *req_x_ = nullptr;
+  double2 *req_y_ = nullptr;
+  int req_n_ = 0;
   bool chol_prev_ = false, have_ritz_ = false;
   double resid_max_ = 0.0;
   long band_applies_ = 0;

@@ -48,11 +48,11 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "qeh.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell),
          offsetof(qeh_cell, npw), offsetof(qeh_cell, miller), offsetof(qeh_cell, beta),
          offsetof(qeh_cell, block), sizeof(qeh_dav_opts), sizeof(qeh_dav_info),
          offsetof(qeh_cell, projgen), sizeof(qeh_projgen), offsetof(qeh_projgen, dq),
-         offsetof(qeh_projgen, tab));
+         offsetof(qeh_projgen, tab), sizeof(qeh_rci_request), offsetof(qeh_rci_request, n));
   return 0;
 }
 ''')
@@ -65,7 +65,8 @@ int main(void) {
     P = q.QehProjgen
     assert vals == [ctypes.sizeof(C), C.npw.offset, C.miller.offset, C.beta.offset,
                     C.block.offset, ctypes.sizeof(q.DavOpts), ctypes.sizeof(q.DavInfo),
-                    C.projgen.offset, ctypes.sizeof(P), P.dq.offset, P.tab.offset]
+                    C.projgen.offset, ctypes.sizeof(P), P.dq.offset, P.tab.offset,
+                    ctypes.sizeof(q.RciRequest), q.RciRequest.n.offset]
 
 
 def _plan(cell, **kw):
@@ -164,10 +165,23 @@ def test_null_context_arguments():
     assert b"null" in q._lib.qeh_last_error()
 
 
+def test_reverse_communication_null_arguments():
+    # argument checks of the reverse-communication handle, before any device call
+    q = _q()
+    req = q.RciRequest()
+    assert q._lib.qeh_dav_rci_step(None, ctypes.byref(req)) == q.QEH_ERR_INVALID
+    assert q._lib.qeh_dav_rci_destroy(None, None) == q.QEH_ERR_INVALID
+    out = ctypes.c_void_p(1)
+    st = q._lib.qeh_dav_rci_create(None, 4, None, 0, None, None, None, 0, ctypes.byref(out))
+    assert st == q.QEH_ERR_INVALID and out.value is None
+    assert q._lib.qeh_dav_rci_create(None, 4, None, 0, None, None, None, 0, None) == \
+        q.QEH_ERR_INVALID
+
+
 def test_status_strings():
     q = _q()
-    for s in range(-8, 1):
-        assert q._lib.qeh_status_str(s)
+    for s in range(-8, 2):
+        assert q._lib.qeh_status_str(s) != b"unknown status"
 
 
 def test_plan_with_device_projectors(c1):
