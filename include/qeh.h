@@ -457,8 +457,10 @@ qeh_status qeh_server_destroy(qeh_server *srv);
 /* Shape facts of a context: [npw, nst, nkb, N1, N2, N3, x-extent, block,
  * precision, plane path (0 fused in one kernel, 1 split through HBM,
  * 2 lane-pair register kernel, 4 lane-quad register kernel), stick path
- * (0 LDS passes, 1 lane-pair register z transforms)].  out has room for n
- * values (up to 11).
+ * (0 LDS passes, 1 lane-pair register z transforms), projector tiles (0 the
+ * 64 x 64 MFMA tiles, 1 the wide single-precision tiles: QEH_MIXED with
+ * >= 2048 projectors and a block of >= 128 bands)].  out has room for n
+ * values (up to 12).
  * The plane path is chosen by LDS fit and box shape: the lane-pair kernel
  * serves the mixed form when N1 = N2 is one of its compiled sizes (even,
  * 16..90), the lane-quad kernel the FP64 form when N1 = N2 is one of its

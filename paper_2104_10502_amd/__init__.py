@@ -587,10 +587,10 @@ class Context:
         return out
 
     def info(self):
-        out = (ctypes.c_long * 11)()
-        _check(_lib.qeh_ctx_info(self._h, out, 11), "qeh_ctx_info")
+        out = (ctypes.c_long * 12)()
+        _check(_lib.qeh_ctx_info(self._h, out, 12), "qeh_ctx_info")
         keys = ["npw", "nst", "nkb", "n1", "n2", "n3", "ext", "block", "precision", "plane_path",
-                "stick_path"]
+                "stick_path", "wide_tiles"]
         return dict(zip(keys, list(out)))
 
     def close(self):

@@ -263,7 +263,7 @@ size_t bump(size_t *cur, size_t bytes) {
 }
 
 struct Geometry {
-  int nkb, nd, nchunk, nsplit, kchunk, plane_path, zpair;
+  int nkb, nd, nchunk, nsplit, kchunk, plane_path, zpair, wide;
   FftDim dx, dy, dz;
   PlaneGeom pg;
   SplitGeom spg;
@@ -393,15 +393,22 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
       cur += c->nproj[a];
     }
   }
-  // split-K of beta^H psi: enough workgroups to fill the chip (~4 per CU),
-  // fixed chunks of >= 256 plane waves, 64 x 64 tiles (measured faster than
-  // 128 x 64 at 128 bands: four waves per SIMD instead of two).
+  // split-K of beta^H psi: fixed chunks of >= 256 plane waves, enough
+  // workgroups to fill the chip.  Single precision with >= 2048 projectors
+  // and blocks of >= 128 bands takes the wide FP32 tiles (128 bands x 128 or,
+  // on Gamma cells, 256 projectors; eight waves, one workgroup per CU): at
+  // most two rounds of 256 workgroups (the chip's CU count), since a third,
+  // nearly empty round costs as much as a full one; otherwise 64 x 64 tiles
+  // (~4 workgroups per CU; measured faster than 128 x 64 at 128 bands and
+  // 512 projectors).
   g->nsplit = 1;
   g->kchunk = c->npw;
+  g->wide = c->precision == QEH_MIXED && c->block >= 128 && g->nkb >= 2048 ? 1 : 0;
   if (g->nkb > 0) {
-    const int bm = 64;
-    const int tiles = ((c->block + bm - 1) / bm) * ((g->nkb + 63) / 64);
-    int ns = std::max(1, (1024 + tiles - 1) / tiles);
+    const int bm = g->wide ? 128 : 64;
+    const int bn = g->wide ? (c->gamma ? 256 : 128) : 64;
+    const int tiles = ((c->block + bm - 1) / bm) * ((g->nkb + bn - 1) / bn);
+    int ns = g->wide ? std::max(1, 2 * 256 / tiles) : std::max(1, (1024 + tiles - 1) / tiles);
     ns = std::min(ns, std::max(1, c->npw / 256));
     int kc = (c->npw + ns - 1) / ns;
     kc = (kc + 15) / 16 * 16;
@@ -540,6 +547,7 @@ qeh_status qeh_ctx_create(const qeh_cell *cell, void *arena, size_t arena_bytes,
   c->plane_path = g.plane_path;
   c->zpair = g.zpair;
   c->nsplit = g.nsplit;
+  c->wide = g.wide;
   c->kchunk = g.kchunk;
   c->nchunk = g.nchunk;
   c->dx = g.dx;
@@ -822,7 +830,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     g1.A = use32 ? static_cast<const void *>(c->d.psi32) : static_cast<const void *>(psi);
     g1.lda = use32 ? c->npw_fft : ldpsi;
     g1.ta = use32 ? T_F2 : T_D2;
-    g1.tile = 0;
+    g1.tile = c->wide;
     g1.B = c->d.beta;
     g1.ldb = c->npw;
     g1.tb = f64 ? T_D2 : T_F2;
@@ -868,6 +876,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     g3.kchunk = c->nkb;
     g3.prec = f64 ? G_F64 : G_F32;
     g3.rmode = c->gamma ? 2 : 0;   // Gamma: ps is real
+    g3.tile = c->wide;
     {
       StageGuard g(c, 5);
       e = launch_cgemm(g3, c->stream);
@@ -942,6 +951,7 @@ qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double
     g1.split_stride = (long)c->block * c->nkb;
     g1.prec = f64 ? G_F64 : G_F32;
     g1.rmode = c->gamma ? 1 : 0;
+    g1.tile = c->wide;
     e = launch_cgemm(g1, c->stream);
     if (e == hipSuccess) e = launch_dscale(c, nbk, pb, ldpsi, c->d.qmat);
     if (e != hipSuccess) return hip_fail(e, "S psi projections");
@@ -964,6 +974,7 @@ qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double
     g3.kchunk = c->nkb;
     g3.prec = f64 ? G_F64 : G_F32;
     g3.rmode = c->gamma ? 2 : 0;
+    g3.tile = c->wide;
     e = launch_cgemm(g3, c->stream);
     if (e != hipSuccess) return hip_fail(e, "S psi product");
   }
@@ -1157,9 +1168,9 @@ qeh_status qeh_ctx_hdiag(const qeh_ctx *c, double *hdiag) {
 
 qeh_status qeh_ctx_info(const qeh_ctx *c, long *out, int n) {
   if (!c || !out) return invalid("null argument");
-  const long v[11] = {c->npw, c->nst, c->nkb, c->n1, c->n2, c->n3, c->ext, c->block, c->prec,
-                      c->plane_path, c->zpair};
-  for (int i = 0; i < n && i < 11; ++i) out[i] = v[i];
+  const long v[12] = {c->npw, c->nst, c->nkb, c->n1, c->n2, c->n3, c->ext, c->block, c->prec,
+                      c->plane_path, c->zpair, c->wide};
+  for (int i = 0; i < n && i < 12; ++i) out[i] = v[i];
   return QEH_OK;
 }
 

@@ -19,8 +19,8 @@
 // Two cheaper forms serve the Gamma-point projections (RM = 1: only the real
 // part of C is wanted, Cr = P1 - P2; RM = 2: A is real, Cr = sum Ar Br and
 // Ci = sum Ar Bi): two MFMA products per step instead of three.
-// 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
-// (BM/2) x (BN/2) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
+// WGM x WGN waves (64 * WGM * WGN threads); each wave owns a
+// (BM/WGM) x (BN/WGN) block of C built from 16 x 16 x 4 MFMA tiles.  Long K is
 // split into fixed chunks whose partial results are summed in double by a
 // separate kernel in a fixed order (deterministic, no atomics).
 #include <algorithm>
@@ -32,20 +32,27 @@ namespace qeh {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-template <typename R> struct acc_of;
-template <> struct acc_of<float> { using type = floatx4; };
-template <> struct acc_of<double> { using type = doublex4; };
+// Accumulator of one BS x BS block: BS = 16 (f32 or f64, k = 4 per
+// instruction) or 32 (f32 only, k = 2 per instruction; on this chip the
+// 32 x 32 f32 instruction sustains close to the matrix peak, the 16 x 16 one
+// about 0.85 of it).
+template <typename R, int BS> struct acc_of;
+template <> struct acc_of<float, 16> { using type = floatx4; };
+template <> struct acc_of<float, 32> { using type = floatx16; };
+template <> struct acc_of<double, 16> { using type = doublex4; };
 
 __device__ __forceinline__ void mfma(float a, float b, floatx4 &c) {
   c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ void mfma(float a, float b, floatx16 &c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
 __device__ __forceinline__ void mfma(double a, double b, doublex4 &c) {
   c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-
-constexpr int kGT = 256;
 
 // Operand load: element of type T (double2/float2) -> compute type R, conj.
 template <typename R, typename T>
@@ -71,18 +78,24 @@ template <typename T> __device__ __forceinline__ T zero_of() {
 // tiles are prefetched into registers while the MFMAs consume the LDS copy of
 // the previous slice (two LDS buffers, one barrier per slice).
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
-          int RM>
-__global__ __launch_bounds__(kGT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
+          int RM, int WGM, int WGN, int BS>
+__global__ __launch_bounds__(64 * WGM * WGN)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
 void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
     long ldc, int M, int N, int K, int conjA, int conjB, int accumulate, int kchunk,
     long split_stride, int tiles_m, int tiles_n, int ntiles, int per_xcd) {
-  using ACC = typename acc_of<R>::type;
+  using ACC = typename acc_of<R, BS>::type;
+  constexpr int NACC = BS * BS / 64;   // accumulator entries per lane
+  constexpr int KS = BS == 32 ? 2 : 4;   // k per instruction
+  static_assert(BK % KS == 0, "K slice / instruction k mismatch");
+  constexpr int kGT = 64 * WGM * WGN;
   constexpr int BKP = BK + 1;
-  constexpr int TM = BM / 32;
-  constexpr int TN = BN / 32;
+  constexpr int TM = BM / (BS * WGM);
+  constexpr int TN = BN / (BS * WGN);
   constexpr int NA = BM * BK / kGT;
   constexpr int NB = BN * BK / kGT;
+  static_assert(TM * BS * WGM == BM && TN * BS * WGN == BN, "tile / wave mismatch");
   static_assert(NA * kGT == BM * BK && NB * kGT == BN * BK, "tile / thread mismatch");
   __shared__ R As[2][2][BM * BKP];   // [buffer][re, im]
   __shared__ R Bs[2][2][BN * BKP];
@@ -90,8 +103,8 @@ void cgemm_kernel(
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm0 = (wave >> 1) * (BM / 2);
-  const int wn0 = (wave & 1) * (BN / 2);
+  const int wm0 = (wave / WGN) * (BM / WGM);
+  const int wn0 = (wave % WGN) * (BN / WGN);
   // Workgroup ids are dealt round-robin to the 8 XCDs (each with its own L2);
   // the remap gives each XCD a contiguous run of (m tile fastest, n tile,
   // K slice), so tiles that read the same operand rows run on one XCD
@@ -114,15 +127,16 @@ void cgemm_kernel(
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-      p1[i][j] = ACC{0, 0, 0, 0};
-      p2[i][j] = ACC{0, 0, 0, 0};
-      p3[i][j] = ACC{0, 0, 0, 0};
-    }
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < NACC; ++e) {
+        p1[i][j][e] = R(0);
+        p2[i][j][e] = R(0);
+        p3[i][j][e] = R(0);
+      }
 
-  TA ra[NA];
-  TB rb[NB];
-  auto gload = [&](int k0) {
+  // Global operand loads for one K slice into registers.
+  auto gload = [&](int k0, TA *ra, TB *rb) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int e = tid + u * kGT;
@@ -144,7 +158,7 @@ void cgemm_kernel(
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const TA *ra, const TB *rb) {
 #pragma unroll
     for (int u = 0; u < NA; ++u) {
       const int e = tid + u * kGT;
@@ -168,31 +182,23 @@ void cgemm_kernel(
     }
   };
 
-  const int lr = lane & 15;   // row (A) / column (B) inside a 16-block
-  const int lk = lane >> 4;   // k inside a 4-step
+  const int lr = lane % BS;   // row (A) / column (B) inside a block
+  const int lk = lane / BS;   // k inside a step of KS
 
-  if (kbeg < kend) {
-    gload(kbeg);
-    sstore(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    const bool more = k0 + BK < kend;
-    if (more) gload(k0 + BK);
+  auto compute = [&](int buf) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
+    for (int kk = 0; kk < BK; kk += KS) {
       R ar[TM], ai[TM], as[TM], br[TN], bi[TN], bs[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        const int off = (wm0 + i * 16 + lr) * BKP + kk + lk;
+        const int off = (wm0 + i * BS + lr) * BKP + kk + lk;
         ar[i] = As[buf][0][off];
         ai[i] = As[buf][1][off];
         as[i] = ar[i] + ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const int off = (wn0 + j * 16 + lr) * BKP + kk + lk;
+        const int off = (wn0 + j * BS + lr) * BKP + kk + lk;
         br[j] = Bs[buf][0][off];
         bi[j] = Bs[buf][1][off];
         bs[j] = br[j] + bi[j];
@@ -210,23 +216,40 @@ void cgemm_kernel(
           }
         }
     }
-    if (more) sstore(buf ^ 1);
+  };
+
+  // one slice in flight: loaded during the MFMAs of the previous one
+  TA ra[NA];
+  TB rb[NB];
+  if (kbeg < kend) {
+    gload(kbeg, ra, rb);
+    sstore(0, ra, rb);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    const bool more = k0 + BK < kend;
+    if (more) gload(k0 + BK, ra, rb);
+    compute(buf);
+    if (more) sstore(buf ^ 1, ra, rb);
     __syncthreads();
     buf ^= 1;
   }
 
-  // ---- epilogue.  Column lane%16 of each 16x16 block; accumulator entry r
-  // holds row 4*(lane/16)+r for the f32 MFMA but row lane/16+4*r for the f64
-  // one (the two instructions lay out D differently).
+  // ---- epilogue.  Column lane%BS of each block.  16 x 16 blocks:
+  // accumulator entry r holds row 4*(lane/16)+r for the f32 instruction but
+  // row lane/16+4*r for the f64 one (the two lay out D differently); 32 x 32
+  // f32 blocks: entry r holds row (r%4) + 8*(r/4) + 4*(lane/32).
   constexpr bool kF64 = sizeof(R) == 8;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm0 + i * 16 + (kF64 ? lk + 4 * r : 4 * lk + r);
-        const int gn = n0 + wn0 + j * 16 + lr;
+      for (int r = 0; r < NACC; ++r) {
+        const int rw = BS == 32 ? (r % 4) + 8 * (r / 4) + 4 * lk : kF64 ? lk + 4 * r : 4 * lk + r;
+        const int gm = m0 + wm0 + i * BS + rw;
+        const int gn = n0 + wn0 + j * BS + lr;
         if (gm < M && gn < N) {
           TC *p = Cz + (long)gm * ldc + gn;
           using RC = typename real_of<TC>::type;
@@ -251,26 +274,28 @@ void cgemm_kernel(
 }
 
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
-          int RM = 0>
+          int RM = 0, int WGM = 2, int WGN = 2, int BS = 16>
 hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   const long total = (long)tm * tn * g.nsplit;
   if (total > (1L << 30)) return hipErrorInvalidValue;
   const int per_xcd = (int)((total + 7) / 8);
   const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
-  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK, RM>), dim3(8 * per_xcd),
-                     dim3(kGT), 0, s, reinterpret_cast<const TA *>(g.A), g.lda,
+  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK, RM, WGM, WGN, BS>),
+                     dim3(8 * per_xcd), dim3(64 * WGM * WGN), 0, s, reinterpret_cast<const TA *>(g.A), g.lda,
                      reinterpret_cast<const TB *>(g.B), g.ldb, reinterpret_cast<TC *>(g.C), g.ldc,
                      g.M, g.N, g.K, g.conjA, g.conjB, g.accumulate, kchunk, g.split_stride, tm, tn,
                      (int)total, per_xcd);
   return hipGetLastError();
 }
 
-// FP64: 64 x 64 tiles, K slices of 8.  FP32: 64 x 64 tiles, or 128 x 64
-// (a whole band block shares one read of the second operand) on request.
+// FP64: 64 x 64 tiles, K slices of 8 (16 x 16 blocks).  FP32: 64 x 64 tiles
+// on four waves (16 x 16 blocks), or the wide tile for the large projector
+// products: 128 x 128 on eight waves with 32 x 32 blocks (half the operand
+// re-reads of 64 x 64, and the faster 32 x 32 instruction).
 template <typename TA, typename TC, int BMODE>
 hipError_t run_f32(const GemmDesc &g, hipStream_t s) {
-  if (g.tile == 1 && g.M > 64) return run_tile<float, TA, float2, TC, BMODE, 128, 64, 16>(g, s);
+  if (g.tile == 1) return run_tile<float, TA, float2, TC, BMODE, 128, 128, 16, 0, 2, 4, 32>(g, s);
   return run_tile<float, TA, float2, TC, BMODE, 64, 64, 16>(g, s);
 }
 
@@ -386,8 +411,10 @@ __global__ __launch_bounds__(256) void dscale_kernel(
 
 }  // namespace
 
-// The Gamma-point forms, 64 x 64 tiles: RM = 1 for beta^H psi (bmode 0, psi
-// read in double), RM = 2 for beta ps (bmode 1, A = ps real, C = hpsi).
+// The Gamma-point forms: RM = 1 for beta^H psi (bmode 0, psi read in
+// double), RM = 2 for beta ps (bmode 1, A = ps real, C = hpsi).  FP32 wide
+// tiles (tile 1): 128 x 256 for beta^H psi (psi re-read once per 256
+// projectors), 128 x 128 for beta ps.
 hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
   if (g.prec == G_F64) {
     if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
@@ -399,9 +426,13 @@ hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
   }
   if (g.tb != T_F2) return hipErrorInvalidValue;
   if (g.rmode == 1 && g.bmode == 0 && g.ta == T_D2 && g.tc == T_F2)
-    return run_tile<float, double2, float2, float2, 0, 64, 64, 16, 1>(g, s);
+    return g.tile == 1
+               ? run_tile<float, double2, float2, float2, 0, 128, 256, 16, 1, 2, 4, 32>(g, s)
+               : run_tile<float, double2, float2, float2, 0, 64, 64, 16, 1>(g, s);
   if (g.rmode == 2 && g.bmode == 1 && g.ta == T_F2 && g.tc == T_D2)
-    return run_tile<float, float2, float2, double2, 1, 64, 64, 16, 2>(g, s);
+    return g.tile == 1
+               ? run_tile<float, float2, float2, double2, 1, 128, 128, 16, 2, 2, 4, 32>(g, s)
+               : run_tile<float, float2, float2, double2, 1, 64, 64, 16, 2>(g, s);
   return hipErrorInvalidValue;
 }
 

@@ -109,6 +109,7 @@ struct qeh_ctx {
                         // 4 lane-quad kernel (FP64)
   int zpair = 0;        // 1: lane-pair K1 / K3 (gmap at natural z)
   int nsplit = 1, kchunk = 0;
+  int wide = 0;         // 1: wide FP32 tiles for the projector products
   int nchunk = 0;
   qeh::FftDim dx{}, dy{}, dz{};
   qeh::PlaneGeom pg{};
@@ -225,7 +226,7 @@ struct GemmDesc {
   int conjA, conjB, accumulate;
   int nsplit, kchunk; long split_stride;
   int prec;
-  int tile;   // FP32 tiles: 0 = 64 x 64, 1 = 128 x 64
+  int tile;   // FP32 tiles: 0 = 64 x 64; 1 = wide (128 x 128, Gamma beta^H psi 128 x 256)
   int rmode;  // 0 complex; 1 only Re(C) wanted (Im written 0); 2 A real (Im A ignored)
 };
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
