@@ -361,20 +361,21 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
     const char *kern = std::getenv("QEH_STICK_KERNEL");
     if (!(kern && std::strcmp(kern, "generic") == 0)) g->zpair = 1;
   }
-  // lane-quad kernel (FP64, N1 = N2 a compiled size): one band per workgroup
-  // by default (QEH_PAIR_PLANES overrides); QEH_PLANE_KERNEL=generic keeps the
-  // fused kernel
+  // lane-quad kernel (N1 = N2 a compiled size: FP64 up to 72, single
+  // precision above the lane-pair sizes): one band per workgroup by default
+  // (QEH_PAIR_PLANES overrides); QEH_PLANE_KERNEL=generic keeps the fused
+  // kernel
   if (g->plane_path == 0 && quad_plane_supported(prec, n1, n2)) {
     const char *kern = std::getenv("QEH_PLANE_KERNEL");
     const bool generic = kern && std::strcmp(kern, "generic") == 0;
     const char *pbs = std::getenv("QEH_PAIR_PLANES");
     int pb = pbs ? std::atoi(pbs) : 1;
     pb = std::max(1, std::min(8, pb));
-    while (pb > 1 && pair_plane_lds_bytes(prec, hm.ext, n2, pb) > (size_t)kLdsMax) --pb;
-    if (!generic && pair_plane_lds_bytes(prec, hm.ext, n2, pb) <= (size_t)kLdsMax) {
+    while (pb > 1 && quad_plane_lds_bytes(prec, hm.ext, n2, pb) > (size_t)kLdsMax) --pb;
+    if (!generic && quad_plane_lds_bytes(prec, hm.ext, n2, pb) <= (size_t)kLdsMax) {
       g->plane_path = 4;
       g->pg.pb = pb;
-      g->pg.lds_pair = pair_plane_lds_bytes(prec, hm.ext, n2, pb);
+      g->pg.lds_pair = quad_plane_lds_bytes(prec, hm.ext, n2, pb);
     }
   }
   g->pg.ext_div = make_fastdiv(hm.ext);

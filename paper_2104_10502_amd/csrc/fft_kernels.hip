@@ -827,21 +827,26 @@ __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__
 }
 
 // ---------------------------------------------------------------- K2, lane quads
-// FP64 form of the register plane pass, for N1 = N2 = N a multiple of 4 with a
-// compiled form: each line belongs to four adjacent lanes holding N/4 points
-// each (quad_inv / quad_fwd; the inverse returns lane-bit-reversed blocks,
-// which is the forward's input layout, so the row chain inverse -> V ->
-// forward moves no data).  The x-extent shift of the rows and the zero /
-// discard slots are those of the lane-pair kernel.  One band per workgroup by
-// default (its column tile is 42 KB at N = 72).
-template <int N>
-__global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 48 ? 3 : 2))) void k2_plane_quad(
-    double2 *__restrict__ sbuf, const double *__restrict__ vs, const int *__restrict__ tidx,
-    const double2 *__restrict__ tw_g, int nst, int n3, int ext, int pb, int nbk, int ngrp,
-    int per_xcd) {
+// Register plane pass for N1 = N2 = N a multiple of 4 with a compiled form:
+// each line belongs to four adjacent lanes holding N/4 points each (quad_inv /
+// quad_fwd; the inverse returns lane-bit-reversed blocks, which is the
+// forward's input layout, so the row chain inverse -> V -> forward moves no
+// data).  The x-extent shift of the rows and the zero / discard slots are
+// those of the lane-pair kernel.  One band per workgroup by default.  FP64
+// (N <= 72, 256 threads): the column tile is 42 KB at N = 72.  Single
+// precision (the boxes above the lane-pair sizes, 512 threads): at N = 160 a
+// lane holds 40 points, and one workgroup (89 KB of column tile at the
+// 512-atom cell's x-extent of 69) fills a CU.
+template <typename C, int N, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
+    NT > 256 ? 2 : (N < 48 ? 3 : 2)))) void k2_plane_quad(
+    C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
+    const int *__restrict__ tidx, const C *__restrict__ tw_g, int nst, int n3, int ext, int pb,
+    int nbk, int ngrp, int per_xcd) {
+  using R = typename real_of<C>::type;
   constexpr int LD = N | 1, Q = N / 4;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double2 *T = reinterpret_cast<double2 *>(smem_raw);
+  C *T = reinterpret_cast<C *>(smem_raw);
   const int id = blockIdx.x;
   const int logical = (id & 7) * per_xcd + (id >> 3);
   if (logical >= ngrp * n3) return;
@@ -851,81 +856,91 @@ __global__ __launch_bounds__(kRT) __attribute__((amdgpu_waves_per_eu(N < 48 ? 3 
   const int np = min(pb, nbk - b0);
   const int tid = threadIdx.x;
   const int tile = ext * LD;
-  const double2 *zslot = T + pb * tile;
-  double2 *dslot = T + pb * tile + 1 + tid;
-  double2 *twq = T + pb * tile + 1 + kRT;   // [4][Q]: row q holds W_N^{q k}
-  const double2 zero = make_double2(0.0, 0.0);
+  const C *zslot = T + pb * tile;
+  C *dslot = T + pb * tile + 1 + tid;
+  C *twq = T + pb * tile + 1 + NT;   // [4][Q]: row q holds W_N^{q k}
+  const C zero = cmk<C>(0, 0);
   const int q = tid & 3;
   const int bq = ((q & 1) << 1) | (q >> 1);   // two-bit reversal of q
-  const regfft::QuadLane<double> ql(q);
-  const double2 *tw = twq + q * Q;
+  const regfft::QuadLane<R> ql(q);
+  const C *tw = twq + q * Q;
 
-  for (int i = tid; i < np * tile; i += kRT) T[i] = zero;
+  for (int i = tid; i < np * tile; i += NT) T[i] = zero;
   if (tid == 0) T[pb * tile] = zero;
-  for (int i = tid; i < 4 * Q; i += kRT) twq[i] = tw_g[((i / Q) * (i % Q)) % N];
+  for (int i = tid; i < 4 * Q; i += NT) twq[i] = tw_g[((i / Q) * (i % Q)) % N];
   __syncthreads();
   for (int p = 0; p < np; ++p) {
-    const double2 *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
-    double2 *Tp = T + p * tile;
-    for (int s = tid; s < nst; s += kRT) Tp[tidx[s]] = plane[s];
+    const C *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    C *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += NT) Tp[tidx[s]] = plane[s];
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * ext; j += kRT) {
-    double2 *col = T + (j >> 2) * LD;
-    double2 v[Q];
+  for (int j = tid; j < 4 * np * ext; j += NT) {
+    C *col = T + (j >> 2) * LD;
+    C v[Q];
 #pragma unroll
     for (int n = 0; n < Q; ++n) v[n] = col[4 * n + q];
-    regfft::quad_inv<double2, N>(v, tw, ql);
-    double2 *out = col + Q * bq;
+    regfft::quad_inv<C, N>(v, tw, ql);
+    C *out = col + Q * bq;
 #pragma unroll
     for (int k = 0; k < Q; ++k) out[k] = v[k];
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * N; j += kRT) {
+  for (int j = tid; j < 4 * np * N; j += NT) {
     const int r = j >> 2;
     const int p = r / N;
     const int y = r - p * N;
-    double2 *row = T + p * tile + y;
-    double2 v[Q];
+    C *row = T + p * tile + y;
+    C v[Q];
 #pragma unroll
     for (int n = 0; n < Q; ++n) {
       const int c = 4 * n + q;
-      const double2 *a = c < ext ? row + c * LD : zslot;
+      const C *a = c < ext ? row + c * LD : zslot;
       v[n] = *a;
     }
-    regfft::quad_inv<double2, N>(v, tw, ql);
-    const double *vr = vs + ((size_t)z * N + y) * N + Q * bq;
+    regfft::quad_inv<C, N>(v, tw, ql);
+    const R *vr = vs + ((size_t)z * N + y) * N + Q * bq;
 #pragma unroll
     for (int k = 0; k < Q; ++k) v[k] = cscale(v[k], vr[k]);
-    regfft::quad_fwd<double2, N>(v, tw, ql);
+    regfft::quad_fwd<C, N>(v, tw, ql);
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
       const int c = 4 * m + q;
-      double2 *a = c < ext ? row + c * LD : dslot;
+      C *a = c < ext ? row + c * LD : dslot;
       *a = v[m];
     }
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * ext; j += kRT) {
-    double2 *col = T + (j >> 2) * LD;
-    const double2 *in = col + Q * bq;
-    double2 v[Q];
+  for (int j = tid; j < 4 * np * ext; j += NT) {
+    C *col = T + (j >> 2) * LD;
+    const C *in = col + Q * bq;
+    C v[Q];
 #pragma unroll
     for (int x = 0; x < Q; ++x) v[x] = in[x];
-    regfft::quad_fwd<double2, N>(v, tw, ql);
+    regfft::quad_fwd<C, N>(v, tw, ql);
 #pragma unroll
     for (int m = 0; m < Q; ++m) col[4 * m + q] = v[m];
   }
   __syncthreads();
   for (int p = 0; p < np; ++p) {
-    double2 *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
-    const double2 *Tp = T + p * tile;
-    for (int s = tid; s < nst; s += kRT) plane[s] = Tp[tidx[s]];
+    C *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
+    const C *Tp = T + p * tile;
+    for (int s = tid; s < nst; s += NT) plane[s] = Tp[tidx[s]];
   }
 }
 
+// threads of the lane-quad plane workgroup.  Single precision: 512 (two
+// waves per SIMD); at N >= 120 that budget spills a few registers (to 120
+// bytes per lane at N = 160) and is still faster than one wave per SIMD
+// without spills (1.74 ms against 2.03 ms per 64-pair launch at 160^2).
+constexpr int quad_plane_threads(bool fp64, int n) { return fp64 ? kRT : 512; }
+
 // Box sizes with a compiled lane-quad kernel (double precision).
 #define QEH_QUAD_SIZES(X) X(16) X(20) X(24) X(32) X(36) X(40) X(48) X(60) X(64) X(72)
+
+// Box sizes with a compiled single-precision lane-quad kernel (above the
+// lane-pair sizes).
+#define QEH_QUAD32_SIZES(X) X(96) X(120) X(128) X(144) X(160)
 
 // Box sizes with a compiled lane-pair kernel (single precision).
 #define QEH_PAIR_SIZES(X) \
@@ -1345,24 +1360,35 @@ hipError_t k3_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi
   }
 }
 
-template <int N> hipError_t k2_quad_launch(const qeh_ctx *c, int nbk) {
+template <typename C, int N> hipError_t k2_quad_launch(const qeh_ctx *c, int nbk) {
+  using R = typename real_of<C>::type;
+  constexpr int NT = quad_plane_threads(sizeof(R) == 8, N);
   const int pb = c->pg.pb;
   const int ngrp = (nbk + pb - 1) / pb;
   const int per_xcd = (ngrp * c->n3 + 7) / 8;
-  allow_lds(k2_plane_quad<N>, c->pg.lds_pair);
-  hipLaunchKernelGGL(k2_plane_quad<N>, dim3(8 * per_xcd), dim3(kRT), c->pg.lds_pair, c->stream,
-                     reinterpret_cast<double2 *>(c->d.sbuf),
-                     reinterpret_cast<const double *>(c->d.vs), c->d.tidx,
-                     reinterpret_cast<const double2 *>(c->d.tw) + c->tw_off[0], c->nst, c->n3,
-                     c->ext, pb, nbk, ngrp, per_xcd);
+  allow_lds(k2_plane_quad<C, N, NT>, c->pg.lds_pair);
+  hipLaunchKernelGGL((k2_plane_quad<C, N, NT>), dim3(8 * per_xcd), dim3(NT), c->pg.lds_pair,
+                     c->stream, reinterpret_cast<C *>(c->d.sbuf),
+                     reinterpret_cast<const R *>(c->d.vs), c->d.tidx,
+                     reinterpret_cast<const C *>(c->d.tw) + c->tw_off[0], c->nst, c->n3, c->ext,
+                     pb, nbk, ngrp, per_xcd);
   return hipGetLastError();
 }
 
 hipError_t k2_quad_impl(const qeh_ctx *c, int nbk) {
+  if (c->prec == QEH_FP64) {
+    switch (c->n1) {
+#define QEH_QUAD_CASE(NN) \
+  case NN: return k2_quad_launch<double2, NN>(c, nbk);
+      QEH_QUAD_SIZES(QEH_QUAD_CASE)
+#undef QEH_QUAD_CASE
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (c->n1) {
 #define QEH_QUAD_CASE(NN) \
-  case NN: return k2_quad_launch<NN>(c, nbk);
-    QEH_QUAD_SIZES(QEH_QUAD_CASE)
+  case NN: return k2_quad_launch<float2, NN>(c, nbk);
+    QEH_QUAD32_SIZES(QEH_QUAD_CASE)
 #undef QEH_QUAD_CASE
     default: return hipErrorInvalidValue;
   }
@@ -1451,14 +1477,30 @@ hipError_t launch_density_reduce(const double *partial, int nsub, long npts, dou
 bool pair_z_supported(int prec, int n3) { return pair_plane_supported(prec, n3, n3); }
 
 bool quad_plane_supported(int prec, int n1, int n2) {
-  if (prec != QEH_FP64 || n1 != n2) return false;
+  if (n1 != n2) return false;
+  if (prec == QEH_FP64) {
+    switch (n1) {
+#define QEH_QUAD_CASE(NN) \
+  case NN: return true;
+      QEH_QUAD_SIZES(QEH_QUAD_CASE)
+#undef QEH_QUAD_CASE
+      default: return false;
+    }
+  }
   switch (n1) {
 #define QEH_QUAD_CASE(NN) \
   case NN: return true;
-    QEH_QUAD_SIZES(QEH_QUAD_CASE)
+    QEH_QUAD32_SIZES(QEH_QUAD_CASE)
 #undef QEH_QUAD_CASE
     default: return false;
   }
+}
+
+size_t quad_plane_lds_bytes(int prec, int ext, int n2, int pb) {
+  const bool f64 = prec == QEH_FP64;
+  const size_t c = f64 ? 16 : 8;
+  // column tiles, zero slot, discard slots, the [4][N/4] twiddle table
+  return c * ((size_t)pb * ext * (n2 | 1) + 1 + quad_plane_threads(f64, n2) + n2);
 }
 
 size_t pair_z_lds_bytes(int n3) { return 8 * (size_t)kPairSticks * (n3 | 1); }
@@ -1476,9 +1518,8 @@ bool pair_plane_supported(int prec, int n1, int n2) {
 
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb) {
   const size_t c = prec == QEH_FP64 ? 16 : 8;
-  // column tiles, zero slot, discard slots, and (lane-quad kernel) the [4][N/4]
-  // twiddle table
-  return c * ((size_t)pb * ext * (n2 | 1) + 1 + kRT + (prec == QEH_FP64 ? n2 : 0));
+  // column tiles, zero slot, discard slots
+  return c * ((size_t)pb * ext * (n2 | 1) + 1 + kRT);
 }
 
 size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {

@@ -156,6 +156,7 @@ bool pair_z_supported(int prec, int n3);
 bool quad_plane_supported(int prec, int n1, int n2);
 size_t pair_z_lds_bytes(int n3);
 size_t pair_plane_lds_bytes(int prec, int ext, int n2, int pb);
+size_t quad_plane_lds_bytes(int prec, int ext, int n2, int pb);
 
 // Charge density: row groups of rg rows, subgroups of bsub bands.
 struct DensityGeom {

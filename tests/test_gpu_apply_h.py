@@ -281,3 +281,23 @@ def test_quad_matches_generic_fp64_c2(pb, monkeypatch):
     b, cb = run(c, psi, 0, 5)
     assert ca.info()["plane_path"] == 4 and cb.info()["plane_path"] == 0
     assert _rel_l2(a, b).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [96, 120])
+def test_apply_h_quad_single_precision(n, monkeypatch):
+    # single-precision lane-quad plane kernel (boxes above the lane-pair
+    # sizes): N1 = N2 = n, N3 = 40, a non-cubic lattice, general k, s/p/d
+    # projectors, 7 bands in blocks of 3 (ragged); against the oracle at the
+    # mixed-form bar, and against the fused LDS-pass kernel
+    c = cellgen.make_cell("t", lattice=np.diag([22.0, 22.0, 9.0]), frac=np.array(
+        [[0.1, 0.2, 0.3], [0.6, 0.5, 0.9], [0.3, 0.8, 0.45]]), kpt=(0.11, -0.07, 0.23),
+        ecutwfc=14.0, fft=(n, n, 40), proj="s2pd", dfixed=False, nbnd=7)
+    psi = cellgen.make_psi0(c.npw, 7, seed=51)
+    got, ctx = run(c, psi, 1, 3)
+    assert ctx.info()["plane_path"] == 4
+    ref = oracle.apply_h(c, psi)
+    assert _rel_l2(got, ref).max() < 1e-5, _rel_l2(got, ref).max()
+    monkeypatch.setenv("QEH_PLANE_KERNEL", "generic")
+    gen, cg = run(c, psi, 1, 3)
+    assert cg.info()["plane_path"] == 0
+    assert _rel_l2(got, gen).max() < 1e-5
