@@ -26,6 +26,8 @@ exascale):
   ``density_direct`` sums the plane waves point by point (tiny cells).
 * ``gamma.expand`` / ``gamma.restrict``: real wavefunctions at k = 0 stored
   over half the sphere, rebuilt as full-sphere vectors for the operators above.
+* ``cg``: the band-by-band preconditioned conjugate-gradient eigensolver,
+  the paper's other iterative solver (same section).
 * ``overlap``: the overlap operator S = 1 + sum |beta> q <beta| of ultrasoft /
   PAW pseudopotentials (also among the ported kernels) and the generalized
   Davidson for H psi = eps S psi.
@@ -46,12 +48,13 @@ from .dft import dft_matrix, dft_axis, inv3, fwd3
 from .hamiltonian import (kinetic, vloc_psi, vnl_psi, apply_h, dense_h, dense_eigs,
                           vloc_coeffs, hdiag)
 from .davidson import davidson, rayleigh_ritz
+from .cg import cg
 from .density import cell_volume, density, density_direct, psi_real_space
 from .beta import beta_projectors, radial_transform, real_harmonics, spherical_bessel
 from . import gamma
 from . import overlap
 
 __all__ = ["dft_matrix", "dft_axis", "inv3", "fwd3", "kinetic", "vloc_psi", "vnl_psi",
-           "apply_h", "dense_h", "dense_eigs", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz",
+           "apply_h", "dense_h", "dense_eigs", "vloc_coeffs", "hdiag", "davidson", "rayleigh_ritz", "cg",
            "cell_volume", "density", "density_direct", "psi_real_space", "beta_projectors",
            "radial_transform", "real_harmonics", "spherical_bessel", "gamma", "overlap"]
