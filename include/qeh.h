@@ -310,6 +310,35 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
                         double *eig, const qeh_dav_opts *opts, void *work,
                         size_t work_bytes, qeh_dav_info *info);
 
+/* Band-by-band preconditioned conjugate-gradient eigensolver, the paper's
+ * other iterative solver of the Kohn-Sham problem beside Davidson (section
+ * "Evolution of the GPU-enabled version"): the lowest nb eigenpairs of H (the
+ * standard problem: a context with q blocks is rejected), starting from
+ * psi_inout (DEVICE, nb rows, ldpsi >= npw).  Steps: Rayleigh-Ritz of the
+ * starting block; then for each band in turn, conjugate-gradient minimisation
+ * of the Rayleigh quotient with the Davidson preconditioner
+ * 1 / sqrt(1 + (diag(H)_G - lam)^2), the search direction kept orthogonal to
+ * the bands below (Polak-Ribiere conjugation, restarted when negative) and an
+ * exact line minimisation over the current vector and the direction; a final
+ * Rayleigh-Ritz of the block.  Band b stops when ||H x - lam x|| <= thr
+ * (thr = rtol, or max(rtol, 1e-5) for QEH_MIXED) or after maxiter
+ * iterations (QEH_ERR_NOT_CONVERGED, results written).  1 <= nb <= 512 (the
+ * block steps use the library's subspace solver).  H is applied one band at a
+ * time, so the solver is latency-bound; Davidson is the throughput path.
+ * On return psi_inout holds orthonormal Ritz vectors and eig (HOST, nb
+ * doubles) their ascending values; info (may be NULL): iters = CG iterations
+ * over all bands, notconv = bands stopped at maxiter, resid_max = the final
+ * Ritz residual.  Blocks until done.  Errors: QEH_ERR_INVALID (sizes, nulls,
+ * overlap context), QEH_ERR_NOMEM (short or misaligned work),
+ * QEH_ERR_NUMERIC (non-finite input or residual), QEH_ERR_CHOLESKY. */
+typedef struct {
+  double rtol;    /* residual 2-norm threshold (Ry); 0 = 1e-8 */
+  int maxiter;    /* iterations per band; 0 = 100 */
+} qeh_cg_opts;
+qeh_status qeh_cg_plan(const qeh_ctx *ctx, int nb, size_t *work_bytes);
+qeh_status qeh_cg(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi, double *eig,
+                  const qeh_cg_opts *opts, void *work, size_t work_bytes, qeh_dav_info *info);
+
 /* Reverse-communication Davidson: the solver hands every H|psi> product to
  * the caller, who computes it with a Hamiltonian builder of its own and
  * passes the result back (the solver library's reverse communication

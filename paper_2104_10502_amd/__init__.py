@@ -68,6 +68,10 @@ class DavOpts(ctypes.Structure):
                 ("subspace", ctypes.c_int), ("refine", ctypes.c_void_p)]
 
 
+class CgOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("maxiter", ctypes.c_int)]
+
+
 class RciRequest(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int),
                 ("ld", ctypes.c_int)]
@@ -97,6 +101,9 @@ _SIGS = {
     "qeh_davidson_plan": ([_vp, ctypes.c_int, ctypes.POINTER(DavOpts), _sz_p], ctypes.c_int),
     "qeh_davidson": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(DavOpts),
                       _vp, ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
+    "qeh_cg_plan": ([_vp, ctypes.c_int, _sz_p], ctypes.c_int),
+    "qeh_cg": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p, ctypes.POINTER(CgOpts), _vp,
+                ctypes.c_size_t, ctypes.POINTER(DavInfo)], ctypes.c_int),
     "qeh_dav_rci_create": ([_vp, ctypes.c_int, _vp, ctypes.c_int, _c_dbl_p,
                             ctypes.POINTER(DavOpts), _vp, ctypes.c_size_t, ctypes.POINTER(_vp)],
                            ctypes.c_int),
@@ -520,6 +527,31 @@ class Context:
                                eig.ctypes.data_as(_c_dbl_p), ctypes.byref(o),
                                _vp(work.data_ptr()), int(work.numel()), ctypes.byref(info))
         _check(st, "qeh_davidson", allow=(QEH_ERR_NOT_CONVERGED,) if allow_notconv else ())
+        d = info.as_dict()
+        d["status"] = st
+        return eig, d
+
+    def cg_plan(self, nb):
+        n = ctypes.c_size_t()
+        _check(_lib.qeh_cg_plan(self._h, int(nb), ctypes.byref(n)), "qeh_cg_plan")
+        return int(n.value)
+
+    def cg(self, psi, rtol=1e-8, maxiter=0, work=None, allow_notconv=False):
+        """In-place band-by-band conjugate gradient on psi (nb, npw) complex128;
+        returns (eig ndarray, info dict) like davidson()."""
+        torch = _torch()
+        psi = self._bands(psi)
+        nb = psi.shape[0]
+        need = self.cg_plan(nb)
+        if work is None or work.numel() < need:
+            work = torch.empty(max(need, 256), dtype=torch.uint8, device=psi.device)
+        o = CgOpts(float(rtol), int(maxiter))
+        eig = np.zeros(nb, dtype=np.float64)
+        info = DavInfo()
+        st = _lib.qeh_cg(self._h, nb, _vp(psi.data_ptr()), psi.stride(0),
+                         eig.ctypes.data_as(_c_dbl_p), ctypes.byref(o), _vp(work.data_ptr()),
+                         int(work.numel()), ctypes.byref(info))
+        _check(st, "qeh_cg", allow=(QEH_ERR_NOT_CONVERGED,) if allow_notconv else ())
         d = info.as_dict()
         d["status"] = st
         return eig, d

@@ -18,8 +18,8 @@ OUT = os.path.join(HERE, "libqeh.so")
 BUILD = os.path.join(ROOT, "_build")
 
 HIP_SOURCES = ["fft_kernels.hip", "gemm_kernels.hip", "dav_kernels.hip", "beta_kernels.hip",
-               "eigh_kernels.hip"]
-CPP_SOURCES = ["ctx.cpp", "davidson.cpp", "server.cpp", "beta.cpp"]
+               "eigh_kernels.hip", "cg_kernels.hip"]
+CPP_SOURCES = ["ctx.cpp", "davidson.cpp", "server.cpp", "beta.cpp", "cg.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(ROOT, "include")]

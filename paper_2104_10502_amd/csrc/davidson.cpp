@@ -43,7 +43,7 @@ qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double
 
 namespace {
 
-constexpr int kMaxSplit = 32;
+constexpr int kMaxSplit = kReduceMaxSplit;
 
 size_t bump2(size_t *cur, size_t bytes) {
   const size_t o = *cur;
@@ -89,6 +89,8 @@ qeh_status solver_bytes(int n, bool real, size_t *out) {
   cache[key] = sz;
   return QEH_OK;
 }
+
+}  // namespace
 
 // out(i, j) = sum_G conj(X_i[G]) Y_j[G] for i < nrow, j < ncol; out col-major
 // with ld.  K = npw is long: split into fixed chunks whose partial products
@@ -212,7 +214,6 @@ hipError_t rotate(const qeh_ctx *c, const double2 *Y, int ld, int n, int nb, con
   return launch_cgemm(g, c->stream);
 }
 
-}  // namespace
 
 void EvPool::start(hipStream_t s) {
   while (ev.size() < used + 2) {

@@ -231,6 +231,63 @@ struct GemmDesc {
   int rmode;  // 0 complex; 1 only Re(C) wanted (Im written 0); 2 A real (Im A ignored)
 };
 hipError_t launch_cgemm(const GemmDesc &g, hipStream_t s);
+
+// ---- Davidson building blocks shared with the CG solver (davidson.cpp) ----
+// out(i, j) = <X_i|Y_j> for i < nrow, j < ncol (col-major, ld), FP64 MFMA,
+// split-K partials in `part` (16 * 32 * nrow * ncol bytes) summed in a fixed
+// order; real inner products on Gamma contexts.
+hipError_t reduce_cols(const qeh_ctx *c, const double2 *X, int nrow, const double2 *Y, int ncol,
+                       double2 *out, int ld, double2 *part);
+// rows b < nb: out_b = sum_j Y(j, b) X_j  (Y col-major ld, j < n)
+hipError_t rotate(const qeh_ctx *c, const double2 *Y, int ld, int n, int nb, const double2 *X,
+                  double2 *out);
+constexpr int kReduceMaxSplit = 32;
+
+// ---- conjugate-gradient solver kernels (cg_kernels.hip) ----
+// Slots of the solver's device scalar array (doubles; complex values take two).
+enum CgSlot {
+  kCgLam = 0,     // Rayleigh quotient of the current band
+  kCgRR = 2,      // <r|r>
+  kCgGpr = 4,     // <g_prev|r>
+  kCgGam = 6,     // <g|r>
+  kCgGamp = 8,    // previous <g|r>
+  kCgXD = 10,     // <x|d>
+  kCgDD = 12,     // <d|d>
+  kCgB = 14,      // <x|H dn>
+  kCgC = 16,      // <dn|H dn>
+  kCgBeta = 18,   // conjugation factor
+  kCgC0 = 20,     // rotation of (x, dn): c0 (real)
+  kCgC1 = 22,     //   and c1 (complex)
+  kCgInvD = 24,   // 1 / ||d - <x|d> x||
+  kCgXX = 26,     // <x|x> at a band's start
+  kCgInvX = 28,   // 1 / ||x||
+  kCgFirst = 30,  // 1 on a band's first iteration
+  kCgSlots = 32
+};
+constexpr int kCgDotBlocks = 64;   // stage-1 blocks per inner product
+constexpr int kCgMaxDots = 4;      // inner products per launch
+struct CgDots {
+  const double2 *a[kCgMaxDots];
+  const double2 *b[kCgMaxDots];
+  int dst[kCgMaxDots];   // slot of <a|b> (re, im)
+};
+// inner products <a_q|b_q> into sc[dst_q] (part: 2 * kCgDotBlocks * npairs doubles)
+hipError_t launch_cg_dots(const CgDots &p, int npairs, int npw, int gamma, double *part,
+                          double *sc, hipStream_t s);
+hipError_t launch_cg_resid(const double2 *x, const double2 *hx, const double *hdiag,
+                           const double *sc, double2 *r, double2 *g, int npw, int gamma,
+                           hipStream_t s);
+hipError_t launch_cg_project(double2 *g, const double2 *X, long ldx, const double2 *coef, int m,
+                             int npw, hipStream_t s);
+hipError_t launch_cg_scale(double2 *x, const double *sc, int npw, hipStream_t s);
+hipError_t launch_cg_dir(const double2 *g, double2 *d, double2 *gp, const double *sc, int npw,
+                         hipStream_t s);
+hipError_t launch_cg_dnorm(double2 *d, const double2 *x, double2 *dn, const double *sc, int npw,
+                           hipStream_t s);
+hipError_t launch_cg_update(double2 *x, double2 *hx, const double2 *dn, const double2 *hd,
+                            const double *sc, int npw, hipStream_t s);
+hipError_t launch_cg_scalar(double *sc, int phase, hipStream_t s);
+
 // C[m][n] (+)= sum_s part[s*stride + m*ldp + n], summed in double in split order.
 hipError_t launch_splitk_reduce(const void *part, int tp, long stride, int nsplit, int M, int N,
                                 long ldp, double2 *C, long ldc, int accumulate, hipStream_t s);

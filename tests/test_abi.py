@@ -48,11 +48,12 @@ def test_struct_layout_matches_header(tmp_path):
 #include <stddef.h>
 #include "qeh.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(qeh_cell),
          offsetof(qeh_cell, npw), offsetof(qeh_cell, miller), offsetof(qeh_cell, beta),
          offsetof(qeh_cell, block), sizeof(qeh_dav_opts), sizeof(qeh_dav_info),
          offsetof(qeh_cell, projgen), sizeof(qeh_projgen), offsetof(qeh_projgen, dq),
-         offsetof(qeh_projgen, tab), sizeof(qeh_rci_request), offsetof(qeh_rci_request, n));
+         offsetof(qeh_projgen, tab), sizeof(qeh_rci_request), offsetof(qeh_rci_request, n),
+         sizeof(qeh_cg_opts));
   return 0;
 }
 ''')
@@ -66,7 +67,7 @@ int main(void) {
     assert vals == [ctypes.sizeof(C), C.npw.offset, C.miller.offset, C.beta.offset,
                     C.block.offset, ctypes.sizeof(q.DavOpts), ctypes.sizeof(q.DavInfo),
                     C.projgen.offset, ctypes.sizeof(P), P.dq.offset, P.tab.offset,
-                    ctypes.sizeof(q.RciRequest), q.RciRequest.n.offset]
+                    ctypes.sizeof(q.RciRequest), q.RciRequest.n.offset, ctypes.sizeof(q.CgOpts)]
 
 
 def _plan(cell, **kw):
@@ -176,6 +177,14 @@ def test_reverse_communication_null_arguments():
     assert st == q.QEH_ERR_INVALID and out.value is None
     assert q._lib.qeh_dav_rci_create(None, 4, None, 0, None, None, None, 0, None) == \
         q.QEH_ERR_INVALID
+
+
+def test_cg_null_arguments():
+    # argument checks of the CG entry points, before any device call
+    q = _q()
+    n = ctypes.c_size_t()
+    assert q._lib.qeh_cg_plan(None, 4, ctypes.byref(n)) == q.QEH_ERR_INVALID
+    assert q._lib.qeh_cg(None, 4, None, 0, None, None, None, 0, None) == q.QEH_ERR_INVALID
 
 
 def test_status_strings():
