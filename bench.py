@@ -320,7 +320,32 @@ def davidson_leg(q, torch, name):
         torch.cuda.empty_cache()
     res["npw_stored"], res["bands"], res["gamma"] = cell.npw, nb, name != "c2"
     res["subspace_solver"] = "own HIP kernels" if name == "c2" else "rocSOLVER (basis > 512)"
+    if name == "c2":
+        res["cg_fp64_1e-8"] = cg_leg(q, torch, cell, psi0, gold)
     return res
+
+
+def cg_leg(q, torch, cell, psi0, gold):
+    """The band-by-band conjugate-gradient solver on the same cell, start and
+    residual threshold as Davidson's FP64 1e-8 Ry run (H applied one band at a
+    time: the latency-bound comparison solver)."""
+    ctx = q.Context.from_cell(cell, precision=q.QEH_FP64, block=cell.block)
+    p = torch.from_numpy(psi0).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, info = ctx.cg(p, rtol=1e-8, maxiter=400, allow_notconv=True)
+    torch.cuda.synchronize()
+    r = dict(seconds=time.perf_counter() - t0, status=info["status"], iters=info["iters"],
+             notconv=info["notconv"], band_applies=info["band_applies"], t_hpsi=info["t_hpsi"],
+             t_subspace=info["t_subspace"], resid_max=info["resid_max"])
+    if gold is not None:
+        m = min(len(gold), len(eig))
+        r["max_err_vs_oracle_Ry"] = float(np.abs(np.sort(eig)[:m] - gold[:m]).max())
+    print("# cg c2: %s" % json.dumps(r), file=sys.stderr, flush=True)
+    ctx.close()
+    del p
+    torch.cuda.empty_cache()
+    return r
 
 
 def time_density(q, torch, cell, prec, nb, steps, warmup):
