@@ -25,7 +25,7 @@ oracle values, a replay of the served request trace (``serve``), and
 the headline cell on the host cores.
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--serve SECONDS]
-                      [--no-cpu] [--no-davidson] [--no-extras]
+                      [--no-cpu] [--no-davidson] [--no-extras] [--no-cg]
 """
 
 from __future__ import annotations
@@ -266,7 +266,7 @@ def golden_eigs(name):
     return np.loadtxt(path)
 
 
-def davidson_leg(q, torch, name):
+def davidson_leg(q, torch, name, with_cg=True):
     """Block Davidson to converged eigenvalues on a named cell.  The 64-atom
     cell runs at its k-point (complex, 128 bands, basis up to 512 vectors); the
     256- and 512-atom Gamma cells run on the Gamma path with projectors built on
@@ -320,7 +320,7 @@ def davidson_leg(q, torch, name):
         torch.cuda.empty_cache()
     res["npw_stored"], res["bands"], res["gamma"] = cell.npw, nb, name != "c2"
     res["subspace_solver"] = "own HIP kernels" if name == "c2" else "rocSOLVER (basis > 512)"
-    if name == "c2":
+    if name == "c2" and with_cg:
         res["cg_fp64_1e-8"] = cg_leg(q, torch, cell, psi0, gold)
     return res
 
@@ -593,6 +593,8 @@ def main():
                     help="skip the Davidson time-to-solution legs")
     ap.add_argument("--davidson-cells", default="c2,c3,c5",
                     help="comma-separated cells of the Davidson legs (c2, c3, c5)")
+    ap.add_argument("--no-cg", action="store_true",
+                    help="skip the conjugate-gradient comparison beside the 64-atom Davidson leg")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the complex-k = 0 and 64-atom legs (density, projectors, Gamma)")
     ap.add_argument("--serve", type=float, default=5.0,
@@ -710,7 +712,7 @@ def main():
         print("# 64-atom extras done", file=sys.stderr, flush=True)
     if not a.no_davidson:
         for name in [x for x in a.davidson_cells.split(",") if x in ("c2", "c3", "c5")]:
-            out["davidson_%s" % name] = davidson_leg(q, torch, name)
+            out["davidson_%s" % name] = davidson_leg(q, torch, name, with_cg=not a.no_cg)
     if a.calibrate_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

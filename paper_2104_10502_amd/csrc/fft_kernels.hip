@@ -826,25 +826,45 @@ __global__ __launch_bounds__(256) void density_reduce(const double *__restrict__
   }
 }
 
-// ---------------------------------------------------------------- K2, lane quads
-// Register plane pass for N1 = N2 = N a multiple of 4 with a compiled form:
-// each line belongs to four adjacent lanes holding N/4 points each (quad_inv /
-// quad_fwd; the inverse returns lane-bit-reversed blocks, which is the
-// forward's input layout, so the row chain inverse -> V -> forward moves no
-// data).  The x-extent shift of the rows and the zero / discard slots are
-// those of the lane-pair kernel.  One band per workgroup by default.  FP64
-// (N <= 72, 256 threads): the column tile is 42 KB at N = 72.  Single
-// precision (the boxes above the lane-pair sizes, 512 threads): at N = 160 a
-// lane holds 40 points, and one workgroup (89 KB of column tile at the
-// 512-atom cell's x-extent of 69) fills a CU.
-template <typename C, int N, int NT>
+// ---------------------------------------------------------------- K2, lane quads / octets
+// Register plane pass for N1 = N2 = N with a compiled form: each line belongs
+// to L adjacent lanes holding N/L points each (L = 4: quad_inv / quad_fwd;
+// L = 8, single precision: oct_inv / oct_fwd).  The inverse returns
+// lane-bit-reversed blocks, which is the forward's input layout, so the row
+// chain inverse -> V -> forward moves no data.  The x-extent shift of the rows
+// and the zero / discard slots are those of the lane-pair kernel.  One band per
+// workgroup by default.  FP64 (lane quads, N <= 72, 256 threads): the column
+// tile is 42 KB at N = 72.  Single precision (the boxes above the lane-pair
+// sizes, 512 threads): lane quads at N = 96, lane octets at N >= 120 (20 points
+// per lane at N = 160, where quads need 40 and spill); at the 512-atom cell
+// one workgroup (89 KB of column tile for its x-extent of 69) fills a CU.
+template <int L> __device__ __forceinline__ int lane_rev(int o) {
+  return L == 4 ? (((o & 1) << 1) | (o >> 1)) : (((o & 1) << 2) | (o & 2) | (o >> 2));
+}
+
+template <typename C, int N, int L> struct LineLanes;
+template <typename C, int N> struct LineLanes<C, N, 4> {
+  regfft::QuadLane<typename real_of<C>::type> ql;
+  __device__ explicit LineLanes(int o) : ql(o) {}
+  __device__ void inv(C *v, const C *tw) const { regfft::quad_inv<C, N>(v, tw, ql); }
+  __device__ void fwd(C *v, const C *tw) const { regfft::quad_fwd<C, N>(v, tw, ql); }
+};
+template <int N> struct LineLanes<float2, N, 8> {
+  regfft::OctLane ol;
+  __device__ explicit LineLanes(int o) : ol(o) {}
+  __device__ void inv(float2 *v, const float2 *tw) const { regfft::oct_inv<N>(v, tw, ol); }
+  __device__ void fwd(float2 *v, const float2 *tw) const { regfft::oct_fwd<N>(v, tw, ol); }
+};
+
+template <typename C, int N, int NT, int L>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
-    NT > 256 ? 2 : (N < 48 ? 3 : 2)))) void k2_plane_quad(
+    NT > 256 ? 2 : (N < 48 ? 3 : 2)))) void k2_plane_lanes(
     C *__restrict__ sbuf, const typename real_of<C>::type *__restrict__ vs,
     const int *__restrict__ tidx, const C *__restrict__ tw_g, int nst, int n3, int ext, int pb,
     int nbk, int ngrp, int per_xcd) {
   using R = typename real_of<C>::type;
-  constexpr int LD = N | 1, Q = N / 4;
+  constexpr int LD = N | 1, Q = N / L;
+  static_assert(Q * L == N, "N must be a multiple of the lanes per line");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *T = reinterpret_cast<C *>(smem_raw);
   const int id = blockIdx.x;
@@ -858,16 +878,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
   const int tile = ext * LD;
   const C *zslot = T + pb * tile;
   C *dslot = T + pb * tile + 1 + tid;
-  C *twq = T + pb * tile + 1 + NT;   // [4][Q]: row q holds W_N^{q k}
+  C *twl = T + pb * tile + 1 + NT;   // [L][Q]: row o holds W_N^{o k}
   const C zero = cmk<C>(0, 0);
-  const int q = tid & 3;
-  const int bq = ((q & 1) << 1) | (q >> 1);   // two-bit reversal of q
-  const regfft::QuadLane<R> ql(q);
-  const C *tw = twq + q * Q;
+  const int o = tid & (L - 1);
+  const int bo = lane_rev<L>(o);
+  const LineLanes<C, N, L> ln(o);
+  const C *tw = twl + o * Q;
 
   for (int i = tid; i < np * tile; i += NT) T[i] = zero;
   if (tid == 0) T[pb * tile] = zero;
-  for (int i = tid; i < 4 * Q; i += NT) twq[i] = tw_g[((i / Q) * (i % Q)) % N];
+  for (int i = tid; i < L * Q; i += NT) twl[i] = tw_g[((i / Q) * (i % Q)) % N];
   __syncthreads();
   for (int p = 0; p < np; ++p) {
     const C *plane = sbuf + ((size_t)(b0 + p) * n3 + z) * nst;
@@ -875,51 +895,51 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
     for (int s = tid; s < nst; s += NT) Tp[tidx[s]] = plane[s];
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * ext; j += NT) {
-    C *col = T + (j >> 2) * LD;
+  for (int j = tid; j < L * np * ext; j += NT) {
+    C *col = T + (j / L) * LD;
     C v[Q];
 #pragma unroll
-    for (int n = 0; n < Q; ++n) v[n] = col[4 * n + q];
-    regfft::quad_inv<C, N>(v, tw, ql);
-    C *out = col + Q * bq;
+    for (int n = 0; n < Q; ++n) v[n] = col[L * n + o];
+    ln.inv(v, tw);
+    C *out = col + Q * bo;
 #pragma unroll
     for (int k = 0; k < Q; ++k) out[k] = v[k];
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * N; j += NT) {
-    const int r = j >> 2;
+  for (int j = tid; j < L * np * N; j += NT) {
+    const int r = j / L;
     const int p = r / N;
     const int y = r - p * N;
     C *row = T + p * tile + y;
     C v[Q];
 #pragma unroll
     for (int n = 0; n < Q; ++n) {
-      const int c = 4 * n + q;
+      const int c = L * n + o;
       const C *a = c < ext ? row + c * LD : zslot;
       v[n] = *a;
     }
-    regfft::quad_inv<C, N>(v, tw, ql);
-    const R *vr = vs + ((size_t)z * N + y) * N + Q * bq;
+    ln.inv(v, tw);
+    const R *vr = vs + ((size_t)z * N + y) * N + Q * bo;
 #pragma unroll
     for (int k = 0; k < Q; ++k) v[k] = cscale(v[k], vr[k]);
-    regfft::quad_fwd<C, N>(v, tw, ql);
+    ln.fwd(v, tw);
 #pragma unroll
     for (int m = 0; m < Q; ++m) {
-      const int c = 4 * m + q;
+      const int c = L * m + o;
       C *a = c < ext ? row + c * LD : dslot;
       *a = v[m];
     }
   }
   __syncthreads();
-  for (int j = tid; j < 4 * np * ext; j += NT) {
-    C *col = T + (j >> 2) * LD;
-    const C *in = col + Q * bq;
+  for (int j = tid; j < L * np * ext; j += NT) {
+    C *col = T + (j / L) * LD;
+    const C *in = col + Q * bo;
     C v[Q];
 #pragma unroll
     for (int x = 0; x < Q; ++x) v[x] = in[x];
-    regfft::quad_fwd<C, N>(v, tw, ql);
+    ln.fwd(v, tw);
 #pragma unroll
-    for (int m = 0; m < Q; ++m) col[4 * m + q] = v[m];
+    for (int m = 0; m < Q; ++m) col[L * m + o] = v[m];
   }
   __syncthreads();
   for (int p = 0; p < np; ++p) {
@@ -929,11 +949,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(
   }
 }
 
-// threads of the lane-quad plane workgroup.  Single precision: 512 (two
-// waves per SIMD); at N >= 120 that budget spills a few registers (to 120
-// bytes per lane at N = 160) and is still faster than one wave per SIMD
-// without spills (1.74 ms against 2.03 ms per 64-pair launch at 160^2).
+// threads of the lane-quad / lane-octet plane workgroup: 256 in FP64, 512 in
+// single precision (two waves per SIMD)
 constexpr int quad_plane_threads(bool fp64, int n) { return fp64 ? kRT : 512; }
+// lanes per line: octets for the single-precision boxes of >= 120 points
+constexpr int plane_lanes(bool fp64, int n) { return !fp64 && n >= 120 ? 8 : 4; }
 
 // Box sizes with a compiled lane-quad kernel (double precision).
 #define QEH_QUAD_SIZES(X) X(16) X(20) X(24) X(32) X(36) X(40) X(48) X(60) X(64) X(72)
@@ -1363,11 +1383,12 @@ hipError_t k3_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi
 template <typename C, int N> hipError_t k2_quad_launch(const qeh_ctx *c, int nbk) {
   using R = typename real_of<C>::type;
   constexpr int NT = quad_plane_threads(sizeof(R) == 8, N);
+  constexpr int L = plane_lanes(sizeof(R) == 8, N);
   const int pb = c->pg.pb;
   const int ngrp = (nbk + pb - 1) / pb;
   const int per_xcd = (ngrp * c->n3 + 7) / 8;
-  allow_lds(k2_plane_quad<C, N, NT>, c->pg.lds_pair);
-  hipLaunchKernelGGL((k2_plane_quad<C, N, NT>), dim3(8 * per_xcd), dim3(NT), c->pg.lds_pair,
+  allow_lds(k2_plane_lanes<C, N, NT, L>, c->pg.lds_pair);
+  hipLaunchKernelGGL((k2_plane_lanes<C, N, NT, L>), dim3(8 * per_xcd), dim3(NT), c->pg.lds_pair,
                      c->stream, reinterpret_cast<C *>(c->d.sbuf),
                      reinterpret_cast<const R *>(c->d.vs), c->d.tidx,
                      reinterpret_cast<const C *>(c->d.tw) + c->tw_off[0], c->nst, c->n3, c->ext,

@@ -245,5 +245,97 @@ __device__ __forceinline__ void quad_fwd(C *v, const C *tw,
   Fft<C, Q, false>::run(v);
 }
 
+// ---------------------------------------------------------------- lane octets
+// A line of N = 8Q points held by eight adjacent lanes (o = lane & 7), Q
+// points each: in-lane transforms of length Q, a per-lane twiddle W_N^{o k},
+// and the 8-point transform across the octet as three radix-2 stages: with
+// partners o ^ 4 (a DPP shift by four lanes inside the 16-lane row, up or down
+// by bit 2 of the lane), then o ^ 2 and o ^ 1 (quad permutations), and the
+// eighth- and quarter-turn twiddles between them.  With br3(o) the three-bit
+// reversal of o:
+//   oct_inv: lane o holds x[8n + o] (n < Q) -> X[k + Q br3(o)] (k < Q);
+//   oct_fwd: lane o holds f[x + Q br3(o)]    -> F[8m + o].
+// Single precision only; all eight lanes of an octet must be active together.
+
+constexpr int kDppShl4 = 0x104;   // lane i reads lane i + 4 (same row)
+constexpr int kDppShr4 = 0x114;   // lane i reads lane i - 4 (same row)
+
+__device__ __forceinline__ float lane_xor4(float v, bool hi) {
+  const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppShl4, 0xF,
+                                                              0xF, false));
+  const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kDppShr4, 0xF,
+                                                              0xF, false));
+  return hi ? dn : up;
+}
+
+// Per-lane constants of an octet: signs of the three radix-2 stages, the
+// eighth-turn w8^{o & 3} of the lanes o >= 4 (after the o ^ 4 stage) and the
+// quarter turn of the lanes o & 3 == 3 (after the o ^ 2 stage), as (cos, sin)
+// of the inverse direction (the forward uses the conjugates).
+struct OctLane {
+  float s1, s2, s4;
+  float ec, es;   // eighth turn: lanes o >= 4, angle 2 pi (o & 3) / 8; else (1, 0)
+  float qc, qs;   // quarter turn: lanes with o & 3 == 3, (0, 1); else (1, 0)
+  bool hi;        // bit 2 of the lane
+  __device__ explicit OctLane(int o)
+      : s1((o & 1) ? -1.f : 1.f), s2((o & 2) ? -1.f : 1.f), s4((o & 4) ? -1.f : 1.f),
+        ec(1.f), es(0.f), qc((o & 3) == 3 ? 0.f : 1.f), qs((o & 3) == 3 ? 1.f : 0.f),
+        hi((o & 4) != 0) {
+    if (o & 4) {
+      const int j = o & 3;   // cos / sin of 2 pi j / 8
+      const float r = 0.70710678118654752440f;
+      ec = j == 0 ? 1.f : j == 1 ? r : j == 2 ? 0.f : -r;
+      es = j == 0 ? 0.f : j == 1 ? r : j == 2 ? 1.f : r;
+    }
+  }
+};
+
+// radix-2 across lanes o and o ^ 4: partner + sign * own
+template <int Q> __device__ __forceinline__ void oct_bfly4(float2 *v, const OctLane &ol) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const float2 a = v[k];
+    v[k].x = lane_xor4(a.x, ol.hi) + ol.s4 * a.x;
+    v[k].y = lane_xor4(a.y, ol.hi) + ol.s4 * a.y;
+  }
+}
+
+// times (c + i s) for the inverse, (c - i s) for the forward
+template <int Q, bool INV>
+__device__ __forceinline__ void oct_rotate(float2 *v, float c, float s0) {
+  const float s = INV ? s0 : -s0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const float2 a = v[k];
+    v[k].x = c * a.x - s * a.y;
+    v[k].y = s * a.x + c * a.y;
+  }
+}
+
+// tw: this lane's table row, tw[k] = W_N^{o k} for k < Q (W_N = exp(-2 pi i / N))
+template <int N>
+__device__ __forceinline__ void oct_inv(float2 *v, const float2 *tw, const OctLane &ol) {
+  constexpr int Q = N / 8;
+  Fft<float2, Q, true>::run(v);
+  quad_twiddle<float2, Q, true>(v, tw);
+  oct_bfly4<Q>(v, ol);
+  oct_rotate<Q, true>(v, ol.ec, ol.es);
+  quad_bfly<float2, Q, kDppXor2>(v, ol.s2);
+  oct_rotate<Q, true>(v, ol.qc, ol.qs);
+  quad_bfly<float2, Q, kDppXor1>(v, ol.s1);
+}
+
+template <int N>
+__device__ __forceinline__ void oct_fwd(float2 *v, const float2 *tw, const OctLane &ol) {
+  constexpr int Q = N / 8;
+  quad_bfly<float2, Q, kDppXor1>(v, ol.s1);
+  oct_rotate<Q, false>(v, ol.qc, ol.qs);
+  quad_bfly<float2, Q, kDppXor2>(v, ol.s2);
+  oct_rotate<Q, false>(v, ol.ec, ol.es);
+  oct_bfly4<Q>(v, ol);
+  quad_twiddle<float2, Q, false>(v, tw);
+  Fft<float2, Q, false>::run(v);
+}
+
 }  // namespace regfft
 }  // namespace qeh
