@@ -791,7 +791,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     const int np = (nbk + 1) / 2;
     {
       StageGuard g(c, 0);
-      e = launch_k1_gamma(c, nbk, psi, ldpsi);
+      e = launch_k1_gamma(c, nbk, psi, ldpsi, nullptr, 0, /*copy32=*/true);
     }
     if (e != hipSuccess) return hip_fail(e, "K1 launch");
     {
@@ -826,8 +826,8 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
   }
   if ((part == 1 || part == 2) && c->nkb > 0) {
     GemmDesc g1{};
-    // K1 has just written psi32 (not for Gamma: there it holds packed band pairs)
-    const bool use32 = !f64 && part == 2 && !c->gamma;
+    // K1 has just written psi32 (the single-precision copy of the block)
+    const bool use32 = !f64 && part == 2;
     g1.A = use32 ? static_cast<const void *>(c->d.psi32) : static_cast<const void *>(psi);
     g1.lda = use32 ? c->npw_fft : ldpsi;
     g1.ta = use32 ? T_F2 : T_D2;

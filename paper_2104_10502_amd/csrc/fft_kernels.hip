@@ -152,6 +152,31 @@ __device__ __forceinline__ double2 gamma_pair(const double2 *__restrict__ psi, i
   return make_double2(va.x - vb.y, va.y + vb.x);
 }
 
+// Single-precision copy of the two bands of Gamma pair p for the projector
+// GEMM: the stored coefficients h = f - (nh - 1) of the +G half of the sphere
+// indices f in [g0, g1), so each is written once.  psi32 rows have length npw.
+__device__ __forceinline__ void gamma_pair_copy32(const double2 *__restrict__ psi, int ldpsi,
+                                                  int p, int g0, int g1, int nh, int nbk,
+                                                  const int2 *__restrict__ pairs,
+                                                  float2 *__restrict__ psi32, int npw, int tid,
+                                                  int nt) {
+  int ia = 2 * p, ib = 2 * p + 1 < nbk ? 2 * p + 1 : -1;
+  if (pairs) {
+    const int2 t = pairs[p];
+    ia = t.x;
+    ib = t.y;
+  }
+  for (int g = max(g0, nh - 1) + tid; g < g1; g += nt) {
+    const int h = g - (nh - 1);
+    const double2 va = psi[(size_t)ia * ldpsi + h];
+    psi32[(size_t)ia * npw + h] = make_float2((float)va.x, (float)va.y);
+    if (ib >= 0) {
+      const double2 vb = psi[(size_t)ib * ldpsi + h];
+      psi32[(size_t)ib * npw + h] = make_float2((float)vb.x, (float)vb.y);
+    }
+  }
+}
+
 // One workgroup: S consecutive sticks of one band.  Their sphere runs are one
 // contiguous range of psi (lexicographic Miller order), so the read is
 // coalesced; the output rows [z][s0 .. s0+S) are contiguous too.  GAM: the
@@ -178,10 +203,13 @@ __global__ __launch_bounds__(kNT) void k1_scatter_zinv(
   const int g0 = stick_off[s0], g1 = stick_off[s0 + ns];
   const double2 *pb = psi + (size_t)b * ldpsi;
   const int base = s0 * ldz;
-  // mixed form: also leave a single-precision copy of psi for the projector GEMM
+  // mixed form: also leave a single-precision copy of psi for the projector
+  // GEMM (on Gamma contexts each stored coefficient of the pair's two bands,
+  // written from the +G half of the full sphere, so once)
   if (GAM) {
     for (int g = g0 + tid; g < g1; g += kNT)
       tile[gmap[g] - base] = ccast<C>(gamma_pair(psi, ldpsi, b, g, nh, nbk, pairs));
+    if (psi32) gamma_pair_copy32(psi, ldpsi, b, g0, g1, nh, nbk, pairs, psi32, npw, tid, kNT);
   } else if (psi32) {
     float2 *p32 = psi32 + (size_t)b * npw;
     for (int g = g0 + tid; g < g1; g += kNT) {
@@ -1006,6 +1034,7 @@ k1_pair(const double2 *__restrict__ psi, int ldpsi, float2 *__restrict__ sbuf,
     tile[gmap[g] - base] = f;
     if (!GAM) psi32[(size_t)b * npw + g] = f;
   }
+  if (GAM && psi32) gamma_pair_copy32(psi, ldpsi, b, g0, g1, nh, nbk, pairs, psi32, npw, tid, kNT);
   __syncthreads();
   float2 *out = sbuf + (size_t)b * N * nst + s0;
   for (int j = tid; j < 2 * ns; j += kNT) {
@@ -1173,15 +1202,14 @@ template <typename K> void allow_lds(K kern, size_t bytes) {
 // the pairs of a table.
 template <typename C, bool GAM>
 hipError_t k1_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
-                   const int2 *pairs) {
+                   const int2 *pairs, float2 *p32) {
   const C *tw = reinterpret_cast<const C *>(c->d.tw) + c->tw_off[2];
   dim3 grid((c->nst + c->sg.S - 1) / c->sg.S, nbk);
   allow_lds(k1_scatter_zinv<C, GAM>, c->sg.lds_bytes);
   hipLaunchKernelGGL((k1_scatter_zinv<C, GAM>), grid, dim3(kNT), c->sg.lds_bytes, c->stream,
                      psi, ldpsi, reinterpret_cast<C *>(c->d.sbuf), c->d.stick_off, c->d.gmap, tw,
                      c->dz, c->nst, c->sg.S, c->sg.ldz, c->sg.s_div, c->sg.slast_div,
-                     (c->prec == QEH_MIXED && !GAM) ? c->d.psi32 : nullptr, c->npw_fft, nb_gam,
-                     c->npw, pairs);
+                     p32, c->npw_fft, nb_gam, c->npw, pairs);
   return hipGetLastError();
 }
 
@@ -1336,13 +1364,13 @@ hipError_t density_rows_impl(const qeh_ctx *c, const DensityGeom &dg, int nbk, c
 
 template <int N, bool GAM>
 hipError_t k1_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
-                          const int2 *pairs) {
+                          const int2 *pairs, float2 *p32) {
   const size_t lds = 8 * (size_t)kPairSticks * (N | 1);
   allow_lds(k1_pair<N, GAM>, lds);
   hipLaunchKernelGGL((k1_pair<N, GAM>), dim3((c->nst + kPairSticks - 1) / kPairSticks, nbk),
                      dim3(kNT), lds, c->stream, psi, ldpsi, reinterpret_cast<float2 *>(c->d.sbuf),
-                     c->d.stick_off, c->d.gmap, c->nst, GAM ? nullptr : c->d.psi32, c->npw_fft,
-                     nb_gam, c->npw, pairs);
+                     c->d.stick_off, c->d.gmap, c->nst, p32, c->npw_fft, nb_gam, c->npw,
+                     pairs);
   return hipGetLastError();
 }
 
@@ -1359,10 +1387,10 @@ hipError_t k3_pair_launch(const qeh_ctx *c, int nbk, const double2 *psi, int ldp
 
 template <bool GAM>
 hipError_t k1_pair_impl(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi, int nb_gam,
-                        const int2 *pairs) {
+                        const int2 *pairs, float2 *p32) {
   switch (c->n3) {
 #define QEH_PAIR_CASE(NN) \
-  case NN: return k1_pair_launch<NN, GAM>(c, nbk, psi, ldpsi, nb_gam, pairs);
+  case NN: return k1_pair_launch<NN, GAM>(c, nbk, psi, ldpsi, nb_gam, pairs, p32);
     QEH_PAIR_SIZES(QEH_PAIR_CASE)
 #undef QEH_PAIR_CASE
     default: return hipErrorInvalidValue;
@@ -1549,17 +1577,23 @@ size_t stick_lds_bytes(int prec, int n3, const StickGeom &g) {
 }
 
 hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi) {
-  if (c->zpair) return k1_pair_impl<false>(c, nbk, psi, ldpsi, 0, nullptr);
-  return c->prec == QEH_FP64 ? k1_impl<double2, false>(c, nbk, psi, ldpsi, 0, nullptr)
-                             : k1_impl<float2, false>(c, nbk, psi, ldpsi, 0, nullptr);
+  // mixed form: K1 also leaves the single-precision copy of the block for the
+  // projector GEMM
+  float2 *p32 = c->prec == QEH_MIXED ? c->d.psi32 : nullptr;
+  if (c->zpair) return k1_pair_impl<false>(c, nbk, psi, ldpsi, 0, nullptr, p32);
+  return c->prec == QEH_FP64 ? k1_impl<double2, false>(c, nbk, psi, ldpsi, 0, nullptr, p32)
+                             : k1_impl<float2, false>(c, nbk, psi, ldpsi, 0, nullptr, p32);
 }
 
 hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
-                           const int2 *pairs, int npairs) {
+                           const int2 *pairs, int npairs, bool copy32) {
   const int np = pairs ? npairs : (nbk + 1) / 2;
-  if (c->zpair) return k1_pair_impl<true>(c, np, psi, ldpsi, nbk, pairs);
-  return c->prec == QEH_FP64 ? k1_impl<double2, true>(c, np, psi, ldpsi, nbk, pairs)
-                             : k1_impl<float2, true>(c, np, psi, ldpsi, nbk, pairs);
+  // the single-precision copy only for a block of <= block bands in natural
+  // pairs (its rows are the bands' indices)
+  float2 *p32 = copy32 && !pairs && nbk <= c->block && c->prec == QEH_MIXED ? c->d.psi32 : nullptr;
+  if (c->zpair) return k1_pair_impl<true>(c, np, psi, ldpsi, nbk, pairs, p32);
+  return c->prec == QEH_FP64 ? k1_impl<double2, true>(c, np, psi, ldpsi, nbk, pairs, p32)
+                             : k1_impl<float2, true>(c, np, psi, ldpsi, nbk, pairs, p32);
 }
 
 hipError_t launch_k2(const qeh_ctx *c, int nbk) {

@@ -411,8 +411,9 @@ __global__ __launch_bounds__(256) void dscale_kernel(
 
 }  // namespace
 
-// The Gamma-point forms: RM = 1 for beta^H psi (bmode 0, psi read in
-// double), RM = 2 for beta ps (bmode 1, A = ps real, C = hpsi).  FP32 wide
+// The Gamma-point forms: RM = 1 for beta^H psi (bmode 0, psi read in double,
+// or its single-precision copy), RM = 2 for beta ps (bmode 1, A = ps real,
+// C = hpsi).  FP32 wide
 // tiles (tile 1): 128 x 256 for beta^H psi (psi re-read once per 256
 // projectors), 128 x 128 for beta ps.
 hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
@@ -429,6 +430,10 @@ hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
     return g.tile == 1
                ? run_tile<float, double2, float2, float2, 0, 128, 256, 16, 1, 2, 4, 32>(g, s)
                : run_tile<float, double2, float2, float2, 0, 64, 64, 16, 1>(g, s);
+  if (g.rmode == 1 && g.bmode == 0 && g.ta == T_F2 && g.tc == T_F2)
+    return g.tile == 1
+               ? run_tile<float, float2, float2, float2, 0, 128, 256, 16, 1, 2, 4, 32>(g, s)
+               : run_tile<float, float2, float2, float2, 0, 64, 64, 16, 1>(g, s);
   if (g.rmode == 2 && g.bmode == 1 && g.ta == T_F2 && g.tc == T_D2)
     return g.tile == 1
                ? run_tile<float, float2, float2, double2, 1, 128, 128, 16, 2, 2, 4, 32>(g, s)

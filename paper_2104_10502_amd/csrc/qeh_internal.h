@@ -141,9 +141,10 @@ hipError_t launch_k1(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi);
 // Gamma contexts: K1 of ceil(nbk/2) band pairs psi_2p + i psi_2p+1, read from
 // the half-sphere bands (nbk rows, ldpsi) and expanded to the full sphere; with
 // a device pair table, K1 of npairs pairs (rows pairs[p].x, pairs[p].y, the
-// second < 0 for none).
+// second < 0 for none).  copy32 (mixed form, natural pairs of a block of
+// <= block bands): K1 also writes the block's single-precision copy psi32.
 hipError_t launch_k1_gamma(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
-                           const int2 *pairs = nullptr, int npairs = 0);
+                           const int2 *pairs = nullptr, int npairs = 0, bool copy32 = false);
 hipError_t launch_k2(const qeh_ctx *c, int nbk);
 hipError_t launch_k3(const qeh_ctx *c, int nbk, const double2 *psi, int ldpsi,
                      double2 *hpsi, int ldh, int add_kinetic);
