@@ -861,7 +861,7 @@ qeh_status apply_block(qeh_ctx *c, int part, int nbk, const double2 *psi, int ld
     GemmDesc g3{};
     g3.A = c->d.ps;
     g3.lda = c->nkb;
-    g3.ta = f64 ? T_D2 : T_F2;
+    g3.ta = f64 ? T_D2 : c->gamma ? T_F1 : T_F2;   // single-precision Gamma: real ps
     g3.B = c->d.beta;
     g3.ldb = c->npw;
     g3.tb = f64 ? T_D2 : T_F2;
@@ -959,7 +959,7 @@ qeh_status apply_s_impl(qeh_ctx *c, int nb, const double *psi, int ldpsi, double
     GemmDesc g3{};
     g3.A = c->d.ps;
     g3.lda = c->nkb;
-    g3.ta = f64 ? T_D2 : T_F2;
+    g3.ta = f64 ? T_D2 : c->gamma ? T_F1 : T_F2;   // single-precision Gamma: real ps
     g3.B = c->d.beta;
     g3.ldb = c->npw;
     g3.tb = f64 ? T_D2 : T_F2;

@@ -73,6 +73,17 @@ template <typename T> __device__ __forceinline__ T zero_of() {
   z.y = 0;
   return z;
 }
+template <> __device__ __forceinline__ float zero_of<float>() { return 0.f; }
+
+// real and imaginary parts of an operand element (a real element: imaginary 0)
+template <typename R, typename T> __device__ __forceinline__ R re_of(const T &v) {
+  return static_cast<R>(v.x);
+}
+template <typename R, typename T> __device__ __forceinline__ R im_of(const T &v) {
+  return static_cast<R>(v.y);
+}
+template <> __device__ __forceinline__ float re_of<float, float>(const float &v) { return v; }
+template <> __device__ __forceinline__ float im_of<float, float>(const float &v) { return 0.f; }
 
 // One workgroup: a BM x BN tile of C over the K slice [kbeg, kend).  Global
 // tiles are prefetched into registers while the MFMAs consume the LDS copy of
@@ -163,8 +174,8 @@ void cgemm_kernel(
     for (int u = 0; u < NA; ++u) {
       const int e = tid + u * kGT;
       const int r = e / BK, k = e % BK;
-      As[buf][0][r * BKP + k] = static_cast<R>(ra[u].x);
-      As[buf][1][r * BKP + k] = sa * static_cast<R>(ra[u].y);
+      As[buf][0][r * BKP + k] = re_of<R>(ra[u]);
+      As[buf][1][r * BKP + k] = sa * im_of<R>(ra[u]);
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
@@ -351,6 +362,17 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP *__restrict
 // Gamma contexts (gpsi set): the partials sum conj(beta) psi over the stored
 // half sphere, and the full-sphere projection is real:
 //   becp = 2 Re(sum) - beta(0) psi(0)   (G = 0 counted once; beta(0) real).
+__device__ __forceinline__ void store_ps(double2 *ps, long i, double sr, double si) {
+  ps[i] = make_double2(sr, si);
+}
+__device__ __forceinline__ void store_ps(float2 *ps, long i, double sr, double si) {
+  ps[i] = make_float2((float)sr, (float)si);
+}
+// Gamma, single precision: ps is real, stored as one float per entry
+__device__ __forceinline__ void store_ps(float *ps, long i, double sr, double) {
+  ps[i] = (float)sr;
+}
+
 template <typename TP, typename TS>
 __global__ __launch_bounds__(256) void dscale_kernel(
     const TP *__restrict__ part, long split_stride, int nsplit, int nkb, TS *__restrict__ ps,
@@ -402,18 +424,15 @@ __global__ __launch_bounds__(256) void dscale_kernel(
       sr += d.x * v.x - d.y * v.y;
       si += d.x * v.y + d.y * v.x;
     }
-    TS o;
-    o.x = static_cast<typename real_of<TS>::type>(sr);
-    o.y = static_cast<typename real_of<TS>::type>(si);
-    ps[(long)b * nkb + j] = o;
+    store_ps(ps, (long)b * nkb + j, sr, si);
   }
 }
 
 }  // namespace
 
 // The Gamma-point forms: RM = 1 for beta^H psi (bmode 0, psi read in double,
-// or its single-precision copy), RM = 2 for beta ps (bmode 1, A = ps real,
-// C = hpsi).  FP32 wide
+// or its single-precision copy), RM = 2 for beta ps (bmode 1, A = ps real:
+// complex storage in FP64, one float per entry in single precision; C = hpsi).  FP32 wide
 // tiles (tile 1): 128 x 256 for beta^H psi (psi re-read once per 256
 // projectors), 128 x 128 for beta ps.
 hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
@@ -438,6 +457,10 @@ hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
     return g.tile == 1
                ? run_tile<float, float2, float2, double2, 1, 128, 128, 16, 2, 2, 4, 32>(g, s)
                : run_tile<float, float2, float2, double2, 1, 64, 64, 16, 2>(g, s);
+  if (g.rmode == 2 && g.bmode == 1 && g.ta == T_F1 && g.tc == T_D2)
+    return g.tile == 1
+               ? run_tile<float, float, float2, double2, 1, 128, 128, 16, 2, 2, 4, 32>(g, s)
+               : run_tile<float, float, float2, double2, 1, 64, 64, 16, 2>(g, s);
   return hipErrorInvalidValue;
 }
 
@@ -482,6 +505,13 @@ hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldp
                        reinterpret_cast<double2 *>(c->d.ps), mat, c->d.pj0, c->d.pnb,
                        c->d.pdoff, c->d.chunk, gpsi, ldpsi,
                        reinterpret_cast<const double2 *>(c->d.beta), (long)c->npw);
+  } else if (c->gamma) {
+    // real ps, one float per entry: half the A operand of the beta ps product
+    hipLaunchKernelGGL((dscale_kernel<float2, float>), grid, dim3(256), 0, c->stream,
+                       reinterpret_cast<const float2 *>(c->d.part), ss, c->nsplit, c->nkb,
+                       reinterpret_cast<float *>(c->d.ps), mat, c->d.pj0, c->d.pnb,
+                       c->d.pdoff, c->d.chunk, gpsi, ldpsi,
+                       reinterpret_cast<const float2 *>(c->d.beta), (long)c->npw);
   } else {
     hipLaunchKernelGGL((dscale_kernel<float2, float2>), grid, dim3(256), 0, c->stream,
                        reinterpret_cast<const float2 *>(c->d.part), ss, c->nsplit, c->nkb,

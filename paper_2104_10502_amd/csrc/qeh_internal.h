@@ -89,7 +89,8 @@ struct DevMaps {
   int *chunk;        // [nchunk+1] atom-aligned projector ranges (<= 256 each)
   void *sbuf;        // [block][N3][nst] stick buffer (working complex type)
   void *part;        // [nsplit][block][nkb] split-K partials
-  void *ps;          // [block][nkb] D * becp (working complex type)
+  void *ps;          // [block][nkb] D * becp (working complex type; real floats on
+                     // single-precision Gamma contexts)
   float2 *psi32;     // mixed form: [block][npw] single-precision copy of psi (K1)
   void *big;         // split plane path: [block][N3][ext][N2] (or null)
   double2 *gbuf;     // Gamma: [(block+1)/2][npw_fft] full-sphere H of band pairs (or null)
@@ -219,7 +220,7 @@ hipError_t beta_static_scratch(hipStream_t s, char **out);
 //   Split-K: grid z = nsplit slices of kchunk; slice s writes
 //      C + s*split_stride (accumulate must be 0 then).
 enum GemmPrec { G_F64 = 0, G_F32 = 1 };
-enum GemmType { T_D2 = 0, T_F2 = 1 };   // storage type of an operand
+enum GemmType { T_D2 = 0, T_F2 = 1, T_F1 = 2 };   // operand storage (T_F1: real float)
 struct GemmDesc {
   const void *A; long lda; int ta;
   const void *B; long ldb; int tb; int bmode;
