@@ -625,8 +625,9 @@ def main():
         env = dict(os.environ)
         # one hardware queue per job stream (up to 32 slots), so that jobs'
         # one-workgroup subspace solves run side by side instead of queueing
-        # behind each other (HIP reads this at initialisation; <= 32)
-        env.setdefault("GPU_MAX_HW_QUEUES", "32")
+        # behind each other (HIP reads this at initialisation; its default is
+        # 4, and values above 32 are not used here)
+        env["GPU_MAX_HW_QUEUES"] = str(max(4, min(32, a.serve_slots)))
         child = subprocess.Popen(
             [sys.executable, os.path.abspath(__file__), "--serve-child", "--serve", str(a.serve),
              "--serve-rate", str(a.serve_rate), "--serve-slots", str(a.serve_slots)] +
