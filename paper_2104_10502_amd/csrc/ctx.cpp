@@ -396,20 +396,21 @@ void geometry(const qeh_cell *c, const HostMaps &hm, Geometry *g) {
   }
   // split-K of beta^H psi: fixed chunks of >= 256 plane waves, enough
   // workgroups to fill the chip.  Single precision with >= 2048 projectors
-  // and blocks of >= 128 bands takes the wide FP32 tiles (128 bands x 128 or,
-  // on Gamma cells, 256 projectors; eight waves, one workgroup per CU): at
-  // most two rounds of 256 workgroups (the chip's CU count), since a third,
-  // nearly empty round costs as much as a full one; otherwise 64 x 64 tiles
-  // (~4 workgroups per CU; measured faster than 128 x 64 at 128 bands and
-  // 512 projectors).
+  // and blocks of >= 128 bands takes the wide FP32 tiles (128 bands x 128
+  // projectors, eight waves): at most two rounds of the workgroups resident
+  // at once (256 CUs; one workgroup per CU, two for the Gamma product held to
+  // 128 registers), since a third, nearly empty round costs as much as a full
+  // one; otherwise 64 x 64 tiles (~4 workgroups per CU; measured faster than
+  // 128 x 64 at 128 bands and 512 projectors).
   g->nsplit = 1;
   g->kchunk = c->npw;
   g->wide = c->precision == QEH_MIXED && c->block >= 128 && g->nkb >= 2048 ? 1 : 0;
   if (g->nkb > 0) {
     const int bm = g->wide ? 128 : 64;
-    const int bn = g->wide ? (c->gamma ? 256 : 128) : 64;
+    const int bn = g->wide ? 128 : 64;
     const int tiles = ((c->block + bm - 1) / bm) * ((g->nkb + bn - 1) / bn);
-    int ns = g->wide ? std::max(1, 2 * 256 / tiles) : std::max(1, (1024 + tiles - 1) / tiles);
+    const int resident = c->gamma ? 2 * 256 : 256;
+    int ns = g->wide ? std::max(1, 2 * resident / tiles) : std::max(1, (1024 + tiles - 1) / tiles);
     ns = std::min(ns, std::max(1, c->npw / 256));
     int kc = (c->npw + ns - 1) / ns;
     kc = (kc + 15) / 16 * 16;

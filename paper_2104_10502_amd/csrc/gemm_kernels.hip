@@ -89,9 +89,9 @@ template <> __device__ __forceinline__ float im_of<float, float>(const float &v)
 // tiles are prefetched into registers while the MFMAs consume the LDS copy of
 // the previous slice (two LDS buffers, one barrier per slice).
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
-          int RM, int WGM, int WGN, int BS>
+          int RM, int WGM, int WGN, int BS, int WPE>
 __global__ __launch_bounds__(64 * WGM * WGN)
-__attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
+__attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : (sizeof(R) == 8 ? 3 : 1))))
 void cgemm_kernel(
     const TA *__restrict__ A, long lda, const TB *__restrict__ B, long ldb, TC *__restrict__ C,
     long ldc, int M, int N, int K, int conjA, int conjB, int accumulate, int kchunk,
@@ -285,14 +285,14 @@ void cgemm_kernel(
 }
 
 template <typename R, typename TA, typename TB, typename TC, int BMODE, int BM, int BN, int BK,
-          int RM = 0, int WGM = 2, int WGN = 2, int BS = 16>
+          int RM = 0, int WGM = 2, int WGN = 2, int BS = 16, int WPE = 0>
 hipError_t run_tile(const GemmDesc &g, hipStream_t s) {
   const int tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
   const long total = (long)tm * tn * g.nsplit;
   if (total > (1L << 30)) return hipErrorInvalidValue;
   const int per_xcd = (int)((total + 7) / 8);
   const int kchunk = g.nsplit > 1 ? g.kchunk : g.K;
-  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK, RM, WGM, WGN, BS>),
+  hipLaunchKernelGGL((cgemm_kernel<R, TA, TB, TC, BMODE, BM, BN, BK, RM, WGM, WGN, BS, WPE>),
                      dim3(8 * per_xcd), dim3(64 * WGM * WGN), 0, s, reinterpret_cast<const TA *>(g.A), g.lda,
                      reinterpret_cast<const TB *>(g.B), g.ldb, reinterpret_cast<TC *>(g.C), g.ldc,
                      g.M, g.N, g.K, g.conjA, g.conjB, g.accumulate, kchunk, g.split_stride, tm, tn,
@@ -432,9 +432,12 @@ __global__ __launch_bounds__(256) void dscale_kernel(
 
 // The Gamma-point forms: RM = 1 for beta^H psi (bmode 0, psi read in double,
 // or its single-precision copy), RM = 2 for beta ps (bmode 1, A = ps real:
-// complex storage in FP64, one float per entry in single precision; C = hpsi).  FP32 wide
-// tiles (tile 1): 128 x 256 for beta^H psi (psi re-read once per 256
-// projectors), 128 x 128 for beta ps.
+// complex storage in FP64, one float per entry in single precision;
+// C = hpsi).  FP32 wide tiles (tile 1): beta^H psi from the single-precision
+// copy on 128 x 128 held to 128 registers (four waves per SIMD, two
+// workgroups per CU: 2.54 against 2.72 ms for 128 x 256 at the 512-atom
+// cell), from psi in double on 128 x 256 (psi re-read once per 256
+// projectors); beta ps on 128 x 128.
 hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
   if (g.prec == G_F64) {
     if (g.ta != T_D2 || g.tb != T_D2 || g.tc != T_D2) return hipErrorInvalidValue;
@@ -451,7 +454,7 @@ hipError_t launch_cgemm_real(const GemmDesc &g, hipStream_t s) {
                : run_tile<float, double2, float2, float2, 0, 64, 64, 16, 1>(g, s);
   if (g.rmode == 1 && g.bmode == 0 && g.ta == T_F2 && g.tc == T_F2)
     return g.tile == 1
-               ? run_tile<float, float2, float2, float2, 0, 128, 256, 16, 1, 2, 4, 32>(g, s)
+               ? run_tile<float, float2, float2, float2, 0, 128, 128, 16, 1, 2, 4, 32, 4>(g, s)
                : run_tile<float, float2, float2, float2, 0, 64, 64, 16, 1>(g, s);
   if (g.rmode == 2 && g.bmode == 1 && g.ta == T_F2 && g.tc == T_D2)
     return g.tile == 1
