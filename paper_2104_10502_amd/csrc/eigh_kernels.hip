@@ -1,18 +1,21 @@
 // Dense Hermitian solver of the Davidson Rayleigh-Ritz step, written for the
 // small reduced problems of block Davidson (n <= 512): the paper solves this
-// "relatively small" generalized eigenproblem with a dense GPU solver (section
-// "Evolution of the GPU-enabled version").  H y = eps S y for the lowest nb
-// pairs, in five deterministic kernels (fixed summation orders, no atomics on
-// floating-point data), each problem a handful of launches instead of the
-// hundreds of a library eigensolver:
+// small generalized eigenproblem with a dense GPU solver (section "Evolution
+// of the GPU-enabled version").  H y = eps S y for the lowest nb
+// pairs, in six deterministic kernels (fixed summation orders, no atomics on
+// floating-point data):
 //
 //   chol_kernel     one workgroup: S = L L^H, right-looking, lower triangle
 //   trsm_kernel     one wave per column, many workgroups: L X = B (forward),
 //                   with B given or as the adjoint of a matrix, or L^H X = B
 //                   (backward with the explicit L^H); A = L^-1 H L^-H by two
 //                   of them, Y = L^-H Z by a third
-//   tridiag_kernel  one workgroup: Householder reduction A = Q T Q^H, T real
-//                   symmetric tridiagonal (d, e), reflectors kept in A
+//   tdstep_kernel   one launch per Householder step while the trailing block
+//                   is larger than kTailN, one wave per column, many
+//                   workgroups
+//   tridiag_kernel  one workgroup: the remaining steps of the Householder
+//                   reduction A = Q T Q^H, T real symmetric tridiagonal (d, e),
+//                   reflectors kept in A
 //   trieig_kernel   one workgroup: the nb lowest eigenpairs of T.  T is split
 //                   where |e_k| <= eps ||T||; the global nb-th eigenvalue is
 //                   bracketed by multisection of Sturm counts; every block's
@@ -56,14 +59,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __shfl(v, 0);
 }
 
-// Sum over the workgroup, identical in every thread and from run to run.
-__device__ double block_sum(double v, double *red) {
+// Sum over the workgroup (NW waves), identical in every thread and from run
+// to run.
+template <int NW = kEW> __device__ double block_sum(double v, double *red) {
   v = wave_sum(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   double s = 0.0;
-  for (int i = 0; i < kEW; ++i) s += red[i];
+  for (int i = 0; i < NW; ++i) s += red[i];
   return s;
 }
 
@@ -231,16 +235,18 @@ __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T
 // Threads cover rows i (fastest, coalesced) x column groups; eight columns'
 // loads are in flight per thread.
 // Householder vector of the column col[0..m) (col[0] the subdiagonal entry):
-// tau, beta, and v written to col (v[0] = 1) and to vs.  Uniform in all threads.
+// tau, beta, and v written to col (v[0] = 1) and to vs.  Uniform in all NT
+// threads of the workgroup.
+template <int NT = kET>
 __device__ void householder(double2 *col, int m, double2 *vs, double *red, double2 *t_out,
                             double *beta_out) {
   const int tid = threadIdx.x;
   double s = 0.0;
-  for (int i = 1 + tid; i < m; i += kET) {
+  for (int i = 1 + tid; i < m; i += NT) {
     const double2 v = col[i];
     s += v.x * v.x + v.y * v.y;
   }
-  const double xn2 = block_sum(s, red);
+  const double xn2 = block_sum<NT / 64>(s, red);
   const double2 alpha = col[0];
   double beta;
   double2 t = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
@@ -254,7 +260,7 @@ __device__ void householder(double2 *col, int m, double2 *vs, double *red, doubl
     scale = make_double2(ab.x / den, -ab.y / den);   // 1 / (alpha - beta)
   }
   const bool refl = t.x != 0.0 || t.y != 0.0;
-  for (int i = tid; i < m; i += kET) {
+  for (int i = tid; i < m; i += NT) {
     const double2 v = i == 0 ? make_double2(1.0, 0.0) : (refl ? cmul(col[i], scale) : col[i]);
     vs[i] = v;
     col[i] = v;
@@ -305,15 +311,14 @@ __device__ void fused_pass(double2 *U, long lda, int m, bool upd, const double2 
   if (mv) part[grp * mm + r] = acc;
 }
 
-__global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int n, double *tri,
+__global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int n, double *d,
+                                                      double *e, double2 *tau,
                                                       const int *info_chol) {
   if (*info_chol != 0) return;
   __shared__ double2 vbuf[2][kEMaxN];   // v_k and v_{k+1}
   __shared__ double2 ps[kEMaxN];        // A22 v_k, then p, then w
   __shared__ double2 part[kET];
   __shared__ double red[kEW];
-  double *d = tri, *e = tri + n;
-  double2 *tau = reinterpret_cast<double2 *>(tri + 2 * n);
   const int tid = threadIdx.x;
   if (n == 1) {
     if (tid == 0) d[0] = A[0].x;
@@ -412,6 +417,137 @@ __global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int 
     __syncthreads();
     t = t1;
     cur ^= 1;
+  }
+}
+
+// Leading steps of the same reduction while the trailing block is large: one
+// launch per step over many workgroups, one wave per column of the trailing
+// block (kSW columns per workgroup); tridiag_kernel then reduces the last
+// kTailN rows and columns as a problem of its own (after k0 steps the rest of
+// the reduction is the reduction of the updated block A[k0:, k0:]).
+//
+// Launch k (k = -1 .. k0-1) applies step k's update A22 -= v w^H + w v^H
+// (A22 = rows / columns k+1..n-1) to the columns its waves own, and forms
+// step k+1's reflector v' (from column k+1) and product y' = A22' v' (A22' =
+// rows / columns k+2..) for the next launch.  w needs the whole y of step k,
+// and v' the updated column k+1: every workgroup forms both itself from the
+// small vectors of the previous launch (the same arithmetic in each, hence
+// the same values), so the launch boundary is the only synchronisation.  y'
+// uses the Hermitian symmetry, (A22' v')_j = sum_i conj(A(i, j)) v'_i, so
+// that a wave needs only its own column.  Launch -1 only forms v_0 and y_0.
+// Scratch (double2, double-buffered by parity so that a launch never writes
+// what it reads): vb[2][n] = v of a step, yb[2][n] = its y, cb[2][n] =
+// column c of A (rows c..n-1) as the launch before left it, for c = k+1.
+// Column k's reflector is written into A by the launch of step k, when no
+// wave reads that column any more.
+constexpr int kSW = 4;         // waves (columns) per workgroup of the step kernel
+constexpr int kTailN = 64;     // order left to the one-workgroup kernel
+
+__global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, int n, int k,
+                                                          int last, double *d, double *e,
+                                                          double2 *tau, double2 *scr,
+                                                          const int *info_chol) {
+  if (*info_chol != 0) return;
+  __shared__ double2 vs[kEMaxN];   // v of step k
+  __shared__ double2 ws[kEMaxN];   // y of step k, then w
+  __shared__ double2 cs[kEMaxN];   // column k+1 (rows k+1..), then v' in cs[1..]
+  __shared__ double red[kSW];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int r0 = k + 1;            // first row / column of A22
+  const int m = n - r0;            // its order
+  double2 *vb = scr, *yb = scr + 2 * (long)n, *cb = scr + 4 * (long)n;
+  const int col = blockIdx.x * kSW + (tid >> 6);   // this wave's column of A22
+  const bool own = col < m;
+  double2 *acol = A + (long)(r0 + col) * lda + r0;
+  // the owned column first: its loads overlap the small vectors'
+  double2 a[kSlots];
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int i = s * 64 + lane;
+    a[s] = own && i < m ? acol[i] : make_double2(0.0, 0.0);
+  }
+  const double2 t = k >= 0 ? tau[k] : make_double2(0.0, 0.0);
+  const bool refl = t.x != 0.0 || t.y != 0.0;
+  const double2 *csrc = k >= 0 ? cb + (long)(r0 & 1) * n : A;
+  for (int i = tid; i < m; i += 64 * kSW) {
+    if (k >= 0) {
+      vs[i] = vb[(long)(k & 1) * n + i];
+      ws[i] = yb[(long)(k & 1) * n + i];
+    }
+    cs[i] = csrc[i];
+  }
+  __syncthreads();
+  if (refl) {
+    // p = t y, alpha = -1/2 t (p^H v), w = p + alpha v
+    double dr = 0.0, di = 0.0;
+    for (int i = tid; i < m; i += 64 * kSW) {
+      const double2 p = cmul(t, ws[i]), v = vs[i];
+      dr += p.x * v.x + p.y * v.y;
+      di += p.x * v.y - p.y * v.x;
+    }
+    dr = block_sum<kSW>(dr, red);
+    di = block_sum<kSW>(di, red);
+    const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
+    for (int i = tid; i < m; i += 64 * kSW) ws[i] = cadd(cmul(t, ws[i]), cmul(a2, vs[i]));
+    __syncthreads();
+    const double2 v0 = vs[0], w0 = ws[0];
+    for (int i = tid; i < m; i += 64 * kSW)
+      cs[i] = csub(cs[i], cadd(cmulc(vs[i], w0), cmulc(ws[i], v0)));
+    __syncthreads();
+  }
+  double2 t1 = make_double2(0.0, 0.0);
+  double beta1 = 0.0;
+  if (!last) {
+    householder<64 * kSW>(cs + 1, m - 1, cs + 1, red, &t1, &beta1);
+    __syncthreads();
+  }
+  if (own) {
+    if (refl) {
+      const double2 vj = vs[col], wj = ws[col];
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int i = s * 64 + lane;
+        if (i < m) {
+          a[s] = csub(a[s], cadd(cmulc(vs[i], wj), cmulc(ws[i], vj)));
+          acol[i] = a[s];
+        }
+      }
+    }
+    if (!last && col >= 1) {
+      double dr = 0.0, di = 0.0;   // conj(column) . v'
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int i = s * 64 + lane;
+        if (i >= 1 && i < m) {
+          const double2 v = cs[i];
+          dr += a[s].x * v.x + a[s].y * v.y;
+          di += a[s].x * v.y - a[s].y * v.x;
+        }
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      if (lane == 0) yb[(long)(r0 & 1) * n + col - 1] = make_double2(dr, di);
+      if (col == 1) {
+        double2 *cn = cb + (long)((r0 + 1) & 1) * n;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+          const int i = s * 64 + lane;
+          if (i >= 1 && i < m) cn[i - 1] = a[s];
+        }
+      }
+    }
+  }
+  if (blockIdx.x == 0) {
+    if (k >= 0)
+      for (int i = tid; i < m; i += 64 * kSW) A[(long)k * lda + r0 + i] = vs[i];
+    if (!last) {
+      for (int i = tid; i + 1 < m; i += 64 * kSW) vb[(long)(r0 & 1) * n + i] = cs[1 + i];
+      if (tid == 0) {
+        d[r0] = cs[0].x;
+        e[r0] = beta1;
+        tau[r0] = t1;
+      }
+    }
   }
 }
 
@@ -855,10 +991,22 @@ hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double
   return hipGetLastError();
 }
 
-hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, const int *info_chol,
-                          hipStream_t s) {
+hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
+                          const int *info_chol, hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A, lda, n, tri, info_chol);
+  double *d = tri, *e = tri + n;
+  double2 *tau = reinterpret_cast<double2 *>(tri + 2 * n);
+  const int k0 = n > kTailN ? n - kTailN : 0;   // steps taken by the step kernel
+  if (k0 > 0) {
+    double2 *w = reinterpret_cast<double2 *>(scr);
+    for (int k = -1; k < k0; ++k) {
+      const int m = n - k - 1;
+      hipLaunchKernelGGL(tdstep_kernel, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s, A, lda,
+                         n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
+    }
+  }
+  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A + k0 + (long)k0 * lda, lda, n - k0,
+                     d + k0, e + k0, tau + k0, info_chol);
   return hipGetLastError();
 }
 

@@ -312,8 +312,10 @@ hipError_t launch_chol(double2 *S, long ld, int n, int *info, hipStream_t s);
 hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double2 *B, long ldb,
                        int ncol, double2 *X, long ldx, hipStream_t s);
 // A = Q T Q^H (Householder, in place); tri = d[n] | e[n] | tau (double2)[n].
-hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, const int *info_chol,
-                          hipStream_t s);
+// scr: 12 n doubles of scratch (the multi-workgroup steps' vectors); the
+// eigenpair scratch below is large enough and free at this point.
+hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
+                          const int *info_chol, hipStream_t s);
 // nb lowest eigenpairs of T: w[nb] ascending, Z (real, n x nb, ldz); scr holds
 // eig_scratch_doubles(n) doubles; info 0 / nonzero on failure.
 size_t eig_scratch_doubles(int n);
