@@ -481,7 +481,7 @@ void DavRun::rr_own() {
   const int n = nbase_, nb = nb_, ld = nvecx_;
   ok(launch_hermitise_copy(Hr_, ld, Hw_, ld, n, s));
   ok(launch_hermitise_copy(Sr_, ld, Sw_, ld, n, s));
-  ok(launch_chol(Sw_, ld, n, info_d_ + 1, s));
+  ok(launch_chol(Sw_, ld, n, info_d_ + 1, escr_, s));
   ok(launch_tril_adjoint(Sw_, Lc_, LcH_, ld, n, s));
   ok(launch_trsm(0, Lc_, ld, n, Hw_, ld, n, X_, ld, s));    // X = L^-1 Hr
   ok(launch_trsm(1, Lc_, ld, n, X_, ld, n, Sw_, ld, s));    // Sw = L^-1 X^H = A
@@ -1044,7 +1044,7 @@ qeh_status qeh_subspace_eigh(int n, int nb, const double *H, const double *S, in
   };
   run(launch_hermitise_copy(h, ld, M(L.Hw), n, n, s));
   run(launch_hermitise_copy(sm, ld, M(L.Sw), n, n, s));
-  run(launch_chol(M(L.Sw), n, n, info, s));
+  run(launch_chol(M(L.Sw), n, n, info, escr, s));
   run(launch_tril_adjoint(M(L.Sw), M(L.Lc), M(L.LcH), n, n, s));
   run(launch_trsm(0, M(L.Lc), n, n, M(L.Hw), n, n, M(L.X), n, s));
   run(launch_trsm(1, M(L.Lc), n, n, M(L.X), n, n, M(L.Sw), n, s));

@@ -152,6 +152,123 @@ __global__ __launch_bounds__(kET) void chol_kernel(double2 *S, long ld, int n, i
   if (tid == 0) *info = 0;
 }
 
+// Blocked form over many workgroups, one launch per panel of kCB columns.
+// Launch p (panel jb = p kCB): every workgroup factors the b x b diagonal
+// block L11 itself (the same data and arithmetic in each, hence the same
+// L11), forms the rows of L21 = A21 L11^-H that its kCT x kCT tile of the
+// trailing lower triangle needs, and subtracts L21 L21^H from that tile.  The
+// factored panel goes to a scratch panel (parity p & 1; L11 by tile (0, 0),
+// the rows of L21 by the diagonal tiles) and launch p + 1, which reads
+// neither, copies it into S: within a launch no workgroup writes what another
+// reads.  The last panel (no trailing block) writes its L11 to S itself.
+// Launch 0 sets info = 0; a panel that is not positive definite sets
+// jb + c + 1, and every later launch returns at once.
+constexpr int kCT = 32;   // trailing-update tile
+constexpr int kCholOneWG = 64;   // orders left to the one-workgroup kernel
+
+__global__ __launch_bounds__(256) void cholp_kernel(double2 *S, long ld, int n, int jb,
+                                                    double2 *scr, int *info) {
+  __shared__ double2 D[kCB * kCBP];          // diagonal block -> L11
+  __shared__ double2 Lr[2][kCT * kCBP];      // panel rows of the tile's rows / columns
+  const int tid = threadIdx.x;
+  if (jb > 0 && *info != 0) return;
+  if (jb == 0 && blockIdx.x == 0 && tid == 0) *info = 0;
+  const int b = min(kCB, n - jb), m = n - jb, mt = m - b;
+  const int pan = jb / kCB;
+  double2 *cur = scr + (long)(pan & 1) * n * kCB;
+  // the previous panel into S
+  if (jb > 0) {
+    const int jp = jb - kCB, mp = n - jp;
+    const double2 *prev = scr + (long)((pan - 1) & 1) * n * kCB;
+    for (int idx = blockIdx.x * 256 + tid; idx < mp * kCB; idx += gridDim.x * 256) {
+      const int r = idx % mp, c = idx / mp;
+      if (r >= c) S[(jp + r) + (long)(jp + c) * ld] = prev[r * kCB + c];
+    }
+  }
+  for (int idx = tid; idx < kCB * kCB; idx += 256) {
+    const int r = idx % kCB, c = idx / kCB;
+    D[r * kCBP + c] = (r < b && c < b && r >= c) ? S[(jb + r) + (long)(jb + c) * ld]
+                                                : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  for (int c = 0; c < b; ++c) {
+    const double ajj = D[c * kCBP + c].x;
+    if (!(ajj > 0.0) || !isfinite(ajj)) {   // same value in every workgroup
+      if (blockIdx.x == 0 && tid == 0) *info = jb + c + 1;
+      return;
+    }
+    const double ljj = sqrt(ajj), rinv = 1.0 / ljj;
+    __syncthreads();
+    if (tid >= c && tid < b)
+      D[tid * kCBP + c] = tid == c ? make_double2(ljj, 0.0) : cscale(D[tid * kCBP + c], rinv);
+    __syncthreads();
+    const int w = b - c - 1;
+    if (tid < b * w) {
+      const int r = tid % b, c2 = c + 1 + tid / b;
+      if (r >= c2) D[r * kCBP + c2] = csub(D[r * kCBP + c2], cmulc(D[r * kCBP + c], D[c2 * kCBP + c]));
+    }
+    __syncthreads();
+  }
+  if (mt == 0) {   // last panel
+    if (blockIdx.x == 0)
+      for (int idx = tid; idx < b * b; idx += 256) {
+        const int r = idx % b, c = idx / b;
+        if (r >= c) S[(jb + r) + (long)(jb + c) * ld] = D[r * kCBP + c];
+      }
+    return;
+  }
+  // this workgroup's tile (ti >= tj) of the trailing lower triangle
+  const int x = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > x) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+  const int tj = x - ti * (ti + 1) / 2;
+  const int r0[2] = {ti * kCT, tj * kCT};   // rows of the trailing block
+  // panel rows of the tile's rows and columns, then L21 = A21 L11^-H (one
+  // thread per row, forward in the column index)
+  for (int idx = tid; idx < 2 * kCT * kCB; idx += 256) {
+    const int h = idx / (kCT * kCB), e = idx % (kCT * kCB);
+    const int r = e % kCT, c = e / kCT;
+    const int gr = r0[h] + r;
+    Lr[h][r * kCBP + c] = (gr < mt && c < b) ? S[(jb + b + gr) + (long)(jb + c) * ld]
+                                             : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (tid < 2 * kCT) {
+    const int h = tid / kCT, r = tid % kCT;
+    double2 *row = &Lr[h][r * kCBP];
+    for (int c = 0; c < b; ++c) {
+      double2 a = row[c];
+      for (int c2 = 0; c2 < c; ++c2) a = csub(a, cmulc(row[c2], D[c * kCBP + c2]));
+      row[c] = cscale(a, 1.0 / D[c * kCBP + c].x);
+    }
+  }
+  __syncthreads();
+  // the factored panel to the scratch panel
+  if (ti == tj) {
+    for (int idx = tid; idx < kCT * kCB; idx += 256) {
+      const int r = idx % kCT, c = idx / kCT;
+      if (r0[0] + r < mt) cur[(b + r0[0] + r) * kCB + c] = Lr[0][r * kCBP + c];
+    }
+    if (ti == 0)
+      for (int idx = tid; idx < kCB * kCB; idx += 256) {
+        const int r = idx % kCB, c = idx / kCB;
+        cur[r * kCB + c] = D[r * kCBP + c];
+      }
+  }
+  // tile -= L21(rows) L21(cols)^H
+  for (int e = tid; e < kCT * kCT; e += 256) {
+    const int r = e % kCT, k = e / kCT;
+    const int gr = r0[0] + r, gk = r0[1] + k;
+    if (gr >= mt || gk >= mt || gk > gr) continue;
+    double2 *p = S + (jb + b + gr) + (long)(jb + b + gk) * ld;
+    double2 acc = *p;
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) acc = csub(acc, cmulc(Lr[0][r * kCBP + c], Lr[1][k * kCBP + c]));
+    *p = acc;
+  }
+}
+
 // ---------------------------------------------------------------- triangular solves
 // One wave per right-hand side column j; the column's n <= 512 entries sit in
 // registers (row s * 64 + lane in slot s).
@@ -564,13 +681,46 @@ __device__ __forceinline__ double recip(double q) {
   return fma(r, e, r);
 }
 
+// The recurrence is one dependent chain; its operands (LDS) are read a chunk
+// of kSU steps ahead so that their latency stays off the chain.
+constexpr int kSU = 8;
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int s, int t, double x,
                                            double pivmin) {
   int c = 0;
   double q = d[s] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   c += q < 0.0;
-  for (int i = s + 1; i < t; ++i) {
+  int i = s + 1;
+  double dn[kSU], en[kSU];
+  if (i + kSU <= t) {
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      dn[u] = d[i + u];
+      en[u] = e2[i - 1 + u];
+    }
+  }
+  for (; i + kSU <= t; i += kSU) {
+    double dc[kSU], ec[kSU];
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      dc[u] = dn[u];
+      ec[u] = en[u];
+    }
+    if (i + 2 * kSU <= t) {
+#pragma unroll
+      for (int u = 0; u < kSU; ++u) {
+        dn[u] = d[i + kSU + u];
+        en[u] = e2[i + kSU - 1 + u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSU; ++u) {
+      q = dc[u] - x - ec[u] * recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0;
+    }
+  }
+  for (; i < t; ++i) {
     q = d[i] - x - e2[i - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
@@ -706,9 +856,12 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     sh_d[1] = gu;
   }
   __syncthreads();
+  // (stops once exactly nb eigenvalues lie below the upper end: the cut then
+  // selects the nb wanted ones and nothing else)
+  int cup = n;   // count at the upper end
   for (int round = 0; round < 8; ++round) {
     const double a = sh_d[0], b = sh_d[1];
-    if (b - a <= 2.0 * kEps * tnorm) break;   // uniform: absolute accuracy eps ||T||
+    if (b - a <= 2.0 * kEps * tnorm || cup == nb) break;   // uniform
     const double x = a + (b - a) * (double)(tid + 1) / (double)(kET + 1);
     const int c = sturm_count(sd, se2, 0, n, x, pivmin);
     if (tid == 0) sh_i[2] = kET;
@@ -716,7 +869,9 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     if (c > nb - 1) atomicMin(&sh_i[2], tid);   // first point above: order-free minimum
     __syncthreads();
     const int f = sh_i[2];
+    if (tid == f) sh_i[3] = c;
     __syncthreads();
+    if (f < kET) cup = sh_i[3];
     if (tid == 0) {
       const double xf = f < kET ? a + (b - a) * (double)(f + 1) / (double)(kET + 1) : b;
       const double xl = f > 0 ? a + (b - a) * (double)f / (double)(kET + 1) : a;
@@ -748,19 +903,58 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   for (int b = tid; b < nblk; b += kET)
     for (int t = bof[b]; t < bof[b + 1]; ++t) tblk[t] = b;
   __syncthreads();
-  // bisection, one thread per task (local index t - bof[b] of block b)
-  if (tid < ntask) {
-    const int b = tblk[tid], s = bst[b], t = bst[b + 1], loc = tid - bof[b];
-    double a = gl, c = xcut;
-    for (int it = 0; it < 160; ++it) {
-      if (c - a <= 2.0 * kEps * tnorm) break;
-      const double mid = 0.5 * (a + c);
-      if (!(mid > a && mid < c)) break;
-      if (sturm_count(sd, se2, s, t, mid, pivmin) > loc) c = mid;
-      else a = mid;
-    }
-    tlam[tid] = 0.5 * (a + c);
+  // Start brackets.  When T is one block (the usual case) a task's local
+  // index is its global one, and one pass of kET Sturm counts over
+  // [gl, xcut] gives every task a bracket 1/(kET + 1) of that range wide
+  // (count at the lower end <= index < count at the upper end).
+  if (nblk == 1) {
+    kid[tid] = sturm_count(sd, se2, 0, n, gl + (xcut - gl) * (double)(tid + 1) / (double)(kET + 1),
+                           pivmin);
+    __syncthreads();
   }
+  // Multisection, G threads per task (the lanes of a group adjacent in one
+  // wave): each round the group's G points split the bracket into G + 1
+  // parts and the first point whose count exceeds the task's index becomes
+  // the upper end.  Every lane takes part in every round (the group
+  // exchanges go through cross-lane reads), finished groups unchanged.
+  {
+    const int G = ntask <= kET / 4 ? 4 : 2;   // ntask <= kEMaxN = kET / 2
+    const int task = tid / G, sub = tid % G;
+    const bool real_task = task < ntask;
+    const int b = real_task ? tblk[task] : 0;
+    const int s = bst[b], t = bst[b + 1], loc = real_task ? task - bof[b] : 0;
+    double a = gl, c = xcut;
+    if (nblk == 1 && real_task) {
+      int lo = 0, hi = kET;   // first point with count > loc (kET: none)
+      while (lo < hi) {
+        const int md = (lo + hi) >> 1;
+        if (kid[md] > loc) hi = md;
+        else lo = md + 1;
+      }
+      if (lo < kET) c = gl + (xcut - gl) * (double)(lo + 1) / (double)(kET + 1);
+      if (lo > 0) a = gl + (xcut - gl) * (double)lo / (double)(kET + 1);
+    }
+    const int base = lane - sub;   // the group's first lane
+    for (int it = 0; it < 160; ++it) {
+      const double x0 = a + (c - a) / (double)(G + 1);
+      const double xl = a + (c - a) * (double)G / (double)(G + 1);
+      const bool act = real_task && c - a > 2.0 * kEps * tnorm && x0 > a && xl < c;
+      if (!__any(act)) break;
+      const double x = a + (c - a) * (double)(sub + 1) / (double)(G + 1);
+      const int above = sturm_count(sd, se2, s, t, x, pivmin) > loc;
+      int first = G;   // first point of the group above the index
+      for (int j = G - 1; j >= 0; --j)
+        if (__shfl(above, base + j)) first = j;
+      if (act) {
+        const double na = first > 0 ? a + (c - a) * (double)first / (double)(G + 1) : a;
+        const double nc = first < G ? a + (c - a) * (double)(first + 1) / (double)(G + 1) : c;
+        a = na;
+        c = nc;
+      }
+    }
+    if (real_task && sub == 0) tlam[task] = 0.5 * (a + c);
+  }
+  __syncthreads();
   // sort (value, task) pairs by value, task index breaking ties (bitonic, 1024 keys)
   key[tid] = tid < ntask ? tlam[tid] : INFINITY;
   kid[tid] = tid;
@@ -799,8 +993,9 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   }
   __syncthreads();
   const long ls = n;   // per-task scratch stride
-  double *twp = scr;                    // [task][n] D+ (top-down pivots)
-  double *twm = scr + ls * kEMaxN;      // [task][n] D- (bottom-up pivots)
+  constexpr long kTS = kEMaxN;          // row stride of the pivot arrays
+  double *twp = scr;                    // [n][task] D+ (top-down pivots)
+  double *twm = scr + ls * kEMaxN;      // [n][task] D- (bottom-up pivots)
   double *lu = scr + 2 * ls * kEMaxN;   // [task][5 n] pivoted LU (group leaders)
   const double dtiny = kEps * tnorm;
   auto in_group = [&](int t) {   // selected task t is in a degenerate group of >= 2
@@ -817,16 +1012,26 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
       if (m == 1) {
         z[s] = 1.0;
       } else {
-        double *dp = twp + (long)tid * ls, *dm = twm + (long)tid * ls;
-        dp[0] = sd[s] - lam;
-        for (int i = 1; i < m; ++i) dp[i] = sd[s + i] - lam - se2[s + i - 1] / guard(dp[i - 1], pivmin);
-        dm[m - 1] = sd[t - 1] - lam;
-        for (int i = m - 2; i >= 0; --i) dm[i] = sd[s + i] - lam - se2[s + i] / guard(dm[i + 1], pivmin);
+        // pivots stored row-major over the tasks ([i][task]): the lanes of a
+        // wave touch consecutive addresses at each step
+        // (the top-down and bottom-up recurrences interleaved: two
+        // independent chains)
+        double *dp = twp + tid, *dm = twm + tid;
+        double qp = sd[s] - lam, qm = sd[t - 1] - lam;
+        dp[0] = qp;
+        dm[(m - 1) * kTS] = qm;
+        for (int i = 1; i < m; ++i) {
+          const int j = m - 1 - i;
+          qp = sd[s + i] - lam - se2[s + i - 1] / guard(qp, pivmin);
+          qm = sd[s + j] - lam - se2[s + j] / guard(qm, pivmin);
+          dp[i * kTS] = qp;
+          dm[j * kTS] = qm;
+        }
         int r = 0;
         double best = INFINITY;
 #pragma unroll 8
         for (int i = 0; i < m; ++i) {
-          const double gm = fabs(dp[i] + dm[i] - (sd[s + i] - lam));
+          const double gm = fabs(dp[i * kTS] + dm[i * kTS] - (sd[s + i] - lam));
           if (gm < best) {
             best = gm;
             r = i;
@@ -836,12 +1041,12 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
         double nn = 1.0;
 #pragma unroll 8
         for (int i = r - 1; i >= 0; --i) {
-          z[s + i] = -se[s + i] / guard(dp[i], pivmin) * z[s + i + 1];
+          z[s + i] = -se[s + i] / guard(dp[i * kTS], pivmin) * z[s + i + 1];
           nn += z[s + i] * z[s + i];
         }
 #pragma unroll 8
         for (int i = r; i + 1 < m; ++i) {
-          z[s + i + 1] = -se[s + i] / guard(dm[i + 1], pivmin) * z[s + i];
+          z[s + i + 1] = -se[s + i] / guard(dm[(i + 1) * kTS], pivmin) * z[s + i];
           nn += z[s + i + 1] * z[s + i + 1];
         }
         const double inv = 1.0 / sqrt(nn);
@@ -972,9 +1177,19 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
 
 size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN; }
 
-hipError_t launch_chol(double2 *S, long ld, int n, int *info, hipStream_t s) {
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kET), 0, s, S, ld, n, info);
+  if (n <= kCholOneWG) {
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kET), 0, s, S, ld, n, info);
+    return hipGetLastError();
+  }
+  double2 *w = reinterpret_cast<double2 *>(scr);
+  for (int jb = 0; jb < n; jb += kCB) {
+    const int mt = max(0, n - jb - kCB);
+    const int t = (mt + kCT - 1) / kCT;
+    hipLaunchKernelGGL(cholp_kernel, dim3(max(1, t * (t + 1) / 2)), dim3(256), 0, s, S, ld, n, jb,
+                       w, info);
+  }
   return hipGetLastError();
 }
 

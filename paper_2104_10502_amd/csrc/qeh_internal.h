@@ -305,8 +305,9 @@ hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldp
 // ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
 // Reduced problems up to kEigMaxN; column-major double2 matrices.
 constexpr int kEigMaxN = 512;
-// S = L L^H in place (lower), one workgroup; info = 0 or the failing column + 1.
-hipError_t launch_chol(double2 *S, long ld, int n, int *info, hipStream_t s);
+// S = L L^H in place (lower); info = 0 or the failing column + 1.  scr: 64 n
+// doubles of scratch (the eigenpair scratch below is large enough and free).
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, hipStream_t s);
 // X = L^-1 B (mode 0, T = L lower), X = L^-1 M^H with B = M (mode 1), or
 // X = U^-1 B (mode 2, T = U upper, backward); ncol columns, one wave each.
 hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double2 *B, long ldb,

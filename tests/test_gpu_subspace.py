@@ -133,6 +133,18 @@ def test_error_returns():
     with pytest.raises(q.QehError) as ei:
         _solve(hn, np.eye(32), 8)
     assert ei.value.status == q.QEH_ERR_NUMERIC
+    # the same two failures at an order that takes the multi-workgroup
+    # Cholesky and Householder paths
+    h2 = _herm(rng, 200)
+    bad_s2 = np.diag(np.r_[np.ones(150), -1.0, np.ones(49)]).astype(np.complex128)
+    with pytest.raises(q.QehError) as ei:
+        _solve(h2, bad_s2, 8)
+    assert ei.value.status == q.QEH_ERR_CHOLESKY
+    h2[77, 140] = np.nan
+    h2[140, 77] = np.nan
+    with pytest.raises(q.QehError) as ei:
+        _solve(h2, np.eye(200), 8)
+    assert ei.value.status == q.QEH_ERR_NUMERIC
     big = torch.zeros((513, 513), dtype=torch.complex128, device="cuda")
     with pytest.raises(q.QehError) as ei:
         q.subspace_eigh(big, big, 4)
