@@ -787,12 +787,22 @@ __device__ void wave_mgs(double *Z, int ldz, const int *zc, int g0, int cnt, int
 }
 
 // The nb lowest eigenpairs of T (tri = d | e).  w[j] ascending, Z(:, j)
-// (column-major, ldz >= n, real) orthonormal eigenvectors.  scr: 7 n kEMaxN
-// doubles.  info: 0, 1 (T not finite), 2 (fewer than nb eigenvalues found).
+// (column-major, ldz >= n, real) orthonormal eigenvectors.  scr:
+// eig_scratch_doubles(n) doubles.  info: 0, 1 (T not finite), 2 (fewer than
+// nb eigenvalues found).  Two launches: PH = 0 over many workgroups finds the
+// cut and the eigenvalues (each workgroup sets up T and the tasks itself, the
+// same arithmetic in each, and bisects its share of the tasks), leaving the
+// cut and the task eigenvalues in scr; PH = 1 (one workgroup) takes them and
+// sorts, groups and forms the eigenvectors.
+template <int PH>
 __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, int nb, double *w,
                                                      double *Z, int ldz, double *scr, int *info,
                                                      const int *info_chol) {
   if (*info_chol != 0) return;
+  if (PH == 1 && *info != 0) return;
+  if (PH == 0 && blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+  double *tlam_g = scr + 7L * n * kEMaxN;   // task eigenvalues, then the cut
+  double *xcut_g = tlam_g + kEMaxN;
   __shared__ double sd[kEMaxN], se[kEMaxN], se2[kEMaxN];
   __shared__ int bst[kEMaxN + 1];    // block starts
   __shared__ int bof[kEMaxN + 1];    // first task of each block
@@ -820,7 +830,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   me = block_max(me, red);
   const double tnorm = md + 2.0 * me;
   if (!isfinite(tnorm) || nb < 1 || nb > n) {
-    if (tid == 0) *info = 1;
+    if (PH == 0 && blockIdx.x == 0 && tid == 0) *info = 1;
     return;
   }
   // split where |e| is negligible
@@ -856,31 +866,34 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     sh_d[1] = gu;
   }
   __syncthreads();
-  // (stops once exactly nb eigenvalues lie below the upper end: the cut then
-  // selects the nb wanted ones and nothing else)
-  int cup = n;   // count at the upper end
-  for (int round = 0; round < 8; ++round) {
-    const double a = sh_d[0], b = sh_d[1];
-    if (b - a <= 2.0 * kEps * tnorm || cup == nb) break;   // uniform
-    const double x = a + (b - a) * (double)(tid + 1) / (double)(kET + 1);
-    const int c = sturm_count(sd, se2, 0, n, x, pivmin);
-    if (tid == 0) sh_i[2] = kET;
-    __syncthreads();
-    if (c > nb - 1) atomicMin(&sh_i[2], tid);   // first point above: order-free minimum
-    __syncthreads();
-    const int f = sh_i[2];
-    if (tid == f) sh_i[3] = c;
-    __syncthreads();
-    if (f < kET) cup = sh_i[3];
-    if (tid == 0) {
-      const double xf = f < kET ? a + (b - a) * (double)(f + 1) / (double)(kET + 1) : b;
-      const double xl = f > 0 ? a + (b - a) * (double)f / (double)(kET + 1) : a;
-      sh_d[0] = xl;
-      sh_d[1] = xf;
+  if (PH == 0) {
+    // (stops once exactly nb eigenvalues lie below the upper end: the cut then
+    // selects the nb wanted ones and nothing else)
+    int cup = n;   // count at the upper end
+    for (int round = 0; round < 8; ++round) {
+      const double a = sh_d[0], b = sh_d[1];
+      if (b - a <= 2.0 * kEps * tnorm || cup == nb) break;   // uniform
+      const double x = a + (b - a) * (double)(tid + 1) / (double)(kET + 1);
+      const int c = sturm_count(sd, se2, 0, n, x, pivmin);
+      if (tid == 0) sh_i[2] = kET;
+      __syncthreads();
+      if (c > nb - 1) atomicMin(&sh_i[2], tid);   // first point above: order-free minimum
+      __syncthreads();
+      const int f = sh_i[2];
+      if (tid == f) sh_i[3] = c;
+      __syncthreads();
+      if (f < kET) cup = sh_i[3];
+      if (tid == 0) {
+        const double xf = f < kET ? a + (b - a) * (double)(f + 1) / (double)(kET + 1) : b;
+        const double xl = f > 0 ? a + (b - a) * (double)f / (double)(kET + 1) : a;
+        sh_d[0] = xl;
+        sh_d[1] = xf;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  const double xcut = sh_d[1] + 4.0 * kEps * tnorm + pivmin;
+  const double xcut = PH == 0 ? sh_d[1] + 4.0 * kEps * tnorm + pivmin : *xcut_g;
+  if (PH == 0 && blockIdx.x == 0 && tid == 0) *xcut_g = xcut;
   // eigenvalues of each block below the cut -> tasks
   for (int b = tid; b < nblk; b += kET) bof[b] = sturm_count(sd, se2, bst[b], bst[b + 1], xcut, pivmin);
   __syncthreads();
@@ -897,29 +910,33 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   __syncthreads();
   const int ntask = sh_i[1];
   if (ntask < nb || ntask > kEMaxN) {
-    if (tid == 0) *info = 2;
+    if (PH == 0 && blockIdx.x == 0 && tid == 0) *info = 2;
     return;
   }
   for (int b = tid; b < nblk; b += kET)
     for (int t = bof[b]; t < bof[b + 1]; ++t) tblk[t] = b;
   __syncthreads();
-  // Start brackets.  When T is one block (the usual case) a task's local
-  // index is its global one, and one pass of kET Sturm counts over
-  // [gl, xcut] gives every task a bracket 1/(kET + 1) of that range wide
-  // (count at the lower end <= index < count at the upper end).
-  if (nblk == 1) {
-    kid[tid] = sturm_count(sd, se2, 0, n, gl + (xcut - gl) * (double)(tid + 1) / (double)(kET + 1),
-                           pivmin);
-    __syncthreads();
-  }
-  // Multisection, G threads per task (the lanes of a group adjacent in one
-  // wave): each round the group's G points split the bracket into G + 1
-  // parts and the first point whose count exceeds the task's index becomes
-  // the upper end.  Every lane takes part in every round (the group
-  // exchanges go through cross-lane reads), finished groups unchanged.
-  {
-    const int G = ntask <= kET / 4 ? 4 : 2;   // ntask <= kEMaxN = kET / 2
-    const int task = tid / G, sub = tid % G;
+  if (PH == 0) {
+    // Start brackets.  When T is one block (the usual case) a task's local
+    // index is its global one, and one pass of kET Sturm counts over
+    // [gl, xcut] gives every task a bracket 1/(kET + 1) of that range wide
+    // (count at the lower end <= index < count at the upper end).
+    if (nblk == 1) {
+      kid[tid] = sturm_count(sd, se2, 0, n,
+                             gl + (xcut - gl) * (double)(tid + 1) / (double)(kET + 1), pivmin);
+      __syncthreads();
+    }
+    // Multisection, G lanes per task over all workgroups (the lanes of a
+    // group adjacent in one wave; G a power of two <= 64): each round the
+    // group's G points split the bracket into G + 1 parts and the first
+    // point whose count exceeds the task's index becomes the upper end.
+    // Every lane takes part in every round (one wave-wide ballot carries
+    // the groups' comparisons), finished groups unchanged.
+    const int gthreads = gridDim.x * kET;
+    int G = 64;
+    while (G > 1 && G * ntask > gthreads) G >>= 1;
+    const int gt = blockIdx.x * kET + tid;
+    const int task = gt / G, sub = gt % G;
     const bool real_task = task < ntask;
     const int b = real_task ? tblk[task] : 0;
     const int s = bst[b], t = bst[b + 1], loc = real_task ? task - bof[b] : 0;
@@ -941,10 +958,11 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
       const bool act = real_task && c - a > 2.0 * kEps * tnorm && x0 > a && xl < c;
       if (!__any(act)) break;
       const double x = a + (c - a) * (double)(sub + 1) / (double)(G + 1);
-      const int above = sturm_count(sd, se2, s, t, x, pivmin) > loc;
-      int first = G;   // first point of the group above the index
-      for (int j = G - 1; j >= 0; --j)
-        if (__shfl(above, base + j)) first = j;
+      const unsigned long long above =
+          __ballot(sturm_count(sd, se2, s, t, x, pivmin) > loc);
+      // first point of the group above the index (G: none)
+      const unsigned long long mine = (above >> base) & (G == 64 ? ~0ull : ((1ull << G) - 1));
+      const int first = mine ? __builtin_ctzll(mine) : G;
       if (act) {
         const double na = first > 0 ? a + (c - a) * (double)first / (double)(G + 1) : a;
         const double nc = first < G ? a + (c - a) * (double)(first + 1) / (double)(G + 1) : c;
@@ -952,8 +970,10 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
         c = nc;
       }
     }
-    if (real_task && sub == 0) tlam[task] = 0.5 * (a + c);
+    if (real_task && sub == 0) tlam_g[task] = 0.5 * (a + c);
+    return;
   }
+  for (int i = tid; i < ntask; i += kET) tlam[i] = tlam_g[i];
   __syncthreads();
   // sort (value, task) pairs by value, task index breaking ties (bitonic, 1024 keys)
   key[tid] = tid < ntask ? tlam[tid] : INFINITY;
@@ -1126,46 +1146,82 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
 }
 
 // ---------------------------------------------------------------- back-transformation
-// Zc(:, j) = Q Zt(:, j) = H_0 (H_1 ( ... H_{n-2} Zt(:, j))), one wave per column.
+constexpr int kTK = 8;   // reflectors staged per chunk
+
+// Zc(:, j) = Q Zt(:, j) = H_0 (H_1 ( ... H_{n-2} Zt(:, j))), one wave per
+// column; the four waves of a workgroup share the reflectors, staged through
+// LDS kTK at a time with the next chunk's loads in flight.
 __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__ A, long lda, int n,
                                                      const double *__restrict__ tri,
                                                      const double *__restrict__ Zt, int ldz,
                                                      int nb, double2 *__restrict__ Zc, long ldc,
                                                      const int *info_chol, const int *info_eig) {
   if (*info_chol != 0 || *info_eig != 0) return;
+  __shared__ double2 Vs[kTK][kEMaxN];
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= nb) return;
+  const bool live = j < nb;   // every wave stays for the barriers
   const double2 *tau = reinterpret_cast<const double2 *>(tri + 2 * n);
   double2 z[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const int i = s * 64 + lane;
-    z[s] = make_double2(i < n ? Zt[i + (long)j * ldz] : 0.0, 0.0);
+    z[s] = make_double2(live && i < n ? Zt[i + (long)j * ldz] : 0.0, 0.0);
   }
-  for (int k = n - 2; k >= 0; --k) {
-    const double2 t = tau[k];
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    const double2 *v = A + (long)k * lda;
-    double dr = 0.0, di = 0.0;   // v^H z
+  // reflectors k = kl .. kh (rows > kl) in descending chunks, the next
+  // chunk's loads in flight during the current one's reflectors
+  constexpr int NPF = kTK * kEMaxN / 256;
+  double2 pf[NPF];
+  auto fetch = [&](int kh) {
+    const int kl = max(0, kh - kTK + 1), rows = n - (kl + 1);
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      const int i = s * 64 + lane;
-      if (i > k && i < n) {
-        const double2 vi = v[i];
-        dr += vi.x * z[s].x + vi.y * z[s].y;
-        di += vi.x * z[s].y - vi.y * z[s].x;
+    for (int u = 0; u < NPF; ++u) {
+      const int idx = threadIdx.x + u * 256;
+      const int c = idx / rows, i = kl + 1 + idx % rows;
+      pf[u] = idx < (kh - kl + 1) * rows ? A[i + (long)(kl + c) * lda] : make_double2(0.0, 0.0);
+    }
+  };
+  const int top = n - 2;
+  if (top >= 0) fetch(top);
+  for (int kh = top; kh >= 0; kh -= kTK) {
+    const int kl = max(0, kh - kTK + 1);
+    __syncthreads();
+    {
+      const int rows = n - (kl + 1);
+#pragma unroll
+      for (int u = 0; u < NPF; ++u) {
+        const int idx = threadIdx.x + u * 256;
+        const int c = idx / rows, i = kl + 1 + idx % rows;
+        if (idx < (kh - kl + 1) * rows) Vs[c][i] = pf[u];
       }
     }
-    dr = wave_sum(dr);
-    di = wave_sum(di);
-    const double2 c = cmul(t, make_double2(dr, di));
+    __syncthreads();
+    if (kh - kTK >= 0) fetch(kh - kTK);
+    for (int k = kh; k >= kl; --k) {
+      const double2 t = tau[k];
+      if (t.x == 0.0 && t.y == 0.0) continue;
+      const double2 *v = Vs[k - kl];
+      double dr = 0.0, di = 0.0;   // v^H z
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-      const int i = s * 64 + lane;
-      if (i > k && i < n) z[s] = csub(z[s], cmul(c, v[i]));
+      for (int s = 0; s < kSlots; ++s) {
+        const int i = s * 64 + lane;
+        if (i > k && i < n) {
+          const double2 vi = v[i];
+          dr += vi.x * z[s].x + vi.y * z[s].y;
+          di += vi.x * z[s].y - vi.y * z[s].x;
+        }
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double2 c = cmul(t, make_double2(dr, di));
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int i = s * 64 + lane;
+        if (i > k && i < n) z[s] = csub(z[s], cmul(c, v[i]));
+      }
     }
   }
+  if (!live) return;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const int i = s * 64 + lane;
@@ -1175,7 +1231,7 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
 
 }  // namespace
 
-size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN; }
+size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN + kEMaxN + 8; }
 
 hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
@@ -1228,7 +1284,11 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
 hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z, int ldz,
                          double *scr, int *info, const int *info_chol, hipStream_t s) {
   if (n < 1 || n > kEMaxN || nb < 1 || nb > n || ldz < n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(trieig_kernel, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
+  // eigenvalues on about 64 lanes per wanted one, then the vectors
+  const int g = max(1, min(32, (nb * 64 + kET - 1) / kET));
+  hipLaunchKernelGGL(trieig_kernel<0>, dim3(g), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
+                     info_chol);
+  hipLaunchKernelGGL(trieig_kernel<1>, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
                      info_chol);
   return hipGetLastError();
 }
