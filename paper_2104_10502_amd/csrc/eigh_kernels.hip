@@ -276,19 +276,95 @@ __global__ __launch_bounds__(256) void cholp_kernel(double2 *S, long ld, int n, 
 //   MODE 1: L x = b,   b = conj(M(j, :)) with M = B (column j of M^H)
 //   MODE 2: U x = b,   U upper (T), b = B(:, j)   (backward)
 // The diagonal of T is real (a Cholesky factor).
+//
+// By blocks of 64 rows (one slot): the diagonal block of T is staged in LDS
+// (shared by the workgroup's four waves) and the block's 64 unknowns are
+// solved there, a dependent chain through LDS and scalar lane reads; the
+// slots on the far side then take the block's contribution, x_s -= T_sb x_b,
+// whose T loads are independent of one another and stream from L2.  Each
+// x_i still receives its terms T_ik x_k in the order of k.
+__device__ __forceinline__ double lane_read(double v, int l) {
+  // value of lane l (wave-uniform) of v, through the scalar unit
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One block round: solve block (= slot) B, then the far side.  B is a
+// template argument so that every slot index is a compile-time constant and
+// x stays in registers.
+template <int MODE, int B>
+__device__ __forceinline__ void trsm_round(double2 (&x)[kSlots], const double2 *__restrict__ T,
+                                           long ldt, int n, int lane, double2 (*Tb)[64],
+                                           double *rd) {
+  const int nbk = (n + 63) / 64;
+  if (B >= nbk) return;   // uniform
+  const int b0 = B * 64, bs = min(64, n - b0);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int r = idx & 63, c = idx >> 6;
+    if (r < bs && c < bs) Tb[c][r] = T[(b0 + r) + (long)(b0 + c) * ldt];
+  }
+  if ((int)threadIdx.x < bs)
+    rd[threadIdx.x] = 1.0 / T[(b0 + threadIdx.x) + (long)(b0 + threadIdx.x) * ldt].x;
+  __syncthreads();
+  // the block's unknowns
+  if (MODE != 2) {
+    for (int c = 0; c < bs; ++c) {
+      const double2 xk = cscale(make_double2(lane_read(x[B].x, c), lane_read(x[B].y, c)), rd[c]);
+      if (lane == c) x[B] = xk;
+      else if (lane > c && lane < bs) x[B] = csub(x[B], cmul(Tb[c][lane], xk));
+    }
+  } else {
+    for (int c = bs - 1; c >= 0; --c) {
+      const double2 xk = cscale(make_double2(lane_read(x[B].x, c), lane_read(x[B].y, c)), rd[c]);
+      if (lane == c) x[B] = xk;
+      else if (lane < c) x[B] = csub(x[B], cmul(Tb[c][lane], xk));
+    }
+  }
+  // the far side: x_s -= T(rows of s, columns of B) x_B
+#pragma unroll
+  for (int s2 = 0; s2 < kSlots; ++s2) {
+    const bool far = MODE == 2 ? s2 < B : s2 > B;
+    const int i = s2 * 64 + lane;
+    if (far && s2 < nbk) {
+      const double2 *tc = T + i + (long)b0 * ldt;
+      double2 acc = x[s2];
+      for (int c0 = 0; c0 < bs; c0 += 8) {
+        double2 tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          tv[u] = i < n && c0 + u < bs ? tc[(long)(c0 + u) * ldt] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (c0 + u < bs) {
+            const double2 xc = make_double2(lane_read(x[B].x, c0 + u), lane_read(x[B].y, c0 + u));
+            acc = csub(acc, cmul(tv[u], xc));
+          }
+        }
+      }
+      if (i < n) x[s2] = acc;
+    }
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T, long ldt, int n,
                                                    const double2 *__restrict__ B, long ldb,
                                                    int ncol, double2 *__restrict__ X, long ldx) {
+  static_assert(kSlots == 8, "block rounds below are written for 8 slots");
+  __shared__ double2 Tb[64][64];   // diagonal block, column-major: Tb[c][r] = T(b0 + r, b0 + c)
+  __shared__ double rd[64];        // reciprocals of its diagonal
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (j >= ncol) return;   // whole waves only: no workgroup barrier below
+  const bool live = j < ncol;   // every wave stays for the barriers
   double2 x[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const int i = s * 64 + lane;
     double2 v = make_double2(0.0, 0.0);
-    if (i < n) {
+    if (live && i < n) {
       if (MODE == 1) {
         const double2 m = B[j + (long)i * ldb];
         v = make_double2(m.x, -m.y);
@@ -299,40 +375,25 @@ __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T
     x[s] = v;
   }
   if (MODE != 2) {
-#pragma unroll
-    for (int sb = 0; sb < kSlots; ++sb) {
-      for (int l = 0; l < 64; ++l) {
-        const int k = sb * 64 + l;
-        if (k >= n) break;
-        const double rinv = 1.0 / T[k + (long)k * ldt].x;
-        double2 xk = make_double2(__shfl(x[sb].x, l), __shfl(x[sb].y, l));
-        xk = cscale(xk, rinv);
-        if (lane == l) x[sb] = xk;
-#pragma unroll
-        for (int s = sb; s < kSlots; ++s) {
-          const int i = s * 64 + lane;
-          if (i > k && i < n) x[s] = csub(x[s], cmul(T[i + (long)k * ldt], xk));
-        }
-      }
-    }
+    trsm_round<MODE, 0>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 1>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 2>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 3>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 4>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 5>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 6>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 7>(x, T, ldt, n, lane, Tb, rd);
   } else {
-#pragma unroll
-    for (int sb = kSlots - 1; sb >= 0; --sb) {
-      for (int l = 63; l >= 0; --l) {
-        const int k = sb * 64 + l;
-        if (k >= n) continue;
-        const double rinv = 1.0 / T[k + (long)k * ldt].x;
-        double2 xk = make_double2(__shfl(x[sb].x, l), __shfl(x[sb].y, l));
-        xk = cscale(xk, rinv);
-        if (lane == l) x[sb] = xk;
-#pragma unroll
-        for (int s = 0; s <= sb; ++s) {
-          const int i = s * 64 + lane;
-          if (i < k) x[s] = csub(x[s], cmul(T[i + (long)k * ldt], xk));
-        }
-      }
-    }
+    trsm_round<MODE, 7>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 6>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 5>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 4>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 3>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 2>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 1>(x, T, ldt, n, lane, Tb, rd);
+    trsm_round<MODE, 0>(x, T, ldt, n, lane, Tb, rd);
   }
+  if (!live) return;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     const int i = s * 64 + lane;
@@ -1025,12 +1086,13 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   if (tid < ntask && tpos[tid] < nb) {
     const int b = tblk[tid], s = bst[b], t = bst[b + 1], m = t - s;
     double *z = Z + (long)tpos[tid] * ldz;
-    for (int i = 0; i < n; ++i)
-      if (i < s || i >= t) z[i] = 0.0;
     const double lam = tlam[tid];
+    if (in_group(tid))
+      for (int i = 0; i < n; ++i)
+        if (i < s || i >= t) z[i] = 0.0;
     if (!in_group(tid)) {
       if (m == 1) {
-        z[s] = 1.0;
+        for (int i = 0; i < n; ++i) z[i] = i == s ? 1.0 : 0.0;
       } else {
         // pivots stored row-major over the tasks ([i][task]): the lanes of a
         // wave touch consecutive addresses at each step
@@ -1057,21 +1119,30 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
             r = i;
           }
         }
-        z[s + r] = 1.0;
-        double nn = 1.0;
+        // the unnormalised vector (entry r = 1) replaces the pivots it is
+        // formed from (coalesced), and goes to Z once, normalised, with the
+        // zeros outside the block (one strided pass)
+        double zc = 1.0, nn = 1.0;
 #pragma unroll 8
         for (int i = r - 1; i >= 0; --i) {
-          z[s + i] = -se[s + i] / guard(dp[i * kTS], pivmin) * z[s + i + 1];
-          nn += z[s + i] * z[s + i];
+          zc = -se[s + i] / guard(dp[i * kTS], pivmin) * zc;
+          dp[i * kTS] = zc;
+          nn += zc * zc;
         }
+        zc = 1.0;
 #pragma unroll 8
         for (int i = r; i + 1 < m; ++i) {
-          z[s + i + 1] = -se[s + i] / guard(dm[(i + 1) * kTS], pivmin) * z[s + i];
-          nn += z[s + i + 1] * z[s + i + 1];
+          zc = -se[s + i] / guard(dm[(i + 1) * kTS], pivmin) * zc;
+          dm[(i + 1) * kTS] = zc;
+          nn += zc * zc;
         }
         const double inv = 1.0 / sqrt(nn);
 #pragma unroll 8
-        for (int i = s; i < t; ++i) z[i] *= inv;
+        for (int i = 0; i < n; ++i) {
+          const int li = i - s;
+          const double v = li < 0 || li >= m ? 0.0 : li < r ? dp[li * kTS] : li == r ? 1.0 : dm[li * kTS];
+          z[i] = v * inv;
+        }
       }
     } else if (gdeg[tid] == tid) {
       // pivoted LU of T_b - lam I (LAPACK gttrf order)
