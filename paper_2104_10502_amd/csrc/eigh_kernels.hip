@@ -2,10 +2,12 @@
 // small reduced problems of block Davidson (n <= 512): the paper solves this
 // small generalized eigenproblem with a dense GPU solver (section "Evolution
 // of the GPU-enabled version").  H y = eps S y for the lowest nb
-// pairs, in six deterministic kernels (fixed summation orders, no atomics on
+// pairs, in deterministic kernels (fixed summation orders, no atomics on
 // floating-point data):
 //
 //   chol_kernel     one workgroup: S = L L^H, right-looking, lower triangle
+//                   (orders <= 64); cholp_kernel: one launch per 16-column
+//                   panel over many workgroups (larger orders)
 //   trsm_kernel     one wave per column, many workgroups: L X = B (forward),
 //                   with B given or as the adjoint of a matrix, or L^H X = B
 //                   (backward with the explicit L^H); A = L^-1 H L^-H by two
@@ -13,14 +15,15 @@
 //   tdstep_kernel   one launch per Householder step while the trailing block
 //                   is larger than kTailN, one wave per column, many
 //                   workgroups
-//   tridiag_kernel  one workgroup: the remaining steps of the Householder
-//                   reduction A = Q T Q^H, T real symmetric tridiagonal (d, e),
-//                   reflectors kept in A
-//   trieig_kernel   one workgroup: the nb lowest eigenpairs of T.  T is split
-//                   where |e_k| <= eps ||T||; the global nb-th eigenvalue is
+//   tridiag_lds_kernel  one workgroup, trailing block in LDS: the last
+//                   kTailN steps of the Householder reduction A = Q T Q^H, T
+//                   real symmetric tridiagonal (d, e), reflectors kept in A
+//   trieig_kernel   the nb lowest eigenpairs of T.  T is split where
+//                   |e_k| <= eps ||T||; the global nb-th eigenvalue is
 //                   bracketed by multisection of Sturm counts; every block's
-//                   eigenvalues below it are found by bisection (one thread
-//                   each) and sorted; eigenvectors come from twisted
+//                   eigenvalues below it are found by multisection over many
+//                   workgroups (first launch) and sorted (second launch, one
+//                   workgroup); eigenvectors come from twisted
 //                   factorizations of T_b - lambda I (one thread each), except
 //                   for groups of numerically equal eigenvalues of one block
 //                   (gap <= 1e-12 ||T||, as exact multiplets of A leave them:
@@ -30,7 +33,8 @@
 //                   sweeps; vectors of close eigenvalues of one block
 //                   (gap <= 1e-5 ||T||) are re-orthogonalised in index order
 //   backtr_kernel   one wave per column, many workgroups: Z = Q Z_T through
-//                   the stored reflectors
+//                   the stored reflectors (staged in LDS, shared by a
+//                   workgroup's waves)
 //
 // Storage: column-major double2 matrices with leading dimension ld.  A real
 // symmetric pair (Gamma point) goes through the same kernels with zero
@@ -51,7 +55,6 @@ constexpr double kEps = 2.220446049250313e-16;
 constexpr double kTiny = 2.2250738585072014e-308;
 constexpr double kDegRel = 1e-12;    // numerically equal eigenvalues (relative to ||T||)
 constexpr double kCloseRel = 1e-5;   // close eigenvalues, re-orthogonalised
-constexpr int kTU = 6;               // independent loads in flight per thread
 
 __device__ __forceinline__ double wave_sum(double v) {
   // fixed butterfly; lane 0's result is what callers use
@@ -406,12 +409,9 @@ __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T
 // H_k = I - tau_k v_k v_k^H acting on rows k+1..n-1.  On return column k of A
 // holds v_k in rows k+1..n-1 (v_k[k+1] = 1); tri = d[n] | e[n] | tau (double2)[n].
 //
-// Step k needs p = A22 v_k (A22 = rows / columns k+1..); the rank-2 update of
-// step k and the product of step k+1 share one pass over the trailing matrix:
-// column k+1 is updated first (it defines v_{k+1}), then every other element
-// is read once, updated, written back and multiplied into p for step k+1.
-// Threads cover rows i (fastest, coalesced) x column groups; eight columns'
-// loads are in flight per thread.
+// Step k needs p = A22 v_k (A22 = rows / columns k+1..) and applies the
+// rank-2 update A22 -= v w^H + w v^H.
+//
 // Householder vector of the column col[0..m) (col[0] the subdiagonal entry):
 // tau, beta, and v written to col (v[0] = 1) and to vs.  Uniform in all NT
 // threads of the workgroup.
@@ -419,13 +419,16 @@ template <int NT = kET>
 __device__ void householder(double2 *col, int m, double2 *vs, double *red, double2 *t_out,
                             double *beta_out) {
   const int tid = threadIdx.x;
+  // alpha is read before the barriers of the sum: thread 0 overwrites col[0]
+  // with v[0] = 1 below, and a wave that read it only after the sum could
+  // see that write
+  const double2 alpha = col[0];
   double s = 0.0;
   for (int i = 1 + tid; i < m; i += NT) {
     const double2 v = col[i];
     s += v.x * v.x + v.y * v.y;
   }
   const double xn2 = block_sum<NT / 64>(s, red);
-  const double2 alpha = col[0];
   double beta;
   double2 t = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
   if (xn2 == 0.0 && alpha.y == 0.0) {
@@ -447,160 +450,18 @@ __device__ void householder(double2 *col, int m, double2 *vs, double *red, doubl
   *beta_out = beta;
 }
 
-// One pass over the m x m block U (columns 1..m-1, rows 1..m-1 of the
-// trailing matrix of step k; element (i, j) at U[i + j*lda]):
-//   if upd:  U(i, j) -= v_i conj(w_j) + w_i conj(v_j)   (stored back)
-//   if vn:   part[grp * mm + (i - 1)] = sum over the thread's columns of U(i, j) vn_{j-1}
-// Rows and columns 0 (column 0 was done separately) are skipped.
-__device__ void fused_pass(double2 *U, long lda, int m, bool upd, const double2 *vs,
-                           const double2 *ws, bool mv, const double2 *vn, double2 *part) {
-  const int tid = threadIdx.x;
-  const int mm = m - 1;
-  if (mm <= 0) return;
-  const int g = kET / mm;   // >= 2 (mm <= 510)
-  if (tid >= g * mm) return;
-  const int r = tid % mm, grp = tid / mm;
-  const int i = r + 1;
-  const double2 vi = vs[i], wi = ws[i];
-  double2 acc = make_double2(0.0, 0.0);
-  int j = 1 + grp;
-  for (; j + (kTU - 1) * g < m; j += kTU * g) {
-    double2 a[kTU];
-#pragma unroll
-    for (int u = 0; u < kTU; ++u) a[u] = U[i + (long)(j + u * g) * lda];
-#pragma unroll
-    for (int u = 0; u < kTU; ++u) {
-      const int jj = j + u * g;
-      if (upd) {
-        a[u] = csub(a[u], cadd(cmulc(vi, ws[jj]), cmulc(wi, vs[jj])));
-        U[i + (long)jj * lda] = a[u];
-      }
-      if (mv) acc = cadd(acc, cmul(a[u], vn[jj - 1]));
-    }
-  }
-  for (; j < m; j += g) {
-    double2 a = U[i + (long)j * lda];
-    if (upd) {
-      a = csub(a, cadd(cmulc(vi, ws[j]), cmulc(wi, vs[j])));
-      U[i + (long)j * lda] = a;
-    }
-    if (mv) acc = cadd(acc, cmul(a, vn[j - 1]));
-  }
-  if (mv) part[grp * mm + r] = acc;
-}
-
-__global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int n, double *d,
-                                                      double *e, double2 *tau,
-                                                      const int *info_chol) {
-  if (*info_chol != 0) return;
-  __shared__ double2 vbuf[2][kEMaxN];   // v_k and v_{k+1}
-  __shared__ double2 ps[kEMaxN];        // A22 v_k, then p, then w
-  __shared__ double2 part[kET];
-  __shared__ double red[kEW];
-  const int tid = threadIdx.x;
-  if (n == 1) {
-    if (tid == 0) d[0] = A[0].x;
-    return;
-  }
-  // step 0's reflector and its product A22 v_0 (a plain pass: no update)
-  double2 t;
-  double beta;
-  householder(A + 1, n - 1, vbuf[0], red, &t, &beta);
-  if (tid == 0) {
-    d[0] = A[0].x;
-    e[0] = beta;
-    tau[0] = t;
-  }
-  __syncthreads();
-  {
-    // the pass skips row / column 0 of its block: hand it the whole A22 by
-    // starting one row and column earlier (A11 corner of A)
-    const int m = n - 1;
-    // rows 0..m-1 of A22 times v: do row 0 and column 0 here too
-    const double2 *a22 = A + lda + 1;
-    const int g = kET / m;
-    if (tid < g * m) {
-      const int i = tid % m, grp = tid / m;
-      double2 acc = make_double2(0.0, 0.0);
-      int jj = grp;
-      for (; jj + (kTU - 1) * g < m; jj += kTU * g) {
-        double2 a[kTU];
-#pragma unroll
-        for (int u = 0; u < kTU; ++u) a[u] = a22[i + (long)(jj + u * g) * lda];
-#pragma unroll
-        for (int u = 0; u < kTU; ++u) acc = cadd(acc, cmul(a[u], vbuf[0][jj + u * g]));
-      }
-      for (; jj < m; jj += g) acc = cadd(acc, cmul(a22[i + (long)jj * lda], vbuf[0][jj]));
-      part[tid] = acc;
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += kET) {
-      double2 acc = part[i];
-      for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * m + i]);
-      ps[i] = acc;
-    }
-    __syncthreads();
-  }
-  int cur = 0;
-  for (int k = 0; k + 1 < n; ++k) {
-    const int m = n - k - 1;   // order of A22 of step k
-    double2 *u = A + (long)(k + 1) * lda + (k + 1);   // A22 of step k, (0, 0) corner
-    const double2 *vs = vbuf[cur];
-    const bool refl = t.x != 0.0 || t.y != 0.0;
-    if (refl) {
-      // p = t A22 v, alpha2 = -1/2 t (p^H v), w = p + alpha2 v (in ps)
-      double dr = 0.0, di = 0.0;
-      for (int i = tid; i < m; i += kET) {
-        const double2 p = cmul(t, ps[i]), v = vs[i];
-        dr += p.x * v.x + p.y * v.y;
-        di += p.x * v.y - p.y * v.x;
-      }
-      dr = block_sum(dr, red);
-      di = block_sum(di, red);
-      const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
-      for (int i = tid; i < m; i += kET) ps[i] = cadd(cmul(t, ps[i]), cmul(a2, vs[i]));
-      __syncthreads();
-      // column 0 of A22 (column k+1 of A), rows 0..m-1
-      for (int i = tid; i < m; i += kET)
-        u[i] = csub(u[i], cadd(cmulc(vs[i], ps[0]), cmulc(ps[i], vs[0])));
-      __syncthreads();
-    }
-    if (m == 1) {
-      if (tid == 0) d[k + 1] = u[0].x;
-      break;
-    }
-    // reflector of step k+1 from column k+1 below the diagonal
-    double2 t1;
-    double beta1;
-    householder(u + 1, m - 1, vbuf[cur ^ 1], red, &t1, &beta1);
-    if (tid == 0) {
-      d[k + 1] = u[0].x;
-      e[k + 1] = beta1;
-      tau[k + 1] = t1;
-    }
-    __syncthreads();
-    const bool refl1 = t1.x != 0.0 || t1.y != 0.0;
-    // rest of step k's update fused with step k+1's product (rows / columns
-    // 1..m-1 of this A22 are A22 of step k+1)
-    fused_pass(u, lda, m, refl, vs, ps, refl1, vbuf[cur ^ 1], part);
-    __syncthreads();
-    if (refl1) {
-      const int mm = m - 1, g = kET / mm;
-      for (int i = tid; i < mm; i += kET) {
-        double2 acc = part[i];
-        for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * mm + i]);
-        ps[i] = acc;
-      }
-    }
-    __syncthreads();
-    t = t1;
-    cur ^= 1;
-  }
-}
+// The last orders of the reduction (m <= kTailN, the whole problem when it
+// is that small): one workgroup with the trailing block in LDS, so nothing
+// leaves LDS between steps.  Step k: reflector of column k, p = t A22 v
+// (each thread a row and a quarter of the columns, partial sums added in a
+// fixed order), alpha = -1/2 t (p^H v), w = p + alpha v, A22 -= v w^H + w v^H
+// (both triangles).  On return the columns hold the reflectors as in the
+// step kernel's part.
+constexpr int kLT = 256;
 
 // Leading steps of the same reduction while the trailing block is large: one
 // launch per step over many workgroups, one wave per column of the trailing
-// block (kSW columns per workgroup); tridiag_kernel then reduces the last
+// block (kSW columns per workgroup); tridiag_lds_kernel then reduces the last
 // kTailN rows and columns as a problem of its own (after k0 steps the rest of
 // the reduction is the reduction of the updated block A[k0:, k0:]).
 //
@@ -726,6 +587,71 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
         tau[r0] = t1;
       }
     }
+  }
+}
+
+__global__ __launch_bounds__(kLT) void tridiag_lds_kernel(double2 *A, long lda, int m, double *d,
+                                                          double *e, double2 *tau,
+                                                          const int *info_chol) {
+  if (*info_chol != 0) return;
+  constexpr int G = kLT / kTailN;            // column groups of the product
+  __shared__ double2 Al[kTailN][kTailN + 1];   // [column][row]
+  __shared__ double2 vs[kTailN], ws[kTailN];
+  __shared__ double2 part[G][kTailN];
+  __shared__ double red[kLT / 64];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < m * m; idx += kLT) {
+    const int r = idx % m, c = idx / m;
+    Al[c][r] = A[r + (long)c * lda];
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < m; ++k) {
+    const int mm = m - k - 1;   // order of A22
+    double2 t;
+    double beta;
+    householder<kLT>(&Al[k][k + 1], mm, vs, red, &t, &beta);
+    if (tid == 0) {
+      d[k] = Al[k][k].x;
+      e[k] = beta;
+      tau[k] = t;
+    }
+    __syncthreads();
+    if (t.x == 0.0 && t.y == 0.0) continue;   // uniform
+    {
+      const int i = tid % kTailN, g = tid / kTailN;
+      double2 acc = make_double2(0.0, 0.0);
+      if (i < mm)
+        for (int j = g; j < mm; j += G) acc = cadd(acc, cmul(Al[k + 1 + j][k + 1 + i], vs[j]));
+      part[g][i] = acc;
+    }
+    __syncthreads();
+    double dr = 0.0, di = 0.0;
+    if (tid < mm) {
+      double2 p = part[0][tid];
+#pragma unroll
+      for (int g = 1; g < G; ++g) p = cadd(p, part[g][tid]);
+      p = cmul(t, p);
+      ws[tid] = p;
+      const double2 v = vs[tid];
+      dr = p.x * v.x + p.y * v.y;
+      di = p.x * v.y - p.y * v.x;
+    }
+    dr = block_sum<kLT / 64>(dr, red);
+    di = block_sum<kLT / 64>(di, red);
+    const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
+    if (tid < mm) ws[tid] = cadd(ws[tid], cmul(a2, vs[tid]));
+    __syncthreads();
+    for (int idx = tid; idx < mm * mm; idx += kLT) {
+      const int i = idx % mm, j = idx / mm;
+      double2 &a = Al[k + 1 + j][k + 1 + i];
+      a = csub(a, cadd(cmulc(vs[i], ws[j]), cmulc(ws[i], vs[j])));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) d[m - 1] = Al[m - 1][m - 1].x;
+  for (int idx = tid; idx < m * m; idx += kLT) {
+    const int r = idx % m, c = idx / m;
+    A[r + (long)c * lda] = Al[c][r];
   }
 }
 
@@ -1347,8 +1273,8 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
                          n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
     }
   }
-  hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A + k0 + (long)k0 * lda, lda, n - k0,
-                     d + k0, e + k0, tau + k0, info_chol);
+  hipLaunchKernelGGL(tridiag_lds_kernel, dim3(1), dim3(kLT), 0, s, A + k0 + (long)k0 * lda, lda,
+                     n - k0, d + k0, e + k0, tau + k0, info_chol);
   return hipGetLastError();
 }
 

@@ -110,12 +110,17 @@ def test_real_symmetric_pencil(n):
     assert np.abs(y.imag).max() == 0.0
 
 
-def test_bitwise_repeatable():
+@pytest.mark.parametrize("n", [48, 100, 300])
+def test_bitwise_repeatable(n):
+    # (repeats: a workgroup race would show as a rare bitwise difference;
+    # n = 48 runs the LDS-resident reduction alone, 100 and 300 the step
+    # kernel, the blocked Cholesky and the multi-workgroup bisection too)
     rng = np.random.default_rng(11)
-    h, s = _herm(rng, 300), _spd(rng, 300)
-    e1, y1 = _solve(h, s, 150)
-    e2, y2 = _solve(h, s, 150)
-    assert np.array_equal(e1, e2) and np.array_equal(y1, y2)
+    h, s = _herm(rng, n), _spd(rng, n)
+    e1, y1 = _solve(h, s, n // 2)
+    for _ in range(6):
+        e2, y2 = _solve(h, s, n // 2)
+        assert np.array_equal(e1, e2) and np.array_equal(y1, y2)
 
 
 def test_error_returns():
