@@ -481,13 +481,13 @@ void DavRun::rr_own() {
   const int n = nbase_, nb = nb_, ld = nvecx_;
   ok(launch_hermitise_copy(Hr_, ld, Hw_, ld, n, s));
   ok(launch_hermitise_copy(Sr_, ld, Sw_, ld, n, s));
-  ok(launch_chol(Sw_, ld, n, info_d_ + 1, escr_, s));
+  ok(launch_chol(Sw_, ld, n, info_d_ + 1, escr_, wide_, s));
   ok(launch_tril_adjoint(Sw_, Lc_, LcH_, ld, n, s));
   ok(launch_trsm(0, Lc_, ld, n, Hw_, ld, n, X_, ld, s));    // X = L^-1 Hr
   ok(launch_trsm(1, Lc_, ld, n, X_, ld, n, Sw_, ld, s));    // Sw = L^-1 X^H = A
   ok(launch_hermitise_copy(Sw_, ld, Hw_, ld, n, s));        // Hw = (A + A^H) / 2
-  ok(launch_tridiag(Hw_, ld, n, tri_, escr_, info_d_ + 1, s));
-  ok(launch_trieig(tri_, n, nb, eps_d_, Zt_, n, escr_, info_d_ + 3, info_d_ + 1, s));
+  ok(launch_tridiag(Hw_, ld, n, tri_, escr_, info_d_ + 1, wide_, s));
+  ok(launch_trieig(tri_, n, nb, eps_d_, Zt_, n, escr_, info_d_ + 3, info_d_ + 1, wide_, s));
   ok(launch_backtr(Hw_, ld, n, tri_, Zt_, n, nb, X_, ld, info_d_ + 1, info_d_ + 3, s));
   ok(launch_trsm(2, LcH_, ld, n, X_, ld, nb, Y_, ld, s));   // Y = L^-H Z
 }
@@ -1044,13 +1044,13 @@ qeh_status qeh_subspace_eigh(int n, int nb, const double *H, const double *S, in
   };
   run(launch_hermitise_copy(h, ld, M(L.Hw), n, n, s));
   run(launch_hermitise_copy(sm, ld, M(L.Sw), n, n, s));
-  run(launch_chol(M(L.Sw), n, n, info, escr, s));
+  run(launch_chol(M(L.Sw), n, n, info, escr, true, s));
   run(launch_tril_adjoint(M(L.Sw), M(L.Lc), M(L.LcH), n, n, s));
   run(launch_trsm(0, M(L.Lc), n, n, M(L.Hw), n, n, M(L.X), n, s));
   run(launch_trsm(1, M(L.Lc), n, n, M(L.X), n, n, M(L.Sw), n, s));
   run(launch_hermitise_copy(M(L.Sw), n, M(L.Hw), n, n, s));
-  run(launch_tridiag(M(L.Hw), n, n, tri, escr, info, s));
-  run(launch_trieig(tri, n, nb, eig, zt, n, escr, info + 2, info, s));
+  run(launch_tridiag(M(L.Hw), n, n, tri, escr, info, true, s));
+  run(launch_trieig(tri, n, nb, eig, zt, n, escr, info + 2, info, true, s));
   run(launch_backtr(M(L.Hw), n, n, tri, zt, n, nb, M(L.X), n, info, info + 2, s));
   run(launch_trsm(2, M(L.LcH), n, n, M(L.X), n, nb, reinterpret_cast<double2 *>(Y), ldy, s));
   int hinfo[4] = {0, 0, 0, 0};

@@ -52,6 +52,9 @@ class DavRun {
   // advance); after advance() returns false, take_request reports whether it
   // stopped for an H application rather than for a stream drain
   void set_rci() { rci_ = true; }
+  // own subspace solver on one workgroup per step (least device time: for
+  // runs that share the device, as the request server's jobs do)
+  void set_narrow_solver() { wide_ = false; }
   bool take_request(const double2 **x, double2 **y, int *n);
   qeh_status result() const { return result_; }
   void fill_info(qeh_dav_info *info) const;
@@ -92,6 +95,7 @@ class DavRun {
   double2 *X_ = nullptr, *Lc_ = nullptr, *LcH_ = nullptr, *Y_ = nullptr;
   double *tri_ = nullptr, *Zt_ = nullptr, *escr_ = nullptr;   // own subspace solver
   bool own_ = false;
+  bool wide_ = true;   // own solver's steps over many workgroups
   double2 *U_ = nullptr, *SP_ = nullptr;   // S V and S P (overlap S != 1)
   bool gen_ = false;                       // generalized problem H psi = eps S psi
   qeh_ctx *c64_ = nullptr;   // mixed form: FP64 context of the refinement phase

@@ -450,6 +450,162 @@ __device__ void householder(double2 *col, int m, double2 *vs, double *red, doubl
   *beta_out = beta;
 }
 
+constexpr int kTU = 6;   // independent loads in flight per thread
+
+// One pass over the m x m block U (columns 1..m-1, rows 1..m-1 of the
+// trailing matrix of step k; element (i, j) at U[i + j*lda]):
+//   if upd:  U(i, j) -= v_i conj(w_j) + w_i conj(v_j)   (stored back)
+//   if vn:   part[grp * mm + (i - 1)] = sum over the thread's columns of U(i, j) vn_{j-1}
+// Rows and columns 0 (column 0 was done separately) are skipped.
+__device__ void fused_pass(double2 *U, long lda, int m, bool upd, const double2 *vs,
+                           const double2 *ws, bool mv, const double2 *vn, double2 *part) {
+  const int tid = threadIdx.x;
+  const int mm = m - 1;
+  if (mm <= 0) return;
+  const int g = kET / mm;   // >= 2 (mm <= 510)
+  if (tid >= g * mm) return;
+  const int r = tid % mm, grp = tid / mm;
+  const int i = r + 1;
+  const double2 vi = vs[i], wi = ws[i];
+  double2 acc = make_double2(0.0, 0.0);
+  int j = 1 + grp;
+  for (; j + (kTU - 1) * g < m; j += kTU * g) {
+    double2 a[kTU];
+#pragma unroll
+    for (int u = 0; u < kTU; ++u) a[u] = U[i + (long)(j + u * g) * lda];
+#pragma unroll
+    for (int u = 0; u < kTU; ++u) {
+      const int jj = j + u * g;
+      if (upd) {
+        a[u] = csub(a[u], cadd(cmulc(vi, ws[jj]), cmulc(wi, vs[jj])));
+        U[i + (long)jj * lda] = a[u];
+      }
+      if (mv) acc = cadd(acc, cmul(a[u], vn[jj - 1]));
+    }
+  }
+  for (; j < m; j += g) {
+    double2 a = U[i + (long)j * lda];
+    if (upd) {
+      a = csub(a, cadd(cmulc(vi, ws[j]), cmulc(wi, vs[j])));
+      U[i + (long)j * lda] = a;
+    }
+    if (mv) acc = cadd(acc, cmul(a, vn[j - 1]));
+  }
+  if (mv) part[grp * mm + r] = acc;
+}
+
+// The whole reduction on one workgroup, the trailing matrix streamed from
+// memory once per step (rank-2 update of step k fused with the product of
+// step k+1): little device time in total, for solves that share the device.
+__global__ __launch_bounds__(kET) void tridiag_kernel(double2 *A, long lda, int n, double *d,
+                                                      double *e, double2 *tau,
+                                                      const int *info_chol) {
+  if (*info_chol != 0) return;
+  __shared__ double2 vbuf[2][kEMaxN];   // v_k and v_{k+1}
+  __shared__ double2 ps[kEMaxN];        // A22 v_k, then p, then w
+  __shared__ double2 part[kET];
+  __shared__ double red[kEW];
+  const int tid = threadIdx.x;
+  if (n == 1) {
+    if (tid == 0) d[0] = A[0].x;
+    return;
+  }
+  // step 0's reflector and its product A22 v_0 (a plain pass: no update)
+  double2 t;
+  double beta;
+  householder(A + 1, n - 1, vbuf[0], red, &t, &beta);
+  if (tid == 0) {
+    d[0] = A[0].x;
+    e[0] = beta;
+    tau[0] = t;
+  }
+  __syncthreads();
+  {
+    // the pass skips row / column 0 of its block: hand it the whole A22 by
+    // starting one row and column earlier (A11 corner of A)
+    const int m = n - 1;
+    // rows 0..m-1 of A22 times v: do row 0 and column 0 here too
+    const double2 *a22 = A + lda + 1;
+    const int g = kET / m;
+    if (tid < g * m) {
+      const int i = tid % m, grp = tid / m;
+      double2 acc = make_double2(0.0, 0.0);
+      int jj = grp;
+      for (; jj + (kTU - 1) * g < m; jj += kTU * g) {
+        double2 a[kTU];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) a[u] = a22[i + (long)(jj + u * g) * lda];
+#pragma unroll
+        for (int u = 0; u < kTU; ++u) acc = cadd(acc, cmul(a[u], vbuf[0][jj + u * g]));
+      }
+      for (; jj < m; jj += g) acc = cadd(acc, cmul(a22[i + (long)jj * lda], vbuf[0][jj]));
+      part[tid] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kET) {
+      double2 acc = part[i];
+      for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * m + i]);
+      ps[i] = acc;
+    }
+    __syncthreads();
+  }
+  int cur = 0;
+  for (int k = 0; k + 1 < n; ++k) {
+    const int m = n - k - 1;   // order of A22 of step k
+    double2 *u = A + (long)(k + 1) * lda + (k + 1);   // A22 of step k, (0, 0) corner
+    const double2 *vs = vbuf[cur];
+    const bool refl = t.x != 0.0 || t.y != 0.0;
+    if (refl) {
+      // p = t A22 v, alpha2 = -1/2 t (p^H v), w = p + alpha2 v (in ps)
+      double dr = 0.0, di = 0.0;
+      for (int i = tid; i < m; i += kET) {
+        const double2 p = cmul(t, ps[i]), v = vs[i];
+        dr += p.x * v.x + p.y * v.y;
+        di += p.x * v.y - p.y * v.x;
+      }
+      dr = block_sum(dr, red);
+      di = block_sum(di, red);
+      const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
+      for (int i = tid; i < m; i += kET) ps[i] = cadd(cmul(t, ps[i]), cmul(a2, vs[i]));
+      __syncthreads();
+      // column 0 of A22 (column k+1 of A), rows 0..m-1
+      for (int i = tid; i < m; i += kET)
+        u[i] = csub(u[i], cadd(cmulc(vs[i], ps[0]), cmulc(ps[i], vs[0])));
+      __syncthreads();
+    }
+    if (m == 1) {
+      if (tid == 0) d[k + 1] = u[0].x;
+      break;
+    }
+    // reflector of step k+1 from column k+1 below the diagonal
+    double2 t1;
+    double beta1;
+    householder(u + 1, m - 1, vbuf[cur ^ 1], red, &t1, &beta1);
+    if (tid == 0) {
+      d[k + 1] = u[0].x;
+      e[k + 1] = beta1;
+      tau[k + 1] = t1;
+    }
+    __syncthreads();
+    const bool refl1 = t1.x != 0.0 || t1.y != 0.0;
+    // rest of step k's update fused with step k+1's product (rows / columns
+    // 1..m-1 of this A22 are A22 of step k+1)
+    fused_pass(u, lda, m, refl, vs, ps, refl1, vbuf[cur ^ 1], part);
+    __syncthreads();
+    if (refl1) {
+      const int mm = m - 1, g = kET / mm;
+      for (int i = tid; i < mm; i += kET) {
+        double2 acc = part[i];
+        for (int q = 1; q < g; ++q) acc = cadd(acc, part[q * mm + i]);
+        ps[i] = acc;
+      }
+    }
+    __syncthreads();
+    t = t1;
+    cur ^= 1;
+  }
+}
+
 // The last orders of the reduction (m <= kTailN, the whole problem when it
 // is that small): one workgroup with the trailing block in LDS, so nothing
 // leaves LDS between steps.  Step k: reflector of column k, p = t A22 v
@@ -1230,9 +1386,10 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
 
 size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN + kEMaxN + 8; }
 
-hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, hipStream_t s) {
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, bool wide,
+                       hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
-  if (n <= kCholOneWG) {
+  if (!wide || n <= kCholOneWG) {
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kET), 0, s, S, ld, n, info);
     return hipGetLastError();
   }
@@ -1260,10 +1417,14 @@ hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double
 }
 
 hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
-                          const int *info_chol, hipStream_t s) {
+                          const int *info_chol, bool wide, hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
   double *d = tri, *e = tri + n;
   double2 *tau = reinterpret_cast<double2 *>(tri + 2 * n);
+  if (!wide && n > kTailN) {
+    hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A, lda, n, d, e, tau, info_chol);
+    return hipGetLastError();
+  }
   const int k0 = n > kTailN ? n - kTailN : 0;   // steps taken by the step kernel
   if (k0 > 0) {
     double2 *w = reinterpret_cast<double2 *>(scr);
@@ -1279,10 +1440,10 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
 }
 
 hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z, int ldz,
-                         double *scr, int *info, const int *info_chol, hipStream_t s) {
+                         double *scr, int *info, const int *info_chol, bool wide, hipStream_t s) {
   if (n < 1 || n > kEMaxN || nb < 1 || nb > n || ldz < n) return hipErrorInvalidValue;
   // eigenvalues on about 64 lanes per wanted one, then the vectors
-  const int g = max(1, min(32, (nb * 64 + kET - 1) / kET));
+  const int g = wide ? max(1, min(32, (nb * 64 + kET - 1) / kET)) : 1;
   hipLaunchKernelGGL(trieig_kernel<0>, dim3(g), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
                      info_chol);
   hipLaunchKernelGGL(trieig_kernel<1>, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,

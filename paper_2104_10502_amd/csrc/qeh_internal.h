@@ -305,9 +305,14 @@ hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldp
 // ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
 // Reduced problems up to kEigMaxN; column-major double2 matrices.
 constexpr int kEigMaxN = 512;
+// The solver's launchers take `wide`: true spreads each step over many
+// workgroups (shortest time for one solve alone on the device), false keeps
+// the Cholesky, the Householder reduction and the bisection on one workgroup
+// each (least device time, for solves that share the device with others).
 // S = L L^H in place (lower); info = 0 or the failing column + 1.  scr: 64 n
 // doubles of scratch (the eigenpair scratch below is large enough and free).
-hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, hipStream_t s);
+hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, bool wide,
+                       hipStream_t s);
 // X = L^-1 B (mode 0, T = L lower), X = L^-1 M^H with B = M (mode 1), or
 // X = U^-1 B (mode 2, T = U upper, backward); ncol columns, one wave each.
 hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double2 *B, long ldb,
@@ -316,12 +321,12 @@ hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double
 // scr: 12 n doubles of scratch (the multi-workgroup steps' vectors); the
 // eigenpair scratch below is large enough and free at this point.
 hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
-                          const int *info_chol, hipStream_t s);
+                          const int *info_chol, bool wide, hipStream_t s);
 // nb lowest eigenpairs of T: w[nb] ascending, Z (real, n x nb, ldz); scr holds
 // eig_scratch_doubles(n) doubles; info 0 / nonzero on failure.
 size_t eig_scratch_doubles(int n);
 hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z, int ldz,
-                         double *scr, int *info, const int *info_chol, hipStream_t s);
+                         double *scr, int *info, const int *info_chol, bool wide, hipStream_t s);
 // Zc = Q Zt (n x nb) through the reflectors stored in A by launch_tridiag.
 hipError_t launch_backtr(const double2 *A, long lda, int n, const double *tri, const double *Zt,
                          int ldz, int nb, double2 *Zc, long ldc, const int *info_chol,

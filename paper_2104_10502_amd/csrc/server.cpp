@@ -235,6 +235,8 @@ bool start_job(qeh_server *s, Job *j) {
   }
   j->eig.assign(j->req->nb, 0.0);
   j->run.reset(new DavRun());
+  // served jobs share the device: the subspace solver's least-device-time form
+  j->run->set_narrow_solver();
   rc = j->run->init(j->ctx, j->req->nb, psi, j->hc.cell.npw, j->eig.data(), &j->opts,
                     after + j->psi_bytes, j->dav_bytes);
   if (rc != QEH_OK) {
