@@ -125,15 +125,21 @@ def plane_bytes(shape, prec, nb):
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c5_gamma_hbm_traffic.json")
 
 
+# sources of the H|psi> kernels whose HBM counters are stored (the FFT
+# passes, the projector GEMMs and D scaling, the Gamma unpack) and the headers
+# they include
+HPSI_SOURCES = ("cplx.h", "dav_kernels.hip", "fft_kernels.hip", "fft_reg.h", "gemm_kernels.hip",
+                "qeh_internal.h")
+
+
 def kernel_source_hash():
-    """Hash of the HIP sources; a stored counter measurement is used only while
-    the kernels are unchanged."""
+    """Hash of the H|psi> kernel sources; a stored counter measurement is used
+    only while those kernels are unchanged."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2104_10502_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in HPSI_SOURCES:
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -1,5 +1,5 @@
 // Dense Hermitian solver of the Davidson Rayleigh-Ritz step, written for the
-// small reduced problems of block Davidson (n <= 512): the paper solves this
+// small reduced problems of block Davidson (n <= 1024): the paper solves this
 // small generalized eigenproblem with a dense GPU solver (section "Evolution
 // of the GPU-enabled version").  H y = eps S y for the lowest nb
 // pairs, in deterministic kernels (fixed summation orders, no atomics on
@@ -49,8 +49,9 @@ namespace {
 
 constexpr int kET = 1024;            // threads of the one-workgroup kernels
 constexpr int kEW = kET / 64;        // their waves
-constexpr int kEMaxN = kEigMaxN;     // largest problem (rows held 8 per lane)
-constexpr int kSlots = kEMaxN / 64;  // register slots per lane in the column kernels
+constexpr int kEMaxN = kEigMaxN;     // largest problem
+constexpr int kSlots = kEMaxN / 64;  // register slots per lane at the largest order
+constexpr int kCholMaxN = 512;       // largest order of the one-workgroup Cholesky (LDS panel)
 constexpr double kEps = 2.220446049250313e-16;
 constexpr double kTiny = 2.2250738585072014e-308;
 constexpr double kDegRel = 1e-12;    // numerically equal eigenvalues (relative to ||T||)
@@ -101,7 +102,7 @@ constexpr int kCB = 16;
 constexpr int kCBP = kCB + 1;   // padded LDS row stride (bank spread)
 
 __global__ __launch_bounds__(kET) void chol_kernel(double2 *S, long ld, int n, int *info) {
-  __shared__ double2 P[kEMaxN * kCBP];
+  __shared__ double2 P[kCholMaxN * kCBP];
   const int tid = threadIdx.x;
   for (int jb = 0; jb < n; jb += kCB) {
     const int b = min(kCB, n - jb), m = n - jb;
@@ -273,7 +274,7 @@ __global__ __launch_bounds__(256) void cholp_kernel(double2 *S, long ld, int n, 
 }
 
 // ---------------------------------------------------------------- triangular solves
-// One wave per right-hand side column j; the column's n <= 512 entries sit in
+// One wave per right-hand side column j; the column's n <= 64 NS entries sit in
 // registers (row s * 64 + lane in slot s).
 //   MODE 0: L x = b,   L lower (T), b = B(:, j)
 //   MODE 1: L x = b,   b = conj(M(j, :)) with M = B (column j of M^H)
@@ -297,8 +298,8 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 // One block round: solve block (= slot) B, then the far side.  B is a
 // template argument so that every slot index is a compile-time constant and
 // x stays in registers.
-template <int MODE, int B>
-__device__ __forceinline__ void trsm_round(double2 (&x)[kSlots], const double2 *__restrict__ T,
+template <int MODE, int B, int NS>
+__device__ __forceinline__ void trsm_round(double2 (&x)[NS], const double2 *__restrict__ T,
                                            long ldt, int n, int lane, double2 (*Tb)[64],
                                            double *rd) {
   const int nbk = (n + 63) / 64;
@@ -328,7 +329,7 @@ __device__ __forceinline__ void trsm_round(double2 (&x)[kSlots], const double2 *
   }
   // the far side: x_s -= T(rows of s, columns of B) x_B
 #pragma unroll
-  for (int s2 = 0; s2 < kSlots; ++s2) {
+  for (int s2 = 0; s2 < NS; ++s2) {
     const bool far = MODE == 2 ? s2 < B : s2 > B;
     const int i = s2 * 64 + lane;
     if (far && s2 < nbk) {
@@ -352,19 +353,30 @@ __device__ __forceinline__ void trsm_round(double2 (&x)[kSlots], const double2 *
   }
 }
 
-template <int MODE>
+// All block rounds, in solve order (forward for MODE 0 / 1, backward for 2).
+template <int MODE, int NS, int Q>
+__device__ __forceinline__ void trsm_rounds(double2 (&x)[NS], const double2 *__restrict__ T,
+                                            long ldt, int n, int lane, double2 (*Tb)[64],
+                                            double *rd) {
+  if constexpr (Q < NS) {
+    trsm_round<MODE, MODE == 2 ? NS - 1 - Q : Q, NS>(x, T, ldt, n, lane, Tb, rd);
+    trsm_rounds<MODE, NS, Q + 1>(x, T, ldt, n, lane, Tb, rd);
+  }
+}
+
+// NS register slots per lane (orders up to 64 NS).
+template <int MODE, int NS>
 __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T, long ldt, int n,
                                                    const double2 *__restrict__ B, long ldb,
                                                    int ncol, double2 *__restrict__ X, long ldx) {
-  static_assert(kSlots == 8, "block rounds below are written for 8 slots");
   __shared__ double2 Tb[64][64];   // diagonal block, column-major: Tb[c][r] = T(b0 + r, b0 + c)
   __shared__ double rd[64];        // reciprocals of its diagonal
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool live = j < ncol;   // every wave stays for the barriers
-  double2 x[kSlots];
+  double2 x[NS];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int i = s * 64 + lane;
     double2 v = make_double2(0.0, 0.0);
     if (live && i < n) {
@@ -377,28 +389,10 @@ __global__ __launch_bounds__(256) void trsm_kernel(const double2 *__restrict__ T
     }
     x[s] = v;
   }
-  if (MODE != 2) {
-    trsm_round<MODE, 0>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 1>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 2>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 3>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 4>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 5>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 6>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 7>(x, T, ldt, n, lane, Tb, rd);
-  } else {
-    trsm_round<MODE, 7>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 6>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 5>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 4>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 3>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 2>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 1>(x, T, ldt, n, lane, Tb, rd);
-    trsm_round<MODE, 0>(x, T, ldt, n, lane, Tb, rd);
-  }
+  trsm_rounds<MODE, NS, 0>(x, T, ldt, n, lane, Tb, rd);
   if (!live) return;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int i = s * 64 + lane;
     if (i < n) X[i + (long)j * ldx] = x[s];
   }
@@ -462,7 +456,7 @@ __device__ void fused_pass(double2 *U, long lda, int m, bool upd, const double2 
   const int tid = threadIdx.x;
   const int mm = m - 1;
   if (mm <= 0) return;
-  const int g = kET / mm;   // >= 2 (mm <= 510)
+  const int g = kET / mm;   // >= 1 (mm < kEMaxN)
   if (tid >= g * mm) return;
   const int r = tid % mm, grp = tid / mm;
   const int i = r + 1;
@@ -638,14 +632,15 @@ constexpr int kLT = 256;
 constexpr int kSW = 4;         // waves (columns) per workgroup of the step kernel
 constexpr int kTailN = 64;     // order left to the one-workgroup kernel
 
+template <int NS>   // register slots per lane: orders up to 64 NS
 __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, int n, int k,
                                                           int last, double *d, double *e,
                                                           double2 *tau, double2 *scr,
                                                           const int *info_chol) {
   if (*info_chol != 0) return;
-  __shared__ double2 vs[kEMaxN];   // v of step k
-  __shared__ double2 ws[kEMaxN];   // y of step k, then w
-  __shared__ double2 cs[kEMaxN];   // column k+1 (rows k+1..), then v' in cs[1..]
+  __shared__ double2 vs[NS * 64];   // v of step k
+  __shared__ double2 ws[NS * 64];   // y of step k, then w
+  __shared__ double2 cs[NS * 64];   // column k+1 (rows k+1..), then v' in cs[1..]
   __shared__ double red[kSW];
   const int tid = threadIdx.x, lane = tid & 63;
   const int r0 = k + 1;            // first row / column of A22
@@ -655,9 +650,9 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
   const bool own = col < m;
   double2 *acol = A + (long)(r0 + col) * lda + r0;
   // the owned column first: its loads overlap the small vectors'
-  double2 a[kSlots];
+  double2 a[NS];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int i = s * 64 + lane;
     a[s] = own && i < m ? acol[i] : make_double2(0.0, 0.0);
   }
@@ -700,7 +695,7 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
     if (refl) {
       const double2 vj = vs[col], wj = ws[col];
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const int i = s * 64 + lane;
         if (i < m) {
           a[s] = csub(a[s], cadd(cmulc(vs[i], wj), cmulc(ws[i], vj)));
@@ -711,7 +706,7 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
     if (!last && col >= 1) {
       double dr = 0.0, di = 0.0;   // conj(column) . v'
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const int i = s * 64 + lane;
         if (i >= 1 && i < m) {
           const double2 v = cs[i];
@@ -725,7 +720,7 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
       if (col == 1) {
         double2 *cn = cb + (long)((r0 + 1) & 1) * n;
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
+        for (int s = 0; s < NS; ++s) {
           const int i = s * 64 + lane;
           if (i >= 1 && i < m) cn[i - 1] = a[s];
         }
@@ -944,7 +939,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   if (*info_chol != 0) return;
   if (PH == 1 && *info != 0) return;
   if (PH == 0 && blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
-  double *tlam_g = scr + 7L * n * kEMaxN;   // task eigenvalues, then the cut
+  double *tlam_g = scr + 7L * n * n;   // task eigenvalues, then the cut
   double *xcut_g = tlam_g + kEMaxN;
   __shared__ double sd[kEMaxN], se[kEMaxN], se2[kEMaxN];
   __shared__ int bst[kEMaxN + 1];    // block starts
@@ -1156,10 +1151,10 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   }
   __syncthreads();
   const long ls = n;   // per-task scratch stride
-  constexpr long kTS = kEMaxN;          // row stride of the pivot arrays
+  const long kTS = ls;                  // row stride of the pivot arrays (tasks <= n)
   double *twp = scr;                    // [n][task] D+ (top-down pivots)
-  double *twm = scr + ls * kEMaxN;      // [n][task] D- (bottom-up pivots)
-  double *lu = scr + 2 * ls * kEMaxN;   // [task][5 n] pivoted LU (group leaders)
+  double *twm = scr + ls * ls;          // [n][task] D- (bottom-up pivots)
+  double *lu = scr + 2 * ls * ls;       // [task][5 n] pivoted LU (group leaders)
   const double dtiny = kEps * tnorm;
   auto in_group = [&](int t) {   // selected task t is in a degenerate group of >= 2
     return gdeg[t] != t || (t + 1 < bof[tblk[t] + 1] && tpos[t + 1] < nb && gdeg[t + 1] == t);
@@ -1304,26 +1299,27 @@ constexpr int kTK = 8;   // reflectors staged per chunk
 // Zc(:, j) = Q Zt(:, j) = H_0 (H_1 ( ... H_{n-2} Zt(:, j))), one wave per
 // column; the four waves of a workgroup share the reflectors, staged through
 // LDS kTK at a time with the next chunk's loads in flight.
+template <int NS>   // register slots per lane: orders up to 64 NS
 __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__ A, long lda, int n,
                                                      const double *__restrict__ tri,
                                                      const double *__restrict__ Zt, int ldz,
                                                      int nb, double2 *__restrict__ Zc, long ldc,
                                                      const int *info_chol, const int *info_eig) {
   if (*info_chol != 0 || *info_eig != 0) return;
-  __shared__ double2 Vs[kTK][kEMaxN];
+  __shared__ double2 Vs[kTK][NS * 64];
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool live = j < nb;   // every wave stays for the barriers
   const double2 *tau = reinterpret_cast<const double2 *>(tri + 2 * n);
-  double2 z[kSlots];
+  double2 z[NS];
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int i = s * 64 + lane;
     z[s] = make_double2(live && i < n ? Zt[i + (long)j * ldz] : 0.0, 0.0);
   }
   // reflectors k = kl .. kh (rows > kl) in descending chunks, the next
   // chunk's loads in flight during the current one's reflectors
-  constexpr int NPF = kTK * kEMaxN / 256;
+  constexpr int NPF = kTK * NS * 64 / 256;
   double2 pf[NPF];
   auto fetch = [&](int kh) {
     const int kl = max(0, kh - kTK + 1), rows = n - (kl + 1);
@@ -1356,7 +1352,7 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
       const double2 *v = Vs[k - kl];
       double dr = 0.0, di = 0.0;   // v^H z
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const int i = s * 64 + lane;
         if (i > k && i < n) {
           const double2 vi = v[i];
@@ -1368,7 +1364,7 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
       di = wave_sum(di);
       const double2 c = cmul(t, make_double2(dr, di));
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const int i = s * 64 + lane;
         if (i > k && i < n) z[s] = csub(z[s], cmul(c, v[i]));
       }
@@ -1376,7 +1372,7 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
   }
   if (!live) return;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int i = s * 64 + lane;
     if (i < n) Zc[i + (long)j * ldc] = z[s];
   }
@@ -1384,12 +1380,12 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
 
 }  // namespace
 
-size_t eig_scratch_doubles(int n) { return (size_t)7 * n * kEMaxN + kEMaxN + 8; }
+size_t eig_scratch_doubles(int n) { return (size_t)7 * n * n + kEMaxN + 8; }
 
 hipError_t launch_chol(double2 *S, long ld, int n, int *info, double *scr, bool wide,
                        hipStream_t s) {
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
-  if (!wide || n <= kCholOneWG) {
+  if ((!wide || n <= kCholOneWG) && n <= kCholMaxN) {
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(kET), 0, s, S, ld, n, info);
     return hipGetLastError();
   }
@@ -1407,12 +1403,18 @@ hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double
                        int ncol, double2 *X, long ldx, hipStream_t s) {
   if (n < 1 || n > kEMaxN || ncol < 1) return hipErrorInvalidValue;
   const dim3 grid((ncol + 3) / 4);
-  if (mode == 0)
-    hipLaunchKernelGGL(trsm_kernel<0>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
-  else if (mode == 1)
-    hipLaunchKernelGGL(trsm_kernel<1>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
-  else
-    hipLaunchKernelGGL(trsm_kernel<2>, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, T, ldt, n, B, ldb, ncol, X, ldx);
+  };
+  if (n <= 512) {
+    if (mode == 0) go(trsm_kernel<0, 8>);
+    else if (mode == 1) go(trsm_kernel<1, 8>);
+    else go(trsm_kernel<2, 8>);
+  } else {
+    if (mode == 0) go(trsm_kernel<0, kSlots>);
+    else if (mode == 1) go(trsm_kernel<1, kSlots>);
+    else go(trsm_kernel<2, kSlots>);
+  }
   return hipGetLastError();
 }
 
@@ -1430,8 +1432,12 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
     double2 *w = reinterpret_cast<double2 *>(scr);
     for (int k = -1; k < k0; ++k) {
       const int m = n - k - 1;
-      hipLaunchKernelGGL(tdstep_kernel, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s, A, lda,
-                         n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
+      if (n <= 512)
+        hipLaunchKernelGGL(tdstep_kernel<8>, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s, A,
+                           lda, n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
+      else
+        hipLaunchKernelGGL(tdstep_kernel<kSlots>, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s,
+                           A, lda, n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
     }
   }
   hipLaunchKernelGGL(tridiag_lds_kernel, dim3(1), dim3(kLT), 0, s, A + k0 + (long)k0 * lda, lda,
@@ -1455,8 +1461,12 @@ hipError_t launch_backtr(const double2 *A, long lda, int n, const double *tri, c
                          int ldz, int nb, double2 *Zc, long ldc, const int *info_chol,
                          const int *info_eig, hipStream_t s) {
   if (n < 1 || n > kEMaxN || nb < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(backtr_kernel, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri, Zt, ldz,
-                     nb, Zc, ldc, info_chol, info_eig);
+  if (n <= 512)
+    hipLaunchKernelGGL(backtr_kernel<8>, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri, Zt,
+                       ldz, nb, Zc, ldc, info_chol, info_eig);
+  else
+    hipLaunchKernelGGL(backtr_kernel<kSlots>, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri,
+                       Zt, ldz, nb, Zc, ldc, info_chol, info_eig);
   return hipGetLastError();
 }
 

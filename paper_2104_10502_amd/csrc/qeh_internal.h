@@ -304,7 +304,7 @@ hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldp
 
 // ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
 // Reduced problems up to kEigMaxN; column-major double2 matrices.
-constexpr int kEigMaxN = 512;
+constexpr int kEigMaxN = 1024;
 // The solver's launchers take `wide`: true spreads each step over many
 // workgroups (shortest time for one solve alone on the device), false keeps
 // the Cholesky, the Householder reduction and the bisection on one workgroup
