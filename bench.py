@@ -325,7 +325,9 @@ def davidson_leg(q, torch, name, with_cg=True):
         del p
         torch.cuda.empty_cache()
     res["npw_stored"], res["bands"], res["gamma"] = cell.npw, nb, name != "c2"
-    res["subspace_solver"] = "own HIP kernels" if name == "c2" else "rocSOLVER (basis > 512)"
+    basis = nvecx or 2 * nb
+    res["subspace_solver"] = ("own HIP kernels (wide form), basis <= %d" % basis if basis <= 1024
+                              else "rocSOLVER (basis <= %d > 1024)" % basis)
     if name == "c2" and with_cg:
         res["cg_fp64_1e-8"] = cg_leg(q, torch, cell, psi0, gold)
     return res
