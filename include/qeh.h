@@ -251,7 +251,7 @@ qeh_status qeh_beta_generate_static(const qeh_cell *cell, int precision, void *b
  * rtol = residual 2-norm threshold (Ry), maxiter = iterations (0 = 200),
  * subspace = solver of the reduced problem H_r y = eps S_r y:
  *   QEH_SUBSPACE_AUTO (0): the library's own when nvecx <= 1024, else rocSOLVER;
- *   QEH_SUBSPACE_OWN (1): the library's own HIP solver (nvecx <= 1024 only):
+ *   QEH_SUBSPACE_OWN (1): the library's own HIP solver (nvecx <= 2048 only):
  *     Cholesky, triangular solves, Householder tridiagonalisation, bisection
  *     and inverse iteration, back-transformation; deterministic (fixed
  *     summation orders), no library calls; about a dozen launches per
@@ -326,7 +326,7 @@ qeh_status qeh_davidson(qeh_ctx *ctx, int nb, double *psi_inout, int ldpsi,
  * exact line minimisation over the current vector and the direction; a final
  * Rayleigh-Ritz of the block.  Band b stops when ||H x - lam x|| <= thr
  * (thr = rtol, or max(rtol, 1e-5) for QEH_MIXED) or after maxiter
- * iterations (QEH_ERR_NOT_CONVERGED, results written).  1 <= nb <= 1024 (the
+ * iterations (QEH_ERR_NOT_CONVERGED, results written).  1 <= nb <= 2048 (the
  * block steps use the library's subspace solver).  H is applied one band at a
  * time, so the solver is latency-bound; Davidson is the throughput path.
  * On return psi_inout holds orthonormal Ritz vectors and eig (HOST, nb
@@ -388,7 +388,7 @@ qeh_status qeh_dav_rci_destroy(qeh_dav_rci *rci, qeh_dav_info *info);
 /* The dense solver of the Rayleigh-Ritz step on its own (the generalized
  * Hermitian eigenproblem the paper solves with a dense GPU solver, section
  * "Evolution of the GPU-enabled version"): the nb lowest eigenpairs of
- * H y = eps S y, S positive definite, 1 <= nb <= n <= 1024.  H, S: DEVICE
+ * H y = eps S y, S positive definite, 1 <= nb <= n <= 2048.  H, S: DEVICE
  * complex n x n column-major with leading dimension ld >= n (Hermitian; only
  * (X + X^H) / 2 is used).  eig: DEVICE, nb doubles, ascending.  Y: DEVICE
  * complex n x nb column-major (ldy >= n), S-orthonormal eigenvectors

@@ -259,7 +259,7 @@ QEH_SUBSPACE_AUTO, QEH_SUBSPACE_OWN, QEH_SUBSPACE_ROCSOLVER = 0, 1, 2
 
 def subspace_eigh(h, s, nb, stream=None):
     """qeh_subspace_eigh: the nb lowest eigenpairs of h y = eps s y for n x n
-    complex128 CUDA tensors (Hermitian h, positive definite s, n <= 1024);
+    complex128 CUDA tensors (Hermitian h, positive definite s, n <= 2048);
     returns (eig float64 CUDA tensor (nb,), Y complex128 CUDA tensor (n, nb)),
     Y column j the eigenvector of eig[j]."""
     torch = _torch()

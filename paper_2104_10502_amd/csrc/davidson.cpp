@@ -270,7 +270,7 @@ qeh_status dav_check_opts(const qeh_ctx *c, int nb, const qeh_dav_opts *o, int *
     set_error("the own subspace solver takes nvecx <= " + std::to_string(kEigMaxN));
     return QEH_ERR_INVALID;
   }
-  *own = sub == QEH_SUBSPACE_OWN || (sub == QEH_SUBSPACE_AUTO && *nvecx <= kEigMaxN);
+  *own = sub == QEH_SUBSPACE_OWN || (sub == QEH_SUBSPACE_AUTO && *nvecx <= kEigAutoMaxN);
   if (o && o->refine) {
     const qeh_ctx *r = o->refine;
     if (c->prec != QEH_MIXED || r->prec != QEH_FP64) {

@@ -1,5 +1,5 @@
 // Dense Hermitian solver of the Davidson Rayleigh-Ritz step, written for the
-// small reduced problems of block Davidson (n <= 1024): the paper solves this
+// small reduced problems of block Davidson (n <= 2048): the paper solves this
 // small generalized eigenproblem with a dense GPU solver (section "Evolution
 // of the GPU-enabled version").  H y = eps S y for the lowest nb
 // pairs, in deterministic kernels (fixed summation orders, no atomics on
@@ -947,8 +947,10 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   __shared__ double tlam[kEMaxN];    // task eigenvalue
   __shared__ int tblk[kEMaxN], tpos[kEMaxN];   // task block, sorted position
   __shared__ int gdeg[kEMaxN], gclo[kEMaxN];   // first task of the task's degenerate / close group
-  __shared__ double key[kET];
-  __shared__ int kid[kET];
+  constexpr int kSK = 2 * kET;       // sort keys (tasks <= kEMaxN <= kSK)
+  static_assert(kEMaxN <= kSK, "one sort pass holds every task");
+  __shared__ double key[kSK];
+  __shared__ int kid[kSK];
   __shared__ double red[kEW];
   __shared__ int sh_i[4];            // nblk, ntask, first qualifying multisection point
   __shared__ double sh_d[2];         // multisection bracket
@@ -1074,7 +1076,9 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     int G = 64;
     while (G > 1 && G * ntask > gthreads) G >>= 1;
     const int gt = blockIdx.x * kET + tid;
-    const int task = gt / G, sub = gt % G;
+    // (more tasks than lanes, one lane each: rounds of gthreads tasks)
+    for (int tb = 0; tb < ntask; tb += gthreads / G) {
+    const int task = tb + gt / G, sub = gt % G;
     const bool real_task = task < ntask;
     const int b = real_task ? tblk[task] : 0;
     const int s = bst[b], t = bst[b + 1], loc = real_task ? task - bof[b] : 0;
@@ -1109,46 +1113,56 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
       }
     }
     if (real_task && sub == 0) tlam_g[task] = 0.5 * (a + c);
+    }
     return;
   }
   for (int i = tid; i < ntask; i += kET) tlam[i] = tlam_g[i];
   __syncthreads();
-  // sort (value, task) pairs by value, task index breaking ties (bitonic, 1024 keys)
-  key[tid] = tid < ntask ? tlam[tid] : INFINITY;
-  kid[tid] = tid;
-  if (tid < kEMaxN) tpos[tid] = nb;   // not selected unless sorted below nb
+  // sort (value, task) pairs by value, task index breaking ties (bitonic over
+  // KS keys, a power of two >= ntask)
+  const int KS = ntask <= kET ? kET : kSK;
+  for (int e = tid; e < KS; e += kET) {
+    key[e] = e < ntask ? tlam[e] : INFINITY;
+    kid[e] = e;
+  }
+  for (int e = tid; e < kEMaxN; e += kET) tpos[e] = nb;   // not selected unless sorted below nb
   __syncthreads();
-  for (int size = 2; size <= kET; size <<= 1) {
+  for (int size = 2; size <= KS; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const int p = tid ^ stride;
-      if (p > tid) {
-        const bool up = (tid & size) == 0;
-        const double ka = key[tid], kb = key[p];
-        const int ia = kid[tid], ib = kid[p];
-        const bool gt = ka > kb || (ka == kb && ia > ib);
-        if (gt == up) {
-          key[tid] = kb;
-          key[p] = ka;
-          kid[tid] = ib;
-          kid[p] = ia;
+      for (int e = tid; e < KS; e += kET) {
+        const int p = e ^ stride;
+        if (p > e) {
+          const bool up = (e & size) == 0;
+          const double ka = key[e], kb = key[p];
+          const int ia = kid[e], ib = kid[p];
+          const bool gt = ka > kb || (ka == kb && ia > ib);
+          if (gt == up) {
+            key[e] = kb;
+            key[p] = ka;
+            kid[e] = ib;
+            kid[p] = ia;
+          }
         }
       }
       __syncthreads();
     }
   }
-  if (tid < ntask && kid[tid] < ntask) tpos[kid[tid]] = tid;
+  for (int e = tid; e < ntask; e += kET)
+    if (kid[e] < ntask) tpos[kid[e]] = e;
   __syncthreads();
   // groups within a block among the selected tasks (tasks of one block are
   // consecutive and ascending)
-  if (tid < ntask && tpos[tid] < nb) {
-    int g = tid;
-    while (g > bof[tblk[tid]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kDegRel * tnorm) --g;
-    gdeg[tid] = g;
-    g = tid;
-    while (g > bof[tblk[tid]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kCloseRel * tnorm)
-      --g;
-    gclo[tid] = g;
-  }
+  for (int task = tid; task < ntask; task += kET)
+    if (tpos[task] < nb) {
+      int g = task;
+      while (g > bof[tblk[task]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kDegRel * tnorm)
+        --g;
+      gdeg[task] = g;
+      g = task;
+      while (g > bof[tblk[task]] && tpos[g - 1] < nb && tlam[g] - tlam[g - 1] <= kCloseRel * tnorm)
+        --g;
+      gclo[task] = g;
+    }
   __syncthreads();
   const long ls = n;   // per-task scratch stride
   const long kTS = ls;                  // row stride of the pivot arrays (tasks <= n)
@@ -1160,14 +1174,15 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     return gdeg[t] != t || (t + 1 < bof[tblk[t] + 1] && tpos[t + 1] < nb && gdeg[t + 1] == t);
   };
   // pass 1: twisted vectors (singletons); LU of the degenerate groups (leaders)
-  if (tid < ntask && tpos[tid] < nb) {
-    const int b = tblk[tid], s = bst[b], t = bst[b + 1], m = t - s;
-    double *z = Z + (long)tpos[tid] * ldz;
-    const double lam = tlam[tid];
-    if (in_group(tid))
+  for (int task = tid; task < ntask; task += kET) {
+    if (tpos[task] >= nb) continue;
+    const int b = tblk[task], s = bst[b], t = bst[b + 1], m = t - s;
+    double *z = Z + (long)tpos[task] * ldz;
+    const double lam = tlam[task];
+    if (in_group(task))
       for (int i = 0; i < n; ++i)
         if (i < s || i >= t) z[i] = 0.0;
-    if (!in_group(tid)) {
+    if (!in_group(task)) {
       if (m == 1) {
         for (int i = 0; i < n; ++i) z[i] = i == s ? 1.0 : 0.0;
       } else {
@@ -1175,7 +1190,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
         // wave touch consecutive addresses at each step
         // (the top-down and bottom-up recurrences interleaved: two
         // independent chains)
-        double *dp = twp + tid, *dm = twm + tid;
+        double *dp = twp + task, *dm = twm + task;
         double qp = sd[s] - lam, qm = sd[t - 1] - lam;
         dp[0] = qp;
         dm[(m - 1) * kTS] = qm;
@@ -1221,9 +1236,9 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
           z[i] = v * inv;
         }
       }
-    } else if (gdeg[tid] == tid) {
+    } else if (gdeg[task] == task) {
       // pivoted LU of T_b - lam I (LAPACK gttrf order)
-      double *dl = lu + (long)tid * 5 * ls, *dd = dl + ls, *du = dd + ls, *du2 = du + ls,
+      double *dl = lu + (long)task * 5 * ls, *dd = dl + ls, *du = dd + ls, *du2 = du + ls,
              *pv = du2 + ls;
       for (int i = 0; i < m; ++i) dd[i] = sd[s + i] - lam;
       for (int i = 0; i + 1 < m; ++i) {
@@ -1257,14 +1272,15 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   // passes 2-5: two sweeps of inverse iteration for the degenerate groups,
   // each followed by Gram-Schmidt within the group (one wave per group)
   for (int sweep = 0; sweep < 2; ++sweep) {
-    if (tid < ntask && tpos[tid] < nb && in_group(tid)) {
-      const int b = tblk[tid], s = bst[b], t = bst[b + 1], m = t - s;
-      const int ld0 = gdeg[tid];
+    for (int task = tid; task < ntask; task += kET) {
+      if (tpos[task] >= nb || !in_group(task)) continue;
+      const int b = tblk[task], s = bst[b], t = bst[b + 1], m = t - s;
+      const int ld0 = gdeg[task];
       const double *dl = lu + (long)ld0 * 5 * ls, *dd = dl + ls, *du = dd + ls, *du2 = du + ls,
                    *pv = du2 + ls;
-      double *z = Z + (long)tpos[tid] * ldz + s;
+      double *z = Z + (long)tpos[task] * ldz + s;
       if (sweep == 0)
-        for (int i = 0; i < m; ++i) z[i] = start_entry(i, tid - ld0);
+        for (int i = 0; i < m; ++i) z[i] = start_entry(i, task - ld0);
       lu_solve(dl, dd, du, du2, pv, m, dtiny, z);
       double nn = 0.0;
       for (int i = 0; i < m; ++i) nn += z[i] * z[i];
@@ -1288,7 +1304,8 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     while (t0 + cnt < bof[tblk[t0] + 1] && tpos[t0 + cnt] < nb && gclo[t0 + cnt] == t0) ++cnt;
     if (cnt > 1) wave_mgs(Z, ldz, tpos, t0, cnt, bst[tblk[t0]], bst[tblk[t0] + 1]);
   }
-  if (tid < ntask && tpos[tid] < nb) w[tpos[tid]] = tlam[tid];
+  for (int task = tid; task < ntask; task += kET)
+    if (tpos[task] < nb) w[tpos[task]] = tlam[task];
   (void)lane;
   if (tid == 0) *info = 0;
 }
@@ -1306,7 +1323,8 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
                                                      int nb, double2 *__restrict__ Zc, long ldc,
                                                      const int *info_chol, const int *info_eig) {
   if (*info_chol != 0 || *info_eig != 0) return;
-  __shared__ double2 Vs[kTK][NS * 64];
+  constexpr int TK = NS <= 16 ? kTK : 2;   // reflectors per chunk (LDS, registers)
+  __shared__ double2 Vs[TK][NS * 64];
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
   const bool live = j < nb;   // every wave stays for the barriers
@@ -1319,10 +1337,10 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
   }
   // reflectors k = kl .. kh (rows > kl) in descending chunks, the next
   // chunk's loads in flight during the current one's reflectors
-  constexpr int NPF = kTK * NS * 64 / 256;
+  constexpr int NPF = TK * NS * 64 / 256;
   double2 pf[NPF];
   auto fetch = [&](int kh) {
-    const int kl = max(0, kh - kTK + 1), rows = n - (kl + 1);
+    const int kl = max(0, kh - TK + 1), rows = n - (kl + 1);
 #pragma unroll
     for (int u = 0; u < NPF; ++u) {
       const int idx = threadIdx.x + u * 256;
@@ -1332,8 +1350,8 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
   };
   const int top = n - 2;
   if (top >= 0) fetch(top);
-  for (int kh = top; kh >= 0; kh -= kTK) {
-    const int kl = max(0, kh - kTK + 1);
+  for (int kh = top; kh >= 0; kh -= TK) {
+    const int kl = max(0, kh - TK + 1);
     __syncthreads();
     {
       const int rows = n - (kl + 1);
@@ -1345,7 +1363,7 @@ __global__ __launch_bounds__(256) void backtr_kernel(const double2 *__restrict__
       }
     }
     __syncthreads();
-    if (kh - kTK >= 0) fetch(kh - kTK);
+    if (kh - TK >= 0) fetch(kh - TK);
     for (int k = kh; k >= kl; --k) {
       const double2 t = tau[k];
       if (t.x == 0.0 && t.y == 0.0) continue;
@@ -1410,10 +1428,14 @@ hipError_t launch_trsm(int mode, const double2 *T, long ldt, int n, const double
     if (mode == 0) go(trsm_kernel<0, 8>);
     else if (mode == 1) go(trsm_kernel<1, 8>);
     else go(trsm_kernel<2, 8>);
+  } else if (n <= 1024) {
+    if (mode == 0) go(trsm_kernel<0, 16>);
+    else if (mode == 1) go(trsm_kernel<1, 16>);
+    else go(trsm_kernel<2, 16>);
   } else {
-    if (mode == 0) go(trsm_kernel<0, kSlots>);
-    else if (mode == 1) go(trsm_kernel<1, kSlots>);
-    else go(trsm_kernel<2, kSlots>);
+    if (mode == 0) go(trsm_kernel<0, 32>);
+    else if (mode == 1) go(trsm_kernel<1, 32>);
+    else go(trsm_kernel<2, 32>);
   }
   return hipGetLastError();
 }
@@ -1423,7 +1445,7 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
   if (n < 1 || n > kEMaxN) return hipErrorInvalidValue;
   double *d = tri, *e = tri + n;
   double2 *tau = reinterpret_cast<double2 *>(tri + 2 * n);
-  if (!wide && n > kTailN) {
+  if (!wide && n > kTailN && n <= kET) {   // (its row x column-group layout needs n <= kET)
     hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(kET), 0, s, A, lda, n, d, e, tau, info_chol);
     return hipGetLastError();
   }
@@ -1432,12 +1454,17 @@ hipError_t launch_tridiag(double2 *A, long lda, int n, double *tri, double *scr,
     double2 *w = reinterpret_cast<double2 *>(scr);
     for (int k = -1; k < k0; ++k) {
       const int m = n - k - 1;
+      const dim3 grid((m + kSW - 1) / kSW), blk(64 * kSW);
+      const int last = k == k0 - 1 ? 1 : 0;
       if (n <= 512)
-        hipLaunchKernelGGL(tdstep_kernel<8>, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s, A,
-                           lda, n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
+        hipLaunchKernelGGL(tdstep_kernel<8>, grid, blk, 0, s, A, lda, n, k, last, d, e, tau, w,
+                           info_chol);
+      else if (n <= 1024)
+        hipLaunchKernelGGL(tdstep_kernel<16>, grid, blk, 0, s, A, lda, n, k, last, d, e, tau, w,
+                           info_chol);
       else
-        hipLaunchKernelGGL(tdstep_kernel<kSlots>, dim3((m + kSW - 1) / kSW), dim3(64 * kSW), 0, s,
-                           A, lda, n, k, k == k0 - 1 ? 1 : 0, d, e, tau, w, info_chol);
+        hipLaunchKernelGGL(tdstep_kernel<32>, grid, blk, 0, s, A, lda, n, k, last, d, e, tau, w,
+                           info_chol);
     }
   }
   hipLaunchKernelGGL(tridiag_lds_kernel, dim3(1), dim3(kLT), 0, s, A + k0 + (long)k0 * lda, lda,
@@ -1461,12 +1488,16 @@ hipError_t launch_backtr(const double2 *A, long lda, int n, const double *tri, c
                          int ldz, int nb, double2 *Zc, long ldc, const int *info_chol,
                          const int *info_eig, hipStream_t s) {
   if (n < 1 || n > kEMaxN || nb < 1) return hipErrorInvalidValue;
+  const dim3 grid((nb + 3) / 4);
   if (n <= 512)
-    hipLaunchKernelGGL(backtr_kernel<8>, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri, Zt,
-                       ldz, nb, Zc, ldc, info_chol, info_eig);
+    hipLaunchKernelGGL(backtr_kernel<8>, grid, dim3(256), 0, s, A, lda, n, tri, Zt, ldz, nb, Zc,
+                       ldc, info_chol, info_eig);
+  else if (n <= 1024)
+    hipLaunchKernelGGL(backtr_kernel<16>, grid, dim3(256), 0, s, A, lda, n, tri, Zt, ldz, nb, Zc,
+                       ldc, info_chol, info_eig);
   else
-    hipLaunchKernelGGL(backtr_kernel<kSlots>, dim3((nb + 3) / 4), dim3(256), 0, s, A, lda, n, tri,
-                       Zt, ldz, nb, Zc, ldc, info_chol, info_eig);
+    hipLaunchKernelGGL(backtr_kernel<32>, grid, dim3(256), 0, s, A, lda, n, tri, Zt, ldz, nb, Zc,
+                       ldc, info_chol, info_eig);
   return hipGetLastError();
 }
 

@@ -304,7 +304,13 @@ hipError_t launch_dscale(const qeh_ctx *c, int nbk, const double2 *psi, long ldp
 
 // ---- dense Hermitian subspace solver (eigh_kernels.hip) --------------------
 // Reduced problems up to kEigMaxN; column-major double2 matrices.
-constexpr int kEigMaxN = 1024;
+constexpr int kEigMaxN = 2048;
+// Largest basis for which the Davidson's automatic choice takes the own solver:
+// above it the one-stage Householder reduction streams the trailing matrix
+// from HBM at every step (n = 2048: 86 ms per complex solve) and rocSOLVER's
+// real solver of the Gamma path measured faster (512-atom cell: 12.8 against
+// 13.6 s per Davidson run).
+constexpr int kEigAutoMaxN = 1024;
 // The solver's launchers take `wide`: true spreads each step over many
 // workgroups (shortest time for one solve alone on the device), false keeps
 // the Cholesky, the Householder reduction and the bisection on one workgroup

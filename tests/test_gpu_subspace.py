@@ -63,7 +63,7 @@ def _check(h, s, nb, tol=1e-12, label=""):
 
 
 @pytest.mark.parametrize("n,nb", [(1, 1), (2, 1), (17, 9), (64, 32), (200, 100), (256, 256),
-                                  (512, 256), (700, 350), (1024, 512)])
+                                  (512, 256), (700, 350), (1024, 512), (2048, 1024)])
 def test_random_pencil(n, nb):
     rng = np.random.default_rng(n)
     _check(_herm(rng, n), _spd(rng, n), nb, label="random")
@@ -150,7 +150,7 @@ def test_error_returns():
     with pytest.raises(q.QehError) as ei:
         _solve(h2, np.eye(200), 8)
     assert ei.value.status == q.QEH_ERR_NUMERIC
-    big = torch.zeros((1025, 1025), dtype=torch.complex128, device="cuda")
+    big = torch.zeros((2049, 2049), dtype=torch.complex128, device="cuda")
     with pytest.raises(q.QehError) as ei:
         q.subspace_eigh(big, big, 4)
     assert ei.value.status == q.QEH_ERR_INVALID

@@ -81,7 +81,7 @@ CHILD = textwrap.dedent(r'''
     pgb = dict(pg); pgb["tab"] = pg["tab"][:, :5].copy()
     assert plan(sv, "short table", beta=None, projgen=pgb) != 0
     assert plan(c1, "block 0", block=0) != 0
-    for nn, nb in ((1, 1), (1024, 512), (1025, 1), (4, 5), (0, 0)):
+    for nn, nb in ((1, 1), (2048, 1024), (2049, 1), (4, 5), (0, 0)):
         lib.qeh_subspace_plan(nn, nb, ctypes.byref(n))
     print("ok", len(seen))
 ''')
