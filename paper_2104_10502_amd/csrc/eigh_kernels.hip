@@ -65,6 +65,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Sum over the workgroup (NW waves), identical in every thread and from run
 // to run.
+// Two sums at once (red holds 2 NW doubles): the same orders as two calls of
+// block_sum, one pair of barriers.
+template <int NW> __device__ double2 block_sum2(double a, double b, double *red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = a;
+    red[NW + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < NW; ++i) sa += red[i];
+  for (int i = 0; i < NW; ++i) sb += red[NW + i];
+  return make_double2(sa, sb);
+}
+
 template <int NW = kEW> __device__ double block_sum(double v, double *red) {
   v = wave_sum(v);
   __syncthreads();
@@ -641,7 +658,7 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
   __shared__ double2 vs[NS * 64];   // v of step k
   __shared__ double2 ws[NS * 64];   // y of step k, then w
   __shared__ double2 cs[NS * 64];   // column k+1 (rows k+1..), then v' in cs[1..]
-  __shared__ double red[kSW];
+  __shared__ double red[2 * kSW];
   const int tid = threadIdx.x, lane = tid & 63;
   const int r0 = k + 1;            // first row / column of A22
   const int m = n - r0;            // its order
@@ -668,21 +685,24 @@ __global__ __launch_bounds__(64 * kSW) void tdstep_kernel(double2 *A, long lda, 
   }
   __syncthreads();
   if (refl) {
-    // p = t y, alpha = -1/2 t (p^H v), w = p + alpha v
+    // p = t y, alpha = -1/2 t (p^H v), w = p + alpha v; then column k+1
+    // less v w0^* + w v0^*.  Every thread forms w0 itself from y0 and v0,
+    // read before the sum's barriers (thread 0 overwrites ws[0] with w0 below).
+    const double2 y0 = ws[0], v0 = vs[0];
     double dr = 0.0, di = 0.0;
     for (int i = tid; i < m; i += 64 * kSW) {
       const double2 p = cmul(t, ws[i]), v = vs[i];
       dr += p.x * v.x + p.y * v.y;
       di += p.x * v.y - p.y * v.x;
     }
-    dr = block_sum<kSW>(dr, red);
-    di = block_sum<kSW>(di, red);
-    const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
-    for (int i = tid; i < m; i += 64 * kSW) ws[i] = cadd(cmul(t, ws[i]), cmul(a2, vs[i]));
-    __syncthreads();
-    const double2 v0 = vs[0], w0 = ws[0];
-    for (int i = tid; i < m; i += 64 * kSW)
-      cs[i] = csub(cs[i], cadd(cmulc(vs[i], w0), cmulc(ws[i], v0)));
+    const double2 pv = block_sum2<kSW>(dr, di, red);
+    const double2 a2 = cscale(cmul(t, pv), -0.5);
+    const double2 w0 = cadd(cmul(t, y0), cmul(a2, v0));
+    for (int i = tid; i < m; i += 64 * kSW) {
+      const double2 wi = cadd(cmul(t, ws[i]), cmul(a2, vs[i]));
+      ws[i] = wi;
+      cs[i] = csub(cs[i], cadd(cmulc(vs[i], w0), cmulc(wi, v0)));
+    }
     __syncthreads();
   }
   double2 t1 = make_double2(0.0, 0.0);
@@ -749,7 +769,7 @@ __global__ __launch_bounds__(kLT) void tridiag_lds_kernel(double2 *A, long lda, 
   __shared__ double2 Al[kTailN][kTailN + 1];   // [column][row]
   __shared__ double2 vs[kTailN], ws[kTailN];
   __shared__ double2 part[G][kTailN];
-  __shared__ double red[kLT / 64];
+  __shared__ double red[2 * (kLT / 64)];
   const int tid = threadIdx.x;
   for (int idx = tid; idx < m * m; idx += kLT) {
     const int r = idx % m, c = idx / m;
@@ -787,9 +807,7 @@ __global__ __launch_bounds__(kLT) void tridiag_lds_kernel(double2 *A, long lda, 
       dr = p.x * v.x + p.y * v.y;
       di = p.x * v.y - p.y * v.x;
     }
-    dr = block_sum<kLT / 64>(dr, red);
-    di = block_sum<kLT / 64>(di, red);
-    const double2 a2 = cscale(cmul(t, make_double2(dr, di)), -0.5);
+    const double2 a2 = cscale(cmul(t, block_sum2<kLT / 64>(dr, di, red)), -0.5);
     if (tid < mm) ws[tid] = cadd(ws[tid], cmul(a2, vs[tid]));
     __syncthreads();
     for (int idx = tid; idx < mm * mm; idx += kLT) {
