@@ -950,7 +950,7 @@ __device__ void wave_mgs(double *Z, int ldz, const int *zc, int g0, int cnt, int
 // same arithmetic in each, and bisects its share of the tasks), leaving the
 // cut and the task eigenvalues in scr; PH = 1 (one workgroup) takes them and
 // sorts, groups and forms the eigenvectors.
-template <int PH>
+template <int PH, int KM>   // KM: largest order this instance takes (array sizes)
 __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, int nb, double *w,
                                                      double *Z, int ldz, double *scr, int *info,
                                                      const int *info_chol) {
@@ -958,15 +958,15 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   if (PH == 1 && *info != 0) return;
   if (PH == 0 && blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
   double *tlam_g = scr + 7L * n * n;   // task eigenvalues, then the cut
-  double *xcut_g = tlam_g + kEMaxN;
-  __shared__ double sd[kEMaxN], se[kEMaxN], se2[kEMaxN];
-  __shared__ int bst[kEMaxN + 1];    // block starts
-  __shared__ int bof[kEMaxN + 1];    // first task of each block
-  __shared__ double tlam[kEMaxN];    // task eigenvalue
-  __shared__ int tblk[kEMaxN], tpos[kEMaxN];   // task block, sorted position
-  __shared__ int gdeg[kEMaxN], gclo[kEMaxN];   // first task of the task's degenerate / close group
-  constexpr int kSK = 2 * kET;       // sort keys (tasks <= kEMaxN <= kSK)
-  static_assert(kEMaxN <= kSK, "one sort pass holds every task");
+  double *xcut_g = tlam_g + KM;
+  __shared__ double sd[KM], se[KM], se2[KM];
+  __shared__ int bst[KM + 1];    // block starts
+  __shared__ int bof[KM + 1];    // first task of each block
+  __shared__ double tlam[KM];    // task eigenvalue
+  __shared__ int tblk[KM], tpos[KM];   // task block, sorted position
+  __shared__ int gdeg[KM], gclo[KM];   // first task of the task's degenerate / close group
+  constexpr int kSK = KM > kET ? KM : kET;   // sort keys (tasks <= KM <= kSK)
+  static_assert(KM <= 2 * kET, "the sort handles at most two keys per thread");
   __shared__ double key[kSK];
   __shared__ int kid[kSK];
   __shared__ double red[kEW];
@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
   }
   __syncthreads();
   const int ntask = sh_i[1];
-  if (ntask < nb || ntask > kEMaxN) {
+  if (ntask < nb || ntask > KM) {
     if (PH == 0 && blockIdx.x == 0 && tid == 0) *info = 2;
     return;
   }
@@ -1143,7 +1143,7 @@ __global__ __launch_bounds__(kET) void trieig_kernel(const double *tri, int n, i
     key[e] = e < ntask ? tlam[e] : INFINITY;
     kid[e] = e;
   }
-  for (int e = tid; e < kEMaxN; e += kET) tpos[e] = nb;   // not selected unless sorted below nb
+  for (int e = tid; e < KM; e += kET) tpos[e] = nb;   // not selected unless sorted below nb
   __syncthreads();
   for (int size = 2; size <= KS; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -1495,10 +1495,15 @@ hipError_t launch_trieig(const double *tri, int n, int nb, double *w, double *Z,
   if (n < 1 || n > kEMaxN || nb < 1 || nb > n || ldz < n) return hipErrorInvalidValue;
   // eigenvalues on about 64 lanes per wanted one, then the vectors
   const int g = wide ? max(1, min(32, (nb * 64 + kET - 1) / kET)) : 1;
-  hipLaunchKernelGGL(trieig_kernel<0>, dim3(g), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
-                     info_chol);
-  hipLaunchKernelGGL(trieig_kernel<1>, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info,
-                     info_chol);
+  // (instances sized for the order: the 2 048-task arrays measured 20% slower
+  // on orders <= 512)
+  auto go = [&](auto k0, auto k1) {
+    hipLaunchKernelGGL(k0, dim3(g), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info, info_chol);
+    hipLaunchKernelGGL(k1, dim3(1), dim3(kET), 0, s, tri, n, nb, w, Z, ldz, scr, info, info_chol);
+  };
+  if (n <= 512) go(trieig_kernel<0, 512>, trieig_kernel<1, 512>);
+  else if (n <= 1024) go(trieig_kernel<0, 1024>, trieig_kernel<1, 1024>);
+  else go(trieig_kernel<0, kEMaxN>, trieig_kernel<1, kEMaxN>);
   return hipGetLastError();
 }
 
